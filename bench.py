@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the FastSimilarityGraph hot path on one MI355X.
+
+One step = the whole hot path over one synthetic point set already resident
+in HBM: prep (FP64 operand fragments and norms), every binned KDE pass and
+tree descent, the leaf stage, degrees, reweighting and the symmetric CSR
+(Algorithms 1 and 2).  Default workload: 100,000 points in R^32 from a seeded
+10-component Gaussian mixture, sigma 2, L 17.
+
+Prints one JSON line: value = sampled edges/s (n*L sampled edges per step /
+step time), plus kernel evaluations/s, p50/p99 step latency, a live roofline
+figure for the dominant kernel (the binned KDE over all points, timed with
+HIP events on the stream it runs on) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "kernel evals/s + sampled edges/s, BF16-split vs FP32 plain; p50/p99 latency"
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+
+
+def kde_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kde.hip", "device.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_2310_13870_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str):
+    """HBM bytes per launch of the root KDE from the committed counter summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"kde_root_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kde_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, w, target_s: float):
+    import oracle
+    import workloads
+    n, L = w.n, w.L
+    rows = workloads.subsample(n, 8, 4242)
+    t0 = time.perf_counter()
+    oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=False)
+    t1 = time.perf_counter() - t0
+    m = int(min(n, max(8, round(8 * target_s / max(t1, 1e-6)))))
+    rows = workloads.subsample(n, m, 4243)
+    t0 = time.perf_counter()
+    oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=False)
+    dt = time.perf_counter() - t0
+    return {
+        "value": m * L / dt,
+        "unit": "sampled edges/s",
+        "kernel_evals_per_s": m * (n - 1) / dt,
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "seconds": dt,
+        "sample": f"{m} seeded rows of the {n}-point workload: per row the full FP64 kernel row "
+                  f"({n - 1} evaluations), the degree and L={L} descents; reweighting/CSR (O(nL)) not included",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mix32-n100k")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how the path would shard over query points).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2310_13870_amd as fsg
+    import workloads
+
+    w = workloads.WORKLOADS[args.workload]()
+    X = w.points()
+    n, d, L = w.n, w.d, w.L
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    ctx = fsg.Context(0)
+
+    def step():
+        pts = fsg.Points(ctx, Xd)
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, L, w.philox_seed)
+        row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, L, nbr, deg)
+        pts.close()
+        return col.numel()
+
+    for _ in range(args.warmup):
+        nnz = step()
+    torch.cuda.synchronize()
+    ctx.reset_profiling()
+    ctx.set_profiling(True)
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        nnz = step()
+        times.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ctx.set_profiling(False)
+    stages = {}
+    for name in ("prep", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
+        ms, cnt = ctx.stage_time(name)
+        if cnt:
+            stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
+    ms_per_step = 1e3 * total / args.steps
+    edges_per_s = n * L / (total / args.steps)
+    # kernel evaluations per step: the root pass evaluates n(n-1) pairs; later
+    # passes and the leaf stage evaluate (samples x node size) pairs
+    import paper_2310_13870_amd  # noqa: F401
+    depth_leaf = 0
+    while math.ceil(n / 2 ** depth_leaf) > 64:
+        depth_leaf += 1
+    evals = n * (n - 1) + n * L * n / 2 ** depth_leaf if depth_leaf > 0 else n * L * n
+    kde = stages.get("kde_root")
+    roofline = None
+    if kde:
+        flops = 2.0 * d * n * (n - 1)
+        achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
+        traffic = traffic_from_profile(args.workload)
+        roofline = {"bound": "mfma", "kernel": "kde_bins_kernel (binned KDE over all points)",
+                    "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                    "ms_per_launch": kde["ms_per_launch"],
+                    "algorithmic_flops_per_launch": flops}
+    times_ms = np.array(times) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": edges_per_s,
+        "unit": "sampled edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "d": d, "L": L, "sigma": w.sigma, "gamma": w.gamma,
+                   "components": w.n_comp, "precision": "fp32 points, fp64 matrix-core cross term, fp64 exp"},
+        "kernel_evals_per_s": evals / (total / args.steps),
+        "p50_ms": float(np.percentile(times_ms, 50)),
+        "p99_ms": float(np.percentile(times_ms, 99)),
+        "distinct_edges": nnz // 2,
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * fsg.h -- C ABI of libfsg.so: the data-parallel hot path of
+ * FastSimilarityGraph (Macgregor & Sun, "A Fast Similarity Graph Construction
+ * via Kernel Density Estimation", NeurIPS 2023) on AMD Instinct MI355X (gfx950).
+ *
+ * The library builds a sparse approximation of the fully connected Gaussian
+ * similarity graph of n points (Section 2.3) without forming the n x n kernel
+ * matrix: every point draws L neighbours j with probability k(x_i,x_j)/deg(x_i)
+ * by a randomised descent of an index-order binary partition tree whose branch
+ * probabilities are kernel density estimates over the tree nodes (Algorithm 1,
+ * Section 4.1, Lemma 1), and the sampled edges are reweighted into a
+ * symmetric CSR graph (Algorithm 2).  The KDE is exact (brute force): the
+ * cross term x.y runs on the FP64 matrix cores, the squared distance is formed
+ * by the norm expansion in FP64, and exp is evaluated in FP64.
+ *
+ * Conventions shared by every call:
+ *  - Points are FP32, row-major n x d, in device memory owned by the caller.
+ *  - Kernel k(x,y) = exp(-gamma ||x-y||^2); gamma > 0 (gamma = 1/sigma^2 in the
+ *    paper's notation, 1/(2 sigma^2) in the usual statistics convention).
+ *  - No self loops: the term j == i is left out of every degree and node mass.
+ *  - Tree: node [a,b) splits at mid = a + floor((b-a)/2) (Section 4.1: the first
+ *    half holds floor(|X|/2) points); the root is [0,n) at level 0.
+ *  - Uniforms: Philox4x64-10 (Salmon et al., SC 2011) with key (seed, 0) and
+ *    counter (i, l, floor(level/4), 0); the uniform of sample l of point i at
+ *    level `level` is (word[level mod 4] >> 11) * 2^-53.  A sample at node
+ *    [a,b) with masses mL, mR of its halves goes left iff u*(mL+mR) < mL
+ *    (Algorithm 1's test r <= g_X1/(g_X1+g_X2)), and never enters a child of
+ *    zero mass.
+ *  - Ownership: every *_dev pointer is device memory owned by the caller; a
+ *    points handle borrows X_dev (which must outlive it) and owns the arrays
+ *    derived from it; a context owns its workspace.
+ *  - Ordering: every call is enqueued on the context's stream, in call order.
+ *    Outputs are valid once that stream is synchronised.  Only fsg_build_csr
+ *    (which returns nnz to the host) synchronises the stream itself.
+ *  - Errors: calls return a status and never throw.  Argument checks are done
+ *    on the host before anything is enqueued (FSG_E_INVALID); HIP failures are
+ *    returned as FSG_E_DEVICE (asynchronous faults surface at a later call or at
+ *    fsg_ctx_sync).  On any error the outputs are unspecified.  fsg_last_error
+ *    gives a message for the last failing call on a context.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef FSG_H
+#define FSG_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSG_OK = 0,
+    FSG_E_INVALID = -1,     /* bad argument (checked on the host) */
+    FSG_E_NOMEM = -2,       /* device allocation failed */
+    FSG_E_DEVICE = -3,      /* a HIP call failed */
+    FSG_E_UNSUPPORTED = -4, /* valid request outside what this build supports */
+    FSG_E_BUDGET = -5       /* the request needs more workspace than the budget allows */
+} fsg_status;
+
+typedef enum {
+    FSG_FP32 = 0 /* FP32 points; FP64 matrix-core cross term, FP64 distances, FP64 exp */
+} fsg_precision;
+
+typedef struct fsg_ctx fsg_ctx;
+typedef struct fsg_points fsg_points;
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  ws_budget_bytes caps the workspace the context may
+ * allocate (0 = a default of 32 GiB). */
+fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes, fsg_ctx** out);
+void fsg_ctx_destroy(fsg_ctx* ctx);
+/* Static string naming a status code. */
+const char* fsg_status_string(fsg_status s);
+/* Message for the last failing call on ctx ("" if none); valid until the next call. */
+const char* fsg_last_error(const fsg_ctx* ctx);
+/* Synchronise the context's stream and report any device error. */
+fsg_status fsg_ctx_sync(fsg_ctx* ctx);
+/* Device workspace currently held by the context, in bytes. */
+uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
+
+/* Stage timing.  When enabled, the context records a pair of HIP events on
+ * its stream around every stage it launches; fsg_ctx_stage_time synchronises
+ * the stream and returns the summed elapsed time (ms) and the number of
+ * launches of one stage since the last reset.  Stages: "prep", "kde_root"
+ * (the binned KDE over all points), "kde_pass" (binned KDE of later passes),
+ * "descend" (descent over bins), "group" (sample sort by node), "leaf"
+ * (leaf stage), "csr" (reweighting and CSR).  Unknown names report 0. */
+fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled);
+fsg_status fsg_ctx_stage_time(fsg_ctx* ctx, const char* stage, double* ms, int64_t* launches);
+fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);
+
+/* Make a point set resident: X_dev is FP32 row-major n x d (borrowed).  Derives
+ * the FP64 matrix-core operand layout and the squared norms (hot-path step
+ * "prep").  1 <= n <= 2^31-1, 1 <= d <= 1024. */
+fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_t d, fsg_precision prec,
+                             fsg_points** out);
+void fsg_points_destroy(fsg_points* pts);
+/* Device bytes owned by the handle (for HBM admission). */
+uint64_t fsg_points_bytes(const fsg_points* pts);
+
+/* Degrees: deg_dev[i] = sum_{j != i} exp(-gamma ||x_i - x_j||^2), FP64 [n].
+ * This is the KDE g_[1,n](x_i) of Algorithm 2 (eq. (1) of Section 2.4) without
+ * the self term. */
+fsg_status fsg_degrees(fsg_ctx* ctx, const fsg_points* X, double gamma, double* deg_dev);
+
+/* Segmented KDE (eq. (1) of Section 2.4 over index ranges; the two KDEs of
+ * Algorithm 1).  Segment s pairs the query entries e in [q_ptr[s], q_ptr[s+1])
+ * -- query point Q[q_idx[e]] -- with the data range X[lo[s]:hi[s]) split at
+ * mid[s]:
+ *   out_left[e]  = sum_{j in [lo[s], mid[s]), j != self_idx[e]} k(Q[q_idx[e]], X[j])
+ *   out_right[e] = sum_{j in [mid[s], hi[s]), j != self_idx[e]} k(Q[q_idx[e]], X[j])
+ * All arrays are device memory: q_ptr int64 [n_seg+1] non-decreasing from 0;
+ * q_idx, self_idx int32 [q_ptr[n_seg]] (self_idx may be NULL: nothing
+ * excluded; a negative entry excludes nothing); lo, mid, hi int32 [n_seg] with
+ * 0 <= lo <= mid <= hi <= n(X); outputs FP64 [q_ptr[n_seg]].  Q and X must
+ * have the same d.  n_entries = q_ptr[n_seg] must be passed by the caller (the
+ * library does not read device memory on the host); segments may be empty,
+ * overlap, and have any size.  Out-of-range device indices are the caller's
+ * responsibility (they are not checked on the host). */
+fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma,
+                             int64_t n_seg, int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx,
+                             const int32_t* lo, const int32_t* mid, const int32_t* hi,
+                             const int32_t* self_idx, double* out_left, double* out_right);
+
+/* Algorithm 1 run L times from the root for every point (Algorithm 2's
+ * sampling loop).  nbr_dev int32 [n*L]: nbr[i*L+l] = the neighbour sampled by
+ * sample l of point i, or -1 when deg_i == 0.  deg_dev FP64 [n] (may be NULL)
+ * receives the degrees.  margin_dev FP32 [n*L] (may be NULL) receives, per
+ * sample, min over its levels of |u - mL/(mL+mR)| as computed on the device. */
+fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, uint64_t seed,
+                            int32_t* nbr_dev, double* deg_dev, float* margin_dev);
+
+/* Algorithm 2 after the sampling loop: the set E of undirected edges
+ * {i, nbr[i*L+l]} (entries -1 skipped), each weighted w = k/p_hat with
+ *   p_i = min(L k/deg_i, 1), p_j = min(L k/deg_j, 1), p_hat = p_i + p_j - p_i p_j,
+ * written as a symmetric CSR: each edge appears in both of its rows, columns
+ * ascending.  nbr_dev int32 [n*L] (entries in [-1, n), never i itself),
+ * deg_dev FP64 [n] (from fsg_degrees or fsg_sample_edges), row_ptr_dev int64
+ * [n+1], col_dev int32 [cap], w_dev FP32 [cap].  *nnz (host) receives 2|E|;
+ * FSG_E_INVALID if cap < 2|E| would be needed (cap >= 2 n L always suffices).
+ * Synchronises the stream. */
+fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, const int32_t* nbr_dev,
+                         const double* deg_dev, int64_t* row_ptr_dev, int32_t* col_dev, float* w_dev,
+                         int64_t cap, int64_t* nnz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

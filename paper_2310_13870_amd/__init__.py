@@ -1,0 +1,218 @@
+"""Python binding of libfsg.so (FastSimilarityGraph hot path on MI355X).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.
+The names follow the C ABI in include/fsg.h.  There is no fallback: if the
+library is missing, importing the binding raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsg.so")
+
+FSG_OK, FSG_E_INVALID, FSG_E_NOMEM, FSG_E_DEVICE, FSG_E_UNSUPPORTED, FSG_E_BUDGET = 0, -1, -2, -3, -4, -5
+FSG_FP32 = 0
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libfsg.so is not built ({LIB_PATH}); run paper_2310_13870_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i64, _i32, _u64, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_lib_fns = dict(
+    fsg_ctx_create=_sig("fsg_ctx_create", ctypes.c_int, ctypes.c_int, _vp, _u64, ctypes.POINTER(_vp)),
+    fsg_ctx_destroy=_sig("fsg_ctx_destroy", None, _vp),
+    fsg_status_string=_sig("fsg_status_string", ctypes.c_char_p, ctypes.c_int),
+    fsg_last_error=_sig("fsg_last_error", ctypes.c_char_p, _vp),
+    fsg_ctx_sync=_sig("fsg_ctx_sync", ctypes.c_int, _vp),
+    fsg_ctx_workspace_bytes=_sig("fsg_ctx_workspace_bytes", _u64, _vp),
+    fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
+    fsg_ctx_stage_time=_sig("fsg_ctx_stage_time", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_dbl),
+                            ctypes.POINTER(_i64)),
+    fsg_ctx_reset_profiling=_sig("fsg_ctx_reset_profiling", ctypes.c_int, _vp),
+    fsg_points_create=_sig("fsg_points_create", ctypes.c_int, _vp, _vp, _i64, _i32, ctypes.c_int,
+                           ctypes.POINTER(_vp)),
+    fsg_points_destroy=_sig("fsg_points_destroy", None, _vp),
+    fsg_points_bytes=_sig("fsg_points_bytes", _u64, _vp),
+    fsg_degrees=_sig("fsg_degrees", ctypes.c_int, _vp, _vp, _dbl, _vp),
+    fsg_kde_segmented=_sig("fsg_kde_segmented", ctypes.c_int, _vp, _vp, _vp, _dbl, _i64, _i64, _vp, _vp, _vp,
+                           _vp, _vp, _vp, _vp, _vp),
+    fsg_sample_edges=_sig("fsg_sample_edges", ctypes.c_int, _vp, _vp, _dbl, _i32, _u64, _vp, _vp, _vp),
+    fsg_build_csr=_sig("fsg_build_csr", ctypes.c_int, _vp, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
+                       ctypes.POINTER(_i64)),
+)
+EXPORTED = sorted(_lib_fns)
+
+
+class FsgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+def status_string(status: int) -> str:
+    return _lib.fsg_status_string(status).decode()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """fsg_ctx: one device and one HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None, ws_budget_bytes: int = 0):
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = _vp()
+        st = _lib.fsg_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ws_budget_bytes, ctypes.byref(h))
+        if st != FSG_OK:
+            raise FsgError(st, "fsg_ctx_create failed")
+        self._h = h
+
+    def check(self, st):
+        if st != FSG_OK:
+            raise FsgError(st, _lib.fsg_last_error(self._h).decode())
+
+    def sync(self):
+        self.check(_lib.fsg_ctx_sync(self._h))
+
+    def set_profiling(self, enabled: bool):
+        self.check(_lib.fsg_ctx_set_profiling(self._h, 1 if enabled else 0))
+
+    def reset_profiling(self):
+        self.check(_lib.fsg_ctx_reset_profiling(self._h))
+
+    def stage_time(self, stage: str):
+        """(summed ms, launches) of one stage since the last reset."""
+        ms, cnt = _dbl(0.0), _i64(0)
+        self.check(_lib.fsg_ctx_stage_time(self._h, stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.fsg_ctx_workspace_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsg_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Points:
+    """fsg_points: a resident point set.  Keeps a reference to X (borrowed by the library)."""
+
+    def __init__(self, ctx: Context, X: torch.Tensor, precision: int = FSG_FP32):
+        _dev_tensor(X, torch.float32, "X")
+        if X.dim() != 2:
+            raise ValueError("X must be n x d")
+        self.ctx, self.X = ctx, X
+        self.n, self.d = X.shape
+        h = _vp()
+        ctx.check(_lib.fsg_points_create(ctx._h, _ptr(X), self.n, self.d, precision, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def bytes(self) -> int:
+        return int(_lib.fsg_points_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsg_points_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def degrees(ctx: Context, pts: Points, gamma: float, out: torch.Tensor = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(pts.n, dtype=torch.float64, device=pts.X.device)
+    _dev_tensor(out, torch.float64, "out")
+    ctx.check(_lib.fsg_degrees(ctx._h, pts._h, gamma, _ptr(out)))
+    return out
+
+
+def kde_segmented(ctx: Context, Q: Points, X: Points, gamma: float, q_ptr, q_idx, lo, mid, hi, self_idx=None):
+    _dev_tensor(q_ptr, torch.int64, "q_ptr")
+    for name, t in (("q_idx", q_idx), ("lo", lo), ("mid", mid), ("hi", hi)):
+        _dev_tensor(t, torch.int32, name)
+    if self_idx is not None:
+        _dev_tensor(self_idx, torch.int32, "self_idx")
+    n_seg = lo.shape[0]
+    n_ent = q_idx.shape[0]
+    left = torch.empty(n_ent, dtype=torch.float64, device=Q.X.device)
+    right = torch.empty(n_ent, dtype=torch.float64, device=Q.X.device)
+    ctx.check(_lib.fsg_kde_segmented(ctx._h, Q._h, X._h, gamma, n_seg, n_ent, _ptr(q_ptr), _ptr(q_idx), _ptr(lo),
+                                     _ptr(mid), _ptr(hi), _ptr(self_idx), _ptr(left), _ptr(right)))
+    return left, right
+
+
+def sample_edges(ctx: Context, pts: Points, gamma: float, L: int, seed: int, want_deg: bool = True,
+                 want_margin: bool = False, nbr: torch.Tensor = None):
+    dev = pts.X.device
+    if nbr is None:
+        nbr = torch.empty((pts.n, L), dtype=torch.int32, device=dev)
+    deg = torch.empty(pts.n, dtype=torch.float64, device=dev) if want_deg else None
+    margin = torch.empty((pts.n, L), dtype=torch.float32, device=dev) if want_margin else None
+    ctx.check(_lib.fsg_sample_edges(ctx._h, pts._h, gamma, L, seed, _ptr(nbr), _ptr(deg), _ptr(margin)))
+    return nbr, deg, margin
+
+
+def build_csr(ctx: Context, pts: Points, gamma: float, L: int, nbr: torch.Tensor, deg: torch.Tensor, cap: int = None,
+              row_ptr=None, col=None, w=None):
+    dev = pts.X.device
+    if cap is None:
+        cap = 2 * pts.n * L
+    if row_ptr is None:
+        row_ptr = torch.empty(pts.n + 1, dtype=torch.int64, device=dev)
+    if col is None:
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    if w is None:
+        w = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    _dev_tensor(nbr, torch.int32, "nbr")
+    _dev_tensor(deg, torch.float64, "deg")
+    nnz = _i64(0)
+    ctx.check(_lib.fsg_build_csr(ctx._h, pts._h, gamma, L, _ptr(nbr), _ptr(deg), _ptr(row_ptr), _ptr(col), _ptr(w),
+                                 cap, ctypes.byref(nnz)))
+    return row_ptr, col[: nnz.value], w[: nnz.value]
+
+
+def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int):
+    """Algorithm 2 end to end: prep, sampling, degrees, reweighting and CSR."""
+    pts = Points(ctx, X)
+    nbr, deg, _ = sample_edges(ctx, pts, gamma, L, seed)
+    row_ptr, col, w = build_csr(ctx, pts, gamma, L, nbr, deg)
+    return row_ptr, col, w, nbr, deg

@@ -1,0 +1,666 @@
+// C ABI of libfsg.so: argument checks, workspace, pass planning and the
+// orchestration of the kernels on the context's stream.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace fsg {
+
+fsg_status set_error(fsg_ctx* ctx, fsg_status s, const std::string& msg) {
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+static hipEvent_t take_event(fsg_ctx* ctx) {
+    if (!ctx->free_events.empty()) {
+        hipEvent_t e = ctx->free_events.back();
+        ctx->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+StageTimer::StageTimer(fsg_ctx* c, const char* n) : ctx(c), name(n) {
+    if (!ctx->profiling) return;
+    start = take_event(ctx);
+    if (start) (void)hipEventRecord(start, ctx->stream);
+}
+
+StageTimer::~StageTimer() {
+    if (!ctx->profiling || !start) return;
+    hipEvent_t stop = take_event(ctx);
+    if (!stop) return;
+    (void)hipEventRecord(stop, ctx->stream);
+    ctx->marks.push_back({name, {start, stop}});
+}
+
+fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    auto it = ctx->bufs.find(name);
+    if (it != ctx->bufs.end() && it->second.second >= bytes) {
+        *out = it->second.first;
+        return FSG_OK;
+    }
+    size_t old = 0;
+    if (it != ctx->bufs.end()) {
+        old = it->second.second;
+        // the stream may still use the old buffer
+        FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        FSG_HIP(ctx, hipFree(it->second.first));
+        ctx->held -= old;
+        ctx->bufs.erase(it);
+    }
+    if (ctx->held + bytes > ctx->budget)
+        return set_error(ctx, FSG_E_BUDGET,
+                         std::string("workspace budget exceeded by buffer ") + name + " (" + std::to_string(bytes) +
+                             " bytes, " + std::to_string(ctx->held) + " held, budget " +
+                             std::to_string(ctx->budget) + ")");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, FSG_E_NOMEM, std::string("hipMalloc of workspace ") + name + " failed");
+    }
+    ctx->bufs[name] = {p, bytes};
+    ctx->held += bytes;
+    *out = p;
+    return FSG_OK;
+}
+
+template <typename T>
+static fsg_status ws(fsg_ctx* ctx, const char* name, size_t count, T** out) {
+    void* p = nullptr;
+    fsg_status s = ws_get(ctx, name, count * sizeof(T), &p);
+    *out = (T*)p;
+    return s;
+}
+
+static bool gamma_ok(double g) { return std::isfinite(g) && g > 0.0; }
+
+static const int32_t* level_bounds(fsg_points* pts, int level, fsg_status* st) {
+    auto it = pts->levels.find(level);
+    if (it != pts->levels.end()) {
+        *st = FSG_OK;
+        return it->second;
+    }
+    int32_t* p = nullptr;
+    const size_t count = ((size_t)1 << level) + 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(int32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *st = set_error(pts->ctx, FSG_E_NOMEM, "hipMalloc of tree level boundaries failed");
+        return nullptr;
+    }
+    e = launch_level_bounds(pts->n, level, p, pts->ctx->stream);
+    if (e != hipSuccess) {
+        hipFree(p);
+        *st = set_error(pts->ctx, FSG_E_DEVICE, std::string("level bounds: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    pts->levels[level] = p;
+    pts->bytes += count * sizeof(int32_t);
+    *st = FSG_OK;
+    return p;
+}
+
+static int floor_log2(int64_t v) {
+    int r = -1;
+    while (v > 0) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+static int bit_length(uint64_t v) {
+    int r = 0;
+    while (v) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+// The levels of the tree are resolved in passes.  A binned pass starting at
+// level `start` computes, for every entry, the masses of the 2^D nodes D
+// levels below the entry's node; the leaf stage finishes nodes of at most
+// kLeafMax points.
+struct Plan {
+    int leaf_level = 0;
+    std::vector<std::pair<int, int>> passes;  // (start level, D)
+};
+
+static Plan make_plan(int64_t n, int32_t L, uint64_t budget) {
+    Plan p;
+    int lv = 0;
+    while ((n + ((int64_t)1 << lv) - 1) >> lv > kLeafMax) ++lv;
+    p.leaf_level = lv;
+    int start = 0;
+    const uint64_t per_pass = budget / 2;
+    while (start < lv) {
+        const uint64_t rows = (start == 0) ? (uint64_t)n : (uint64_t)n * (uint64_t)L;
+        int maxD = floor_log2((int64_t)(per_pass / (rows * 8)));
+        if (maxD > 12) maxD = 12;
+        if (maxD < 1) maxD = 1;
+        int D = lv - start;
+        if (D > maxD) D = maxD;
+        p.passes.push_back({start, D});
+        start += D;
+    }
+    return p;
+}
+
+static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma) {
+    KdeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Qp = Q->Xp;
+    a.qnorm = Q->norm;
+    a.Xp = X->Xp;
+    a.xnorm = X->norm;
+    a.D4 = X->D4;
+    a.n_query = Q->n;
+    a.n_data = X->n;
+    a.s = gamma * 1.442695040888963407359924681001892137;
+    return a;
+}
+
+// Binned KDE of all n points against the nodes of tree level D (one segment).
+static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
+    fsg_status st;
+    const int32_t* bnd = level_bounds(X, D, &st);
+    if (!bnd) return st;
+    const int64_t n = X->n;
+    const int32_t nbins = 1 << D;
+    const int64_t tiles = (n + kTileQ - 1) / kTileQ;
+    const int64_t waves = (int64_t)ctx->num_cus * 8;
+    int64_t chunks = (32 * waves + tiles - 1) / tiles;
+    if (chunks > nbins) chunks = nbins;
+    if (chunks < 1) chunks = 1;
+    const int32_t bpc = (int32_t)((nbins + chunks - 1) / chunks);
+    const int64_t n_items = tiles * ((nbins + bpc - 1) / bpc);
+    WorkItem* items;
+    SegDesc* segs;
+    int32_t* n_items_dev;
+    if ((st = ws(ctx, "root_items", (size_t)n_items, &items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "root_segs", 1, &segs)) != FSG_OK) return st;
+    if ((st = ws(ctx, "root_nitems", 1, &n_items_dev)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_uniform_segs(segs, 1, 0, nbins, ctx->stream));
+    FSG_HIP(ctx, launch_regular_items(n, nbins, bpc, kTileQ, items, n_items_dev, ctx->stream));
+    KdeArgs a = kde_args(X, X, gamma);
+    a.q_idx = nullptr;
+    a.self_mode = SELF_POINT;
+    a.bounds = bnd;
+    a.segs = segs;
+    a.items = items;
+    a.n_items = n_items_dev;
+    a.out = M;
+    a.out_stride = nbins;
+    {
+        StageTimer t(ctx, "kde_root");
+        FSG_HIP(ctx, launch_kde(a, n_items, ctx->num_cus, ctx->stream));
+    }
+    return FSG_OK;
+}
+
+static SortBufs sort_bufs(fsg_ctx* ctx, int64_t n, size_t key_bytes, fsg_status* st) {
+    SortBufs b{};
+    void* p;
+    if ((*st = ws_get(ctx, "sort_keys_tmp", n * key_bytes, &p)) != FSG_OK) return b;
+    b.keys_tmp = p;
+    if ((*st = ws(ctx, "sort_vals_tmp", (size_t)n, &b.vals_tmp)) != FSG_OK) return b;
+    const int64_t h = sort_hist_elems(n);
+    if ((*st = ws(ctx, "sort_hist", (size_t)h, &b.hist)) != FSG_OK) return b;
+    if ((*st = ws(ctx, "sort_partials", (size_t)scan_partials(h) + 1, &b.partials)) != FSG_OK) return b;
+    return b;
+}
+
+// Orders the samples by their node at `level` (2^level nodes); inactive
+// samples last.  Returns sorted sample ids and node starts.
+static fsg_status group_by_node(fsg_ctx* ctx, const int32_t* node, int64_t ns, int level, int32_t** sorted,
+                                int32_t** starts) {
+    fsg_status st;
+    uint32_t* keys;
+    int32_t* vals;
+    int32_t* start;
+    const int64_t n_nodes = (int64_t)1 << level;
+    if ((st = ws(ctx, "grp_keys", (size_t)ns, &keys)) != FSG_OK) return st;
+    if ((st = ws(ctx, "grp_vals", (size_t)ns, &vals)) != FSG_OK) return st;
+    if ((st = ws(ctx, "grp_starts", (size_t)n_nodes + 1, &start)) != FSG_OK) return st;
+    SortBufs b = sort_bufs(ctx, ns, sizeof(uint32_t), &st);
+    if (st != FSG_OK) return st;
+    StageTimer t(ctx, "group");
+    FSG_HIP(ctx, launch_node_keys(node, ns, (uint32_t)n_nodes, keys, vals, ctx->stream));
+    FSG_HIP(ctx, radix_sort_u32(keys, vals, ns, bit_length((uint64_t)n_nodes), b, ctx->stream));
+    FSG_HIP(ctx, launch_node_starts(keys, ns, n_nodes, start, ctx->stream));
+    *sorted = vals;
+    *starts = start;
+    return FSG_OK;
+}
+
+}  // namespace fsg
+
+using namespace fsg;
+
+extern "C" {
+
+const char* fsg_status_string(fsg_status s) {
+    switch (s) {
+        case FSG_OK: return "FSG_OK";
+        case FSG_E_INVALID: return "FSG_E_INVALID";
+        case FSG_E_NOMEM: return "FSG_E_NOMEM";
+        case FSG_E_DEVICE: return "FSG_E_DEVICE";
+        case FSG_E_UNSUPPORTED: return "FSG_E_UNSUPPORTED";
+        case FSG_E_BUDGET: return "FSG_E_BUDGET";
+    }
+    return "FSG_UNKNOWN";
+}
+
+fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes, fsg_ctx** out) {
+    if (!out) return FSG_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        return FSG_E_DEVICE;
+    }
+    if (device < 0 || device >= count) return FSG_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return FSG_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FSG_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FSG_E_UNSUPPORTED;
+    fsg_ctx* c = new (std::nothrow) fsg_ctx();
+    if (!c) return FSG_E_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = ws_budget_bytes ? ws_budget_bytes : ((uint64_t)32 << 30);
+    c->num_cus = prop.multiProcessorCount;
+    if (hipHostMalloc((void**)&c->host_scratch, 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return FSG_E_NOMEM;
+    }
+    *out = c;
+    return FSG_OK;
+}
+
+void fsg_ctx_destroy(fsg_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (fsg_points* p : ctx->points) p->ctx = nullptr;  // they stay valid; their destroy syncs the device
+    for (auto& kv : ctx->bufs) (void)hipFree(kv.second.first);
+    for (auto& m : ctx->marks) {
+        (void)hipEventDestroy(m.second.first);
+        (void)hipEventDestroy(m.second.second);
+    }
+    for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
+    delete ctx;
+}
+
+const char* fsg_last_error(const fsg_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+fsg_status fsg_ctx_sync(fsg_ctx* ctx) {
+    if (!ctx) return FSG_E_INVALID;
+    FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    FSG_HIP(ctx, hipGetLastError());
+    return FSG_OK;
+}
+
+uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled) {
+    if (!ctx) return FSG_E_INVALID;
+    ctx->profiling = enabled != 0;
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx) {
+    if (!ctx) return FSG_E_INVALID;
+    FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& m : ctx->marks) {
+        ctx->free_events.push_back(m.second.first);
+        ctx->free_events.push_back(m.second.second);
+    }
+    ctx->marks.clear();
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_stage_time(fsg_ctx* ctx, const char* stage, double* ms, int64_t* launches) {
+    if (!ctx || !stage || !ms || !launches) return FSG_E_INVALID;
+    FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double total = 0.0;
+    int64_t count = 0;
+    for (auto& m : ctx->marks) {
+        if (m.first != stage) continue;
+        float t = 0.0f;
+        FSG_HIP(ctx, hipEventElapsedTime(&t, m.second.first, m.second.second));
+        total += t;
+        ++count;
+    }
+    *ms = total;
+    *launches = count;
+    return FSG_OK;
+}
+
+fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_t d, fsg_precision prec,
+                             fsg_points** out) {
+    if (!ctx || !out) return FSG_E_INVALID;
+    *out = nullptr;
+    if (!X_dev) return set_error(ctx, FSG_E_INVALID, "X_dev is NULL");
+    if (n < 1 || n > 2147483647LL) return set_error(ctx, FSG_E_INVALID, "n must be in [1, 2^31-1]");
+    if (d < 1 || d > 1024) return set_error(ctx, FSG_E_INVALID, "d must be in [1, 1024]");
+    if (prec != FSG_FP32) return set_error(ctx, FSG_E_INVALID, "unknown precision");
+    const int D4 = feature_steps(d);
+    if (D4 < 0) return set_error(ctx, FSG_E_UNSUPPORTED, "d > 128 is not built in this version");
+    fsg_points* p = new (std::nothrow) fsg_points();
+    if (!p) return set_error(ctx, FSG_E_NOMEM, "host allocation failed");
+    p->ctx = ctx;
+    p->X = X_dev;
+    p->n = n;
+    p->d = d;
+    p->D4 = D4;
+    p->n_pad = (n + 15) & ~(int64_t)15;
+    p->prec = prec;
+    const size_t frag = (size_t)p->n_pad * D4 * 4 * sizeof(double);
+    const size_t nrm = (size_t)p->n_pad * sizeof(double);
+    if (hipMalloc(&p->Xp, frag) != hipSuccess || hipMalloc(&p->norm, nrm) != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->Xp) hipFree(p->Xp);
+        delete p;
+        return set_error(ctx, FSG_E_NOMEM, "hipMalloc of point arrays failed");
+    }
+    p->bytes = frag + nrm;
+    hipError_t e;
+    {
+        StageTimer t(ctx, "prep");
+        e = launch_prep(X_dev, n, d, D4, p->n_pad, p->Xp, p->norm, ctx->stream);
+    if (e != hipSuccess) {
+        hipFree(p->Xp);
+        hipFree(p->norm);
+        delete p;
+        return set_error(ctx, FSG_E_DEVICE, std::string("prep: ") + hipGetErrorString(e));
+    }
+    }
+    ctx->points.insert(p);
+    *out = p;
+    return FSG_OK;
+}
+
+void fsg_points_destroy(fsg_points* p) {
+    if (!p) return;
+    if (p->ctx) {
+        (void)hipStreamSynchronize(p->ctx->stream);
+        p->ctx->points.erase(p);
+    } else {
+        (void)hipDeviceSynchronize();
+    }
+    if (p->Xp) (void)hipFree(p->Xp);
+    if (p->norm) (void)hipFree(p->norm);
+    for (auto& kv : p->levels) (void)hipFree(kv.second);
+    delete p;
+}
+
+uint64_t fsg_points_bytes(const fsg_points* p) { return p ? p->bytes : 0; }
+
+fsg_status fsg_degrees(fsg_ctx* ctx, const fsg_points* Xc, double gamma, double* deg_dev) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!Xc || !deg_dev) return set_error(ctx, FSG_E_INVALID, "NULL argument");
+    if (Xc->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    fsg_points* X = const_cast<fsg_points*>(Xc);
+    const int64_t n = X->n;
+    int D = floor_log2(n);
+    if (D > 3) D = 3;
+    double* M;
+    fsg_status st;
+    if ((st = ws(ctx, "deg_bins", (size_t)n << D, &M)) != FSG_OK) return st;
+    if ((st = root_bins(ctx, X, gamma, D, M)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_row_sums(M, n, 1 << D, deg_dev, ctx->stream));
+    return FSG_OK;
+}
+
+fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma, int64_t n_seg,
+                             int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx, const int32_t* lo,
+                             const int32_t* mid, const int32_t* hi, const int32_t* self_idx, double* out_left,
+                             double* out_right) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!Q || !X) return set_error(ctx, FSG_E_INVALID, "NULL points");
+    if (Q->ctx != ctx || X->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (Q->d != X->d) return set_error(ctx, FSG_E_INVALID, "Q and X differ in d");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    if (n_seg < 0 || n_entries < 0) return set_error(ctx, FSG_E_INVALID, "negative count");
+    if (n_seg > 2147483647LL || n_entries > 2147483647LL)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "more than 2^31-1 segments or entries");
+    if (n_seg == 0 || n_entries == 0) return FSG_OK;
+    if (!q_ptr || !q_idx || !lo || !mid || !hi || !out_left || !out_right)
+        return set_error(ctx, FSG_E_INVALID, "NULL array");
+    fsg_status st;
+    int32_t* bounds;
+    SegDesc* segs;
+    WorkItem* items;
+    int32_t* n_items;
+    int64_t* scratch;
+    double* pairs;
+    const int64_t max_items = n_entries / kTileQ + n_seg + 1;
+    if ((st = ws(ctx, "seg_bounds", (size_t)(3 * n_seg), &bounds)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_descs", (size_t)n_seg, &segs)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_items", (size_t)max_items, &items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_nitems", 1, &n_items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_scratch", (size_t)(2 * (n_seg + 1) + 1 + scan_partials(n_seg)), &scratch)) != FSG_OK)
+        return st;
+    if ((st = ws(ctx, "seg_pairs", (size_t)(2 * n_entries), &pairs)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_api_segments(lo, mid, hi, n_seg, bounds, segs, ctx->stream));
+    FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, kTileQ, scratch, items, n_items, max_items, ctx->stream));
+    KdeArgs a = kde_args(Q, X, gamma);
+    a.q_idx = q_idx;
+    a.self_idx = self_idx;
+    a.self_mode = self_idx ? SELF_ARRAY : SELF_NONE;
+    a.bounds = bounds;
+    a.segs = segs;
+    a.items = items;
+    a.n_items = n_items;
+    a.out = pairs;
+    a.out_stride = 2;
+    FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
+    FSG_HIP(ctx, launch_split_pairs(pairs, n_entries, out_left, out_right, ctx->stream));
+    return FSG_OK;
+}
+
+fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int32_t L, uint64_t seed,
+                            int32_t* nbr_dev, double* deg_dev, float* margin_dev) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!Xc || !nbr_dev) return set_error(ctx, FSG_E_INVALID, "NULL argument");
+    if (Xc->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    if (L < 1) return set_error(ctx, FSG_E_INVALID, "L must be >= 1");
+    fsg_points* X = const_cast<fsg_points*>(Xc);
+    const int64_t n = X->n;
+    const int64_t ns = n * (int64_t)L;
+    if (ns > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "n*L must be < 2^31");
+    const double s = gamma * 1.442695040888963407359924681001892137;
+    fsg_status st;
+    const Plan plan = make_plan(n, L, ctx->budget);
+
+    int32_t* node;
+    if ((st = ws(ctx, "smp_node", (size_t)ns, &node)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_init_samples(ns, node, margin_dev, ctx->stream));
+
+    for (size_t p = 0; p < plan.passes.size(); ++p) {
+        const int start = plan.passes[p].first, D = plan.passes[p].second;
+        const int32_t nbins = 1 << D;
+        DescArgs da;
+        std::memset(&da, 0, sizeof(da));
+        da.D = D;
+        da.start_level = start;
+        da.L = L;
+        da.seed = seed;
+        da.node = node;
+        da.margin = margin_dev;
+        if (p == 0) {
+            double* M;
+            if ((st = ws(ctx, "pass_masses", (size_t)n << D, &M)) != FSG_OK) return st;
+            if ((st = root_bins(ctx, X, gamma, D, M)) != FSG_OK) return st;
+            da.M = M;
+            da.n_entries = n;
+            da.entry_sample = nullptr;
+            da.deg = deg_dev;
+            StageTimer t(ctx, "descend");
+            FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
+        } else {
+            int32_t *sorted, *starts;
+            if ((st = group_by_node(ctx, node, ns, start, &sorted, &starts)) != FSG_OK) return st;
+            const int64_t n_nodes = (int64_t)1 << start;
+            const int32_t* bnd = level_bounds(X, start + D, &st);
+            if (!bnd) return st;
+            int64_t* q_ptr;
+            int32_t* q_idx;
+            SegDesc* segs;
+            WorkItem* items;
+            int32_t* n_items;
+            int64_t* scratch;
+            double* M;
+            const int64_t max_items = ns / kTileQ + n_nodes + 1;
+            if ((st = ws(ctx, "pass_qptr", (size_t)n_nodes + 1, &q_ptr)) != FSG_OK) return st;
+            if ((st = ws(ctx, "pass_qidx", (size_t)ns, &q_idx)) != FSG_OK) return st;
+            if ((st = ws(ctx, "pass_segs", (size_t)n_nodes, &segs)) != FSG_OK) return st;
+            if ((st = ws(ctx, "pass_items", (size_t)max_items, &items)) != FSG_OK) return st;
+            if ((st = ws(ctx, "pass_nitems", 1, &n_items)) != FSG_OK) return st;
+            if ((st = ws(ctx, "pass_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
+                FSG_OK)
+                return st;
+            if ((st = ws(ctx, "pass_masses", (size_t)ns << D, &M)) != FSG_OK) return st;
+            FSG_HIP(ctx, launch_node_qptr(starts, n_nodes, q_ptr, ctx->stream));
+            FSG_HIP(ctx, launch_entry_points(sorted, ns, L, q_idx, ctx->stream));
+            FSG_HIP(ctx, launch_uniform_segs(segs, n_nodes, nbins, nbins, ctx->stream));
+            FSG_HIP(ctx, launch_build_items(q_ptr, n_nodes, nbins, nbins, kTileQ, scratch, items, n_items, max_items,
+                                            ctx->stream));
+            KdeArgs a = kde_args(X, X, gamma);
+            a.q_idx = q_idx;
+            a.self_idx = q_idx;
+            a.self_mode = SELF_ARRAY;
+            a.bounds = bnd;
+            a.segs = segs;
+            a.items = items;
+            a.n_items = n_items;
+            a.out = M;
+            a.out_stride = nbins;
+            {
+                StageTimer t(ctx, "kde_pass");
+                FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
+            }
+            da.M = M;
+            da.n_entries = ns;
+            da.entry_sample = sorted;
+            da.deg = nullptr;
+            StageTimer t(ctx, "descend");
+            FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
+        }
+    }
+
+    // leaf stage
+    {
+        int32_t *sorted, *starts;
+        if ((st = group_by_node(ctx, node, ns, plan.leaf_level, &sorted, &starts)) != FSG_OK) return st;
+        const int64_t n_nodes = (int64_t)1 << plan.leaf_level;
+        const int32_t* bnd = level_bounds(X, plan.leaf_level, &st);
+        if (!bnd) return st;
+        int32_t* items;
+        int32_t* n_items;
+        int64_t* scratch;
+        const int64_t max_items = ns / 64 + n_nodes + 1;
+        if ((st = ws(ctx, "leaf_items", (size_t)(2 * max_items), &items)) != FSG_OK) return st;
+        if ((st = ws(ctx, "leaf_nitems", 1, &n_items)) != FSG_OK) return st;
+        if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
+            FSG_OK)
+            return st;
+        StageTimer t(ctx, "leaf");
+        FSG_HIP(ctx, launch_leaf_items(starts, n_nodes, scratch, items, n_items, ctx->stream));
+        LeafArgs la;
+        std::memset(&la, 0, sizeof(la));
+        la.X = X->X;
+        la.n = n;
+        la.d = X->d;
+        la.bounds = bnd;
+        la.level = plan.leaf_level;
+        la.s = s;
+        la.L = L;
+        la.seed = seed;
+        la.sorted_samples = sorted;
+        la.node_start = starts;
+        la.items = items;
+        la.n_items = n_items;
+        la.nbr = nbr_dev;
+        la.margin = margin_dev;
+        FSG_HIP(ctx, launch_leaf(la, max_items, ctx->num_cus, ctx->stream));
+        FSG_HIP(ctx, launch_finish_inactive(node, ns, nbr_dev, ctx->stream));
+    }
+    if (plan.passes.empty() && deg_dev) return fsg_degrees(ctx, X, gamma, deg_dev);
+    return FSG_OK;
+}
+
+fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, const int32_t* nbr_dev,
+                         const double* deg_dev, int64_t* row_ptr_dev, int32_t* col_dev, float* w_dev, int64_t cap,
+                         int64_t* nnz) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!X || !nbr_dev || !deg_dev || !row_ptr_dev || !nnz) return set_error(ctx, FSG_E_INVALID, "NULL argument");
+    if (X->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    if (L < 1) return set_error(ctx, FSG_E_INVALID, "L must be >= 1");
+    if (cap < 0 || (cap > 0 && (!col_dev || !w_dev))) return set_error(ctx, FSG_E_INVALID, "bad cap or outputs");
+    const int64_t n = X->n;
+    const int64_t m = 2 * n * (int64_t)L;
+    if (m > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "2*n*L must be < 2^31");
+    fsg_status st;
+    uint64_t* keys;
+    int32_t* vals;
+    int64_t* flags;
+    int64_t* pos;
+    int64_t* partials;
+    if ((st = ws(ctx, "csr_keys", (size_t)m, &keys)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_vals", (size_t)m, &vals)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_flags", (size_t)m, &flags)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_pos", (size_t)m + 1, &pos)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_partials", (size_t)scan_partials(m) + 1, &partials)) != FSG_OK) return st;
+    SortBufs b = sort_bufs(ctx, m, sizeof(uint64_t), &st);
+    if (st != FSG_OK) return st;
+    const uint64_t sentinel = (uint64_t)n * (uint64_t)n;
+    {
+    StageTimer t(ctx, "csr");
+    FSG_HIP(ctx, launch_csr_emit(nbr_dev, n, L, keys, vals, ctx->stream));
+    FSG_HIP(ctx, radix_sort_u64(keys, vals, m, bit_length(sentinel), b, ctx->stream));
+    FSG_HIP(ctx, launch_csr_flags(keys, m, sentinel, flags, ctx->stream));
+    FSG_HIP(ctx, launch_exclusive_scan_i64(flags, pos, m, pos + m, partials, ctx->stream));
+    CsrArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.keys = keys;
+    a.pos = pos;
+    a.flags = flags;
+    a.m = m;
+    a.n = n;
+    a.d = X->d;
+    a.X = X->X;
+    a.deg = deg_dev;
+    a.s = gamma * 1.442695040888963407359924681001892137;
+    a.L = L;
+    a.row_ptr = row_ptr_dev;
+    a.col = col_dev;
+    a.w = w_dev;
+    a.cap = cap;
+    FSG_HIP(ctx, launch_csr_fill(a, ctx->stream));
+    }
+    FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *nnz = ctx->host_scratch[0];
+    if (*nnz > cap) return set_error(ctx, FSG_E_INVALID, "cap is smaller than 2|E|");
+    return FSG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// Internal declarations shared by the HIP sources of libfsg.so (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+#include <map>
+#include <set>
+
+#include "fsg.h"
+
+namespace fsg {
+
+// ---------------------------------------------------------------------------
+// Geometry of the FP64 matrix-core operand layout.
+// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// receives C[l/16 + 4i][l%16] in element i.  Points are stored so that one
+// 64-lane load of 512 contiguous bytes is one operand fragment:
+//   Xp[((p >> 4) * D4 + kk) * 64 + lane] = X[16*(p>>4) + (lane & 15)][4*kk + (lane >> 4)]
+// with D4 = number of 4-wide feature steps (features zero-padded to 4*D4) and
+// rows zero-padded to a multiple of 16.
+// ---------------------------------------------------------------------------
+constexpr int kLeafMax = 64;     // largest node the leaf stage resolves
+constexpr int kTileQ = 64;       // query entries per wave in the KDE kernel
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// One unit of KDE work for one wave: up to 16*RQ query entries of one
+// segment against the bins [b0, b1) of that segment.
+struct WorkItem {
+    int32_t seg;
+    int32_t ne;      // number of valid entries (<= tile)
+    int64_t e0;      // first entry
+    int32_t b0, b1;  // bin range (indices into the segment's boundary list)
+};
+
+struct SegDesc {
+    int64_t bound_off;  // offset of the segment's boundary list in the bounds array
+    int32_t nbins;      // bins in the segment (boundaries: nbins + 1)
+    int32_t pad;
+};
+
+enum SelfMode : int32_t { SELF_NONE = 0, SELF_POINT = 1, SELF_ARRAY = 2 };
+
+struct KdeArgs {
+    const double* Qp;        // query operand fragments
+    const double* qnorm;     // ||q||^2, FP64
+    const double* Xp;        // data operand fragments
+    const double* xnorm;     // ||x||^2, FP64 (padded rows hold 0)
+    int32_t D4;              // feature steps
+    int64_t n_query;         // points in the query set (indices are clamped into range)
+    int64_t n_data;          // points in the data set (column ranges are clamped into range)
+    const int32_t* q_idx;    // entry -> query point (NULL: entry index itself)
+    const int32_t* self_idx; // entry -> excluded data index (SELF_ARRAY)
+    int32_t self_mode;
+    const int32_t* bounds;   // boundary lists
+    const SegDesc* segs;
+    const WorkItem* items;
+    const int32_t* n_items;  // device-side count
+    double s;                // gamma * log2(e)
+    double* out;             // out[e * out_stride + bin]
+    int64_t out_stride;
+};
+
+// ---------------------------------------------------------------------------
+// Internal handles.
+// ---------------------------------------------------------------------------
+struct Arena;
+
+}  // namespace fsg
+
+struct fsg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;
+    int num_cus = 256;
+    std::string last_error;
+    // workspace: named device buffers that grow on demand (never shrink)
+    std::map<std::string, std::pair<void*, size_t>> bufs;
+    size_t held = 0;
+    // pinned host scratch for small device->host reads
+    int64_t* host_scratch = nullptr;
+    // stage timing (opt-in): recorded event pairs per stage
+    bool profiling = false;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    std::vector<hipEvent_t> free_events;
+    // live point sets; detached (their ctx cleared) when the context is destroyed
+    std::set<fsg_points*> points;
+};
+
+struct fsg_points {
+    fsg_ctx* ctx = nullptr;
+    const float* X = nullptr;  // borrowed, FP32 row-major n x d
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t D4 = 0;            // padded feature steps
+    int64_t n_pad = 0;         // rows padded to a multiple of 16
+    fsg_precision prec = FSG_FP32;
+    double* Xp = nullptr;      // FP64 operand fragments [n_pad/16][D4][64]
+    double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
+    // tree level boundaries, computed on demand: level -> int32 [2^level + 1]
+    std::map<int, int32_t*> levels;
+    size_t bytes = 0;
+};
+
+namespace fsg {
+
+// Error helpers: every API function funnels HIP failures through these.
+fsg_status set_error(fsg_ctx* ctx, fsg_status s, const std::string& msg);
+#define FSG_HIP(ctx, call)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return ::fsg::set_error((ctx), e_ == hipErrorOutOfMemory ? FSG_E_NOMEM : FSG_E_DEVICE, \
+                                    std::string(#call) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+#define FSG_CHECK_LAUNCH(ctx) FSG_HIP(ctx, hipGetLastError())
+
+// Stage timing: begin/end record events on the context stream when enabled.
+struct StageTimer {
+    fsg_ctx* ctx;
+    std::string name;
+    hipEvent_t start = nullptr;
+    StageTimer(fsg_ctx* c, const char* n);
+    ~StageTimer();
+};
+
+// Workspace buffer of at least `bytes`, keyed by name (reused across calls).
+fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out);
+
+// Feature-step count used for a dimension d (a size the KDE kernel is built for).
+int feature_steps(int d);
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip sources).
+// ---------------------------------------------------------------------------
+hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t n_pad, double* Xp, double* norm,
+                       hipStream_t st);
+hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t st);
+
+// KDE over a work list; grid = waves / 4 blocks of 256 threads.
+hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
+// Work list for segments given by q_ptr (device, int64 [n_seg+1]); every
+// segment has `nbins` bins split into chunks of `bins_per_chunk`.
+hipError_t launch_build_items(const int64_t* q_ptr, int64_t n_seg, int32_t nbins, int32_t bins_per_chunk,
+                              int32_t tile, int64_t* scratch_counts, WorkItem* items, int32_t* n_items,
+                              int64_t max_items, hipStream_t st);
+hipError_t launch_regular_items(int64_t n_entries, int32_t nbins, int32_t bins_per_chunk, int32_t tile,
+                                WorkItem* items, int32_t* n_items, hipStream_t st);
+hipError_t launch_uniform_segs(SegDesc* segs, int64_t n_seg, int64_t stride, int32_t nbins, hipStream_t st);
+hipError_t launch_row_sums(const double* M, int64_t rows, int32_t cols, double* out, hipStream_t st);
+hipError_t launch_api_segments(const int32_t* lo, const int32_t* mid, const int32_t* hi, int64_t n_seg,
+                               int32_t* bounds, SegDesc* segs, hipStream_t st);
+hipError_t launch_split_pairs(const double* pairs, int64_t n, double* left, double* right, hipStream_t st);
+
+// Descent over the bins of one binned pass.
+struct DescArgs {
+    const double* M;           // masses [entries][2^D]
+    int64_t n_entries;
+    int32_t D;                 // levels resolved by this pass
+    int32_t start_level;       // level of the nodes the entries sit at
+    int32_t L;
+    uint64_t seed;
+    const int32_t* entry_sample;  // pass >= 1: entry -> sample id; NULL for the root pass
+    int32_t* node;             // sample -> node index at the current level (in/out)
+    float* margin;             // sample -> running min margin (in/out), may be NULL
+    double* deg;               // root pass: point -> degree, may be NULL
+};
+hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st);
+
+struct LeafArgs {
+    const float* X;            // FP32 points
+    int64_t n;
+    int32_t d;
+    const int32_t* bounds;     // boundaries of the nodes at `level`
+    int32_t level;
+    double s;                  // gamma * log2(e)
+    int32_t L;
+    uint64_t seed;
+    const int32_t* sorted_samples;  // samples ordered by node
+    const int32_t* node_start;      // node -> first position in sorted_samples ([n_nodes+1])
+    const int32_t* items;           // (node, first position) pairs, 64 samples per item
+    const int32_t* n_items;
+    int32_t* nbr;
+    float* margin;
+};
+hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st);
+
+// Samples: sort ids by node; inactive samples (node < 0) go last.
+hipError_t launch_init_samples(int64_t n_samples, int32_t* node, float* margin, hipStream_t st);
+hipError_t launch_node_keys(const int32_t* node, int64_t n_samples, uint32_t inactive_key, uint32_t* keys,
+                            int32_t* vals, hipStream_t st);
+hipError_t launch_node_starts(const uint32_t* sorted_keys, int64_t n_samples, int64_t n_nodes, int32_t* start,
+                              hipStream_t st);
+hipError_t launch_entry_points(const int32_t* sorted_samples, int64_t n, int32_t L, int32_t* q_idx,
+                               hipStream_t st);
+hipError_t launch_leaf_items(const int32_t* node_start, int64_t n_nodes, int64_t* scratch, int32_t* items,
+                             int32_t* n_items, hipStream_t st);
+hipError_t launch_finish_inactive(const int32_t* node, int64_t n_samples, int32_t* nbr, hipStream_t st);
+hipError_t launch_node_qptr(const int32_t* node_start, int64_t n_nodes, int64_t* q_ptr, hipStream_t st);
+
+// Stable LSD radix sort of 32- or 64-bit keys with int32 values over the low
+// `bits` key bits.  tmp buffers must hold n elements each.
+struct SortBufs {
+    void* keys_tmp;     // n keys
+    int32_t* vals_tmp;  // n values
+    uint32_t* hist;     // sort_hist_elems(n)
+    uint32_t* partials; // scan_partials(sort_hist_elems(n)) + 1
+};
+int64_t sort_hist_elems(int64_t n);
+hipError_t radix_sort_u32(uint32_t* keys, int32_t* vals, int64_t n, int bits, const SortBufs& b, hipStream_t st);
+hipError_t radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n, int bits, const SortBufs& b, hipStream_t st);
+
+// Exclusive scan (three phases, tiles of 4096); out may alias in; *total
+// receives the sum; partials needs scan_partials(n) elements.
+int64_t scan_partials(int64_t n);
+hipError_t launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, int64_t* partials,
+                                     hipStream_t st);
+hipError_t launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                                     uint32_t* partials, hipStream_t st);
+
+// CSR.
+hipError_t launch_csr_emit(const int32_t* nbr, int64_t n, int32_t L, uint64_t* keys, int32_t* vals, hipStream_t st);
+hipError_t launch_csr_flags(const uint64_t* keys, int64_t m, uint64_t sentinel, int64_t* flags, hipStream_t st);
+struct CsrArgs {
+    const uint64_t* keys;    // sorted directed entries row*n + col (sentinel n*n)
+    const int64_t* pos;      // exclusive scan of the unique flags, pos[m] = nnz
+    const int64_t* flags;
+    int64_t m;
+    int64_t n;
+    int32_t d;
+    const float* X;
+    const double* deg;
+    double s;                // gamma * log2(e)
+    int32_t L;
+    int64_t* row_ptr;
+    int32_t* col;
+    float* w;
+    int64_t cap;
+};
+hipError_t launch_csr_fill(const CsrArgs& a, hipStream_t st);
+
+}  // namespace fsg

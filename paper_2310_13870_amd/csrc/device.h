@@ -1,0 +1,120 @@
+// Device-side helpers shared by the kernels of libfsg.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsg {
+
+// ---------------------------------------------------------------------------
+// 2^a in FP64 for the Gaussian kernel.  a = n + f with n = rint(a) and
+// |f| <= 1/2; 2^f = e^(f ln 2) is summed as its Taylor series to degree 11,
+// whose remainder is below (ln2/2)^12/12! < 7e-15 relative, and the result is
+// scaled by 2^n with ldexp (exact, gradual underflow to 0 below 2^-1074).
+// ---------------------------------------------------------------------------
+constexpr double kLn2 = 0.693147180559945309417232121458176568;
+constexpr double kLog2e = 1.442695040888963407359924681001892137;
+constexpr double taylor_coef(int k) {
+    double v = 1.0;
+    for (int i = 1; i <= k; ++i) v = v * kLn2 / (double)i;
+    return v;
+}
+
+__device__ __forceinline__ double exp2_fp64(double a) {
+    a = __builtin_fmax(a, -2000.0);  // below 2^-1074 anyway; keeps (int)n defined
+    double n = __builtin_rint(a);
+    double f = a - n;
+    double p = taylor_coef(11);
+    p = __builtin_fma(p, f, taylor_coef(10));
+    p = __builtin_fma(p, f, taylor_coef(9));
+    p = __builtin_fma(p, f, taylor_coef(8));
+    p = __builtin_fma(p, f, taylor_coef(7));
+    p = __builtin_fma(p, f, taylor_coef(6));
+    p = __builtin_fma(p, f, taylor_coef(5));
+    p = __builtin_fma(p, f, taylor_coef(4));
+    p = __builtin_fma(p, f, taylor_coef(3));
+    p = __builtin_fma(p, f, taylor_coef(2));
+    p = __builtin_fma(p, f, taylor_coef(1));
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)n);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 64x64->128 multiplies; the key advances by the Weyl increments between
+// rounds.  u(seed, i, l, level) = (word[level % 4] >> 11) * 2^-53 of the block
+// with key (seed, 0) and counter (i, l, level / 4, 0).
+// ---------------------------------------------------------------------------
+struct PhiloxWords {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ PhiloxWords philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                      uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t p0hi = __umul64hi(M0, c0), p0lo = M0 * c0;
+        const uint64_t p1hi = __umul64hi(M1, c2), p1lo = M1 * c2;
+        const uint64_t n0 = p1hi ^ c1 ^ k0;
+        const uint64_t n2 = p0hi ^ c3 ^ k1;
+        c0 = n0;
+        c1 = p1lo;
+        c2 = n2;
+        c3 = p0lo;
+    }
+    PhiloxWords o;
+    o.w[0] = c0;
+    o.w[1] = c1;
+    o.w[2] = c2;
+    o.w[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ double word_to_uniform(uint64_t w) {
+    return (double)(w >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Uniform source for one sample: caches the Philox block of the current group
+// of four levels.
+struct SampleUniforms {
+    uint64_t seed, i, l;
+    int32_t group;
+    PhiloxWords words;
+    __device__ void init(uint64_t seed_, uint64_t i_, uint64_t l_) {
+        seed = seed_;
+        i = i_;
+        l = l_;
+        group = -1;
+    }
+    __device__ double at(int32_t level) {
+        const int32_t g = level >> 2;
+        if (g != group) {
+            words = philox4x64_10(i, l, (uint64_t)g, 0, seed, 0);
+            group = g;
+        }
+        const int k = level & 3;  // explicit selects keep the words in registers
+        const uint64_t w = (k == 0) ? words.w[0] : (k == 1) ? words.w[1] : (k == 2) ? words.w[2] : words.w[3];
+        return word_to_uniform(w);
+    }
+};
+
+// The descent rule of Algorithm 1 at one node: left iff u*(mL+mR) < mL, never
+// into a child of zero mass.  Returns true for left; *margin = |u - mL/t|.
+__device__ __forceinline__ bool choose_left(double u, double mL, double mR, double* margin) {
+    const double t = mL + mR;
+    bool left = (u * t < mL);
+    if (left && mL == 0.0) left = false;
+    if (!left && mR == 0.0) left = true;
+    *margin = __builtin_fabs(u - mL / t);
+    return left;
+}
+
+// Split of node [a,b): the left half holds floor((b-a)/2) points.
+__device__ __forceinline__ int32_t tree_split(int32_t a, int32_t b) { return a + ((b - a) >> 1); }
+
+}  // namespace fsg

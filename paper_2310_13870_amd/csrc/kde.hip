@@ -1,0 +1,326 @@
+// Segmented Gaussian KDE over tree bins on the FP64 matrix cores (hot-path
+// step "segmented KDE"; the two KDEs of Algorithm 1 and the degree KDE of
+// Algorithm 2, eq. (1) of Section 2.4 over index ranges).
+//
+// A wave owns one work item: up to 16*RQ query entries of one segment and a
+// run of that segment's bins (consecutive index ranges of the data).  It
+// streams the data in 16-column blocks.  Per block and query block, D4
+// v_mfma_f64_16x16x4f64 give the cross terms x_j . q (data as the A operand,
+// so lane l holds data rows l/16 + 4i of query row l%16); the epilogue forms
+// the exponent -gamma log2(e) (|q|^2 + |x|^2 - 2 x.q) in FP64, evaluates 2^a
+// in FP64, removes the self term, and accumulates per lane.  When a bin
+// boundary is crossed the 4 partial sums of each query row are combined with
+// two cross-lane steps and written once: no atomics, fixed order, so results
+// are bit-reproducible.
+#include "common.h"
+#include "device.h"
+
+namespace fsg {
+
+template <int D4, int RQ>
+__global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    const int32_t n_items = *a.n_items;
+    const double two_s = 2.0 * a.s;
+    const int grp = lane >> 4;  // data row group inside a 16-column block
+    const int r = lane & 15;    // query row inside a query block
+
+    for (int64_t it = wave; it < n_items; it += n_waves) {
+        const WorkItem w = a.items[it];
+        const SegDesc sg = a.segs[w.seg];
+        const int32_t* bnd = a.bounds + sg.bound_off;
+
+        double qf[RQ][D4];
+        double hq[RQ];
+        int32_t selfv[RQ], smin[RQ], smax[RQ];
+        bool rowok[RQ];
+#pragma unroll
+        for (int qb = 0; qb < RQ; ++qb) {
+            const int32_t t = 16 * qb + r;
+            const bool ok = t < w.ne;
+            const int64_t e = w.e0 + (ok ? t : 0);
+            int32_t p = a.q_idx ? a.q_idx[e] : (int32_t)e;
+            p = min(max(p, 0), (int32_t)(a.n_query - 1));  // never read outside the query set
+            int32_t sf = -1;
+            if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
+            selfv[qb] = sf;
+            rowok[qb] = ok;
+            hq[qb] = -a.s * a.qnorm[p];
+            const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
+#pragma unroll
+            for (int kk = 0; kk < D4; ++kk) qf[qb][kk] = src[kk * 64];
+            int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                mn = min(mn, __shfl_xor(mn, off));
+                mx = max(mx, __shfl_xor(mx, off));
+            }
+            smin[qb] = mn;
+            smax[qb] = mx;
+        }
+
+        const int32_t b0 = w.b0, b1 = w.b1;
+        // never read outside the data set, whatever the boundaries say
+        const int32_t col_end = min(max(bnd[b1], 0), (int32_t)a.n_data);
+        const int32_t col_begin = min(max(bnd[b0], 0), col_end);
+        int32_t cur = b0 - 1;  // bin being accumulated (b0-1: before the first bin)
+        int32_t nxt = col_begin;
+        double acc[RQ];
+#pragma unroll
+        for (int qb = 0; qb < RQ; ++qb) acc[qb] = 0.0;
+
+        auto flush = [&](int32_t bin) {
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb) {
+                double v = acc[qb];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < 16 && rowok[qb]) a.out[(w.e0 + 16 * qb + lane) * a.out_stride + bin] = v;
+                acc[qb] = 0.0;
+            }
+        };
+
+        for (int32_t c0 = col_begin & ~15; c0 < col_end; c0 += 16) {
+            double xf[D4];
+            const double* xs = a.Xp + (int64_t)(c0 >> 4) * D4 * 64 + lane;
+#pragma unroll
+            for (int kk = 0; kk < D4; ++kk) xf[kk] = xs[kk * 64];
+            int32_t jj[4];
+            double hx[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                jj[i] = c0 + grp + 4 * i;
+                hx[i] = -a.s * a.xnorm[jj[i]];
+            }
+            double kv[RQ][4];
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb) {
+                double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < D4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) kv[qb][i] = exp2_fp64(__builtin_fma(two_s, c[i], hq[qb] + hx[i]));
+                if (smax[qb] >= c0 && smin[qb] < c0 + 16) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (jj[i] == selfv[qb]) kv[qb][i] = 0.0;
+                }
+            }
+            // bin boundaries inside this block (uniform across the wave)
+            while (nxt < c0 + 16) {
+                if (cur >= b0) {
+#pragma unroll
+                    for (int qb = 0; qb < RQ; ++qb) {
+                        double part = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (jj[i] < nxt) part += kv[qb][i];
+                        acc[qb] += part;
+                    }
+                    flush(cur);
+                }
+#pragma unroll
+                for (int qb = 0; qb < RQ; ++qb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (jj[i] < nxt) kv[qb][i] = 0.0;
+                ++cur;
+                nxt = (cur < b1) ? bnd[cur + 1] : INT32_MAX;
+            }
+            if (cur >= b0 && cur < b1) {
+#pragma unroll
+                for (int qb = 0; qb < RQ; ++qb) acc[qb] += (kv[qb][0] + kv[qb][1]) + (kv[qb][2] + kv[qb][3]);
+            }
+        }
+        // the bin still open and any empty bins after the last column
+        while (cur < b1) {
+            if (cur >= b0) flush(cur);
+            ++cur;
+        }
+    }
+}
+
+template <int D4, int RQ>
+static hipError_t launch_kde_t(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
+    int64_t waves = (int64_t)num_cus * 8;
+    if (max_items < waves) waves = max_items;
+    if (waves < 1) waves = 1;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    kde_bins_kernel<D4, RQ><<<blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+int feature_steps(int d) {
+    const int d4 = (d + 3) / 4;
+    if (d4 <= 1) return 1;
+    if (d4 <= 2) return 2;
+    if (d4 <= 4) return 4;
+    if (d4 <= 8) return 8;
+    if (d4 <= 16) return 16;
+    if (d4 <= 32) return 32;
+    return -1;  // larger d: not built
+}
+
+hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
+    switch (a.D4) {
+        case 1: return launch_kde_t<1, 4>(a, max_items, num_cus, st);
+        case 2: return launch_kde_t<2, 4>(a, max_items, num_cus, st);
+        case 4: return launch_kde_t<4, 4>(a, max_items, num_cus, st);
+        case 8: return launch_kde_t<8, 4>(a, max_items, num_cus, st);
+        case 16: return launch_kde_t<16, 4>(a, max_items, num_cus, st);
+        case 32: return launch_kde_t<32, 4>(a, max_items, num_cus, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work lists.
+// ---------------------------------------------------------------------------
+__global__ void regular_items_kernel(int64_t n_entries, int32_t nbins, int32_t bpc, int32_t tile, int64_t n_tiles,
+                                     int64_t total, WorkItem* items, int32_t* n_items) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *n_items = (int32_t)total;
+    if (t >= total) return;
+    // chunk-major: waves that run together share the same data columns
+    const int64_t c = t / n_tiles, q = t - c * n_tiles;
+    WorkItem w;
+    w.seg = 0;
+    w.e0 = q * tile;
+    const int64_t rem = n_entries - w.e0;
+    w.ne = (int32_t)(rem < tile ? rem : tile);
+    w.b0 = (int32_t)(c * bpc);
+    w.b1 = (int32_t)min((int64_t)nbins, (c + 1) * (int64_t)bpc);
+    items[t] = w;
+}
+
+hipError_t launch_regular_items(int64_t n_entries, int32_t nbins, int32_t bins_per_chunk, int32_t tile,
+                                WorkItem* items, int32_t* n_items, hipStream_t st) {
+    const int64_t n_tiles = (n_entries + tile - 1) / tile;
+    const int64_t n_chunks = (nbins + bins_per_chunk - 1) / bins_per_chunk;
+    const int64_t total = n_tiles * n_chunks;
+    regular_items_kernel<<<(unsigned)((total + 255) / 256 + 1), 256, 0, st>>>(n_entries, nbins, bins_per_chunk, tile,
+                                                                             n_tiles, total, items, n_items);
+    return hipGetLastError();
+}
+
+__global__ void segment_item_counts_kernel(const int64_t* q_ptr, int64_t n_seg, int32_t n_chunks, int32_t tile,
+                                           int64_t* counts) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    const int64_t cnt = q_ptr[s + 1] - q_ptr[s];
+    counts[s] = ((cnt + tile - 1) / tile) * n_chunks;
+}
+
+__global__ void segment_items_fill_kernel(const int64_t* q_ptr, const int64_t* offsets, int64_t n_seg,
+                                          int32_t nbins, int32_t bpc, int32_t n_chunks, int32_t tile,
+                                          const int64_t* total, int64_t max_items, WorkItem* items,
+                                          int32_t* n_items) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = *total;
+    if (t == 0) *n_items = (int32_t)(tot < max_items ? tot : max_items);
+    if (t >= tot || t >= max_items) return;
+    // segment of item t: last s with offsets[s] <= t (skipping empty segments)
+    int64_t lo = 0, hi = n_seg - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (offsets[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int64_t s = lo;
+    const int64_t local = t - offsets[s];
+    const int64_t cnt = q_ptr[s + 1] - q_ptr[s];
+    const int64_t n_tiles = (cnt + tile - 1) / tile;
+    const int64_t c = local / n_tiles, q = local - c * n_tiles;
+    WorkItem w;
+    w.seg = (int32_t)s;
+    w.e0 = q_ptr[s] + q * tile;
+    const int64_t rem = cnt - q * tile;
+    w.ne = (int32_t)(rem < tile ? rem : tile);
+    w.b0 = (int32_t)(c * bpc);
+    w.b1 = (int32_t)min((int64_t)nbins, (c + 1) * (int64_t)bpc);
+    items[t] = w;
+}
+
+hipError_t launch_build_items(const int64_t* q_ptr, int64_t n_seg, int32_t nbins, int32_t bins_per_chunk,
+                              int32_t tile, int64_t* scratch_counts, WorkItem* items, int32_t* n_items,
+                              int64_t max_items, hipStream_t st) {
+    // scratch_counts: n_seg + 1 counts, then n_seg + 1 offsets, then 1 total, then scan partials
+    const int32_t n_chunks = (nbins + bins_per_chunk - 1) / bins_per_chunk;
+    int64_t* counts = scratch_counts;
+    int64_t* offsets = counts + (n_seg + 1);
+    int64_t* total = offsets + (n_seg + 1);
+    int64_t* partials = total + 1;
+    segment_item_counts_kernel<<<(unsigned)((n_seg + 255) / 256 + 1), 256, 0, st>>>(q_ptr, n_seg, n_chunks, tile,
+                                                                                   counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan_i64(counts, offsets, n_seg, total, partials, st);
+    if (e != hipSuccess) return e;
+    segment_items_fill_kernel<<<(unsigned)((max_items + 255) / 256 + 1), 256, 0, st>>>(
+        q_ptr, offsets, n_seg, nbins, bins_per_chunk, n_chunks, tile, total, max_items, items, n_items);
+    return hipGetLastError();
+}
+
+__global__ void uniform_segs_kernel(SegDesc* segs, int64_t n_seg, int64_t stride, int32_t nbins) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    SegDesc g;
+    g.bound_off = s * stride;
+    g.nbins = nbins;
+    g.pad = 0;
+    segs[s] = g;
+}
+
+hipError_t launch_uniform_segs(SegDesc* segs, int64_t n_seg, int64_t stride, int32_t nbins, hipStream_t st) {
+    uniform_segs_kernel<<<(unsigned)((n_seg + 255) / 256 + 1), 256, 0, st>>>(segs, n_seg, stride, nbins);
+    return hipGetLastError();
+}
+
+__global__ void api_segments_kernel(const int32_t* lo, const int32_t* mid, const int32_t* hi, int64_t n_seg,
+                                    int32_t* bounds, SegDesc* segs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_seg) return;
+    bounds[3 * s] = lo[s];
+    bounds[3 * s + 1] = mid[s];
+    bounds[3 * s + 2] = hi[s];
+    SegDesc g;
+    g.bound_off = 3 * s;
+    g.nbins = 2;
+    g.pad = 0;
+    segs[s] = g;
+}
+
+hipError_t launch_api_segments(const int32_t* lo, const int32_t* mid, const int32_t* hi, int64_t n_seg,
+                               int32_t* bounds, SegDesc* segs, hipStream_t st) {
+    api_segments_kernel<<<(unsigned)((n_seg + 255) / 256 + 1), 256, 0, st>>>(lo, mid, hi, n_seg, bounds, segs);
+    return hipGetLastError();
+}
+
+__global__ void row_sums_kernel(const double* M, int64_t rows, int32_t cols, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const double* m = M + i * cols;
+    double s = 0.0;
+    for (int32_t b = 0; b < cols; ++b) s += m[b];
+    out[i] = s;
+}
+
+hipError_t launch_row_sums(const double* M, int64_t rows, int32_t cols, double* out, hipStream_t st) {
+    row_sums_kernel<<<(unsigned)((rows + 255) / 256 + 1), 256, 0, st>>>(M, rows, cols, out);
+    return hipGetLastError();
+}
+
+__global__ void split_pairs_kernel(const double* pairs, int64_t n, double* left, double* right) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    left[e] = pairs[2 * e];
+    right[e] = pairs[2 * e + 1];
+}
+
+hipError_t launch_split_pairs(const double* pairs, int64_t n, double* left, double* right, hipStream_t st) {
+    split_pairs_kernel<<<(unsigned)((n + 255) / 256 + 1), 256, 0, st>>>(pairs, n, left, right);
+    return hipGetLastError();
+}
+
+}  // namespace fsg

@@ -1,0 +1,75 @@
+// Hot-path step "prep": FP64 matrix-core operand fragments, squared norms,
+// and the node boundaries of one level of the index-order partition tree.
+#include "common.h"
+#include "device.h"
+
+namespace fsg {
+
+__global__ void prep_fragments_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t D4, int64_t total,
+                                      double* __restrict__ Xp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t per_blk = (int64_t)D4 * 64;
+    const int64_t blk = idx / per_blk;
+    const int32_t rem = (int32_t)(idx - blk * per_blk);
+    const int32_t kk = rem >> 6, lane = rem & 63;
+    const int64_t row = blk * 16 + (lane & 15);
+    const int32_t col = kk * 4 + (lane >> 4);
+    Xp[idx] = (row < n && col < d) ? (double)X[row * d + col] : 0.0;
+}
+
+__global__ void prep_norms_kernel(const float* __restrict__ X, int64_t n, int32_t d, int64_t n_pad,
+                                  double* __restrict__ norm) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n_pad) return;
+    double s = 0.0;
+    if (row < n) {
+        const float* x = X + row * d;
+        for (int32_t t = 0; t < d; ++t) {
+            const double v = (double)x[t];
+            s = __builtin_fma(v, v, s);
+        }
+    }
+    norm[row] = s;
+}
+
+hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t n_pad, double* Xp, double* norm,
+                       hipStream_t st) {
+    const int64_t total = n_pad * D4 * 4;
+    prep_fragments_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, n, d, D4, total, Xp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    prep_norms_kernel<<<(unsigned)((n_pad + 255) / 256), 256, 0, st>>>(X, n, d, n_pad, norm);
+    return hipGetLastError();
+}
+
+// out[v] = first index of node v at depth `level` (v < 2^level), out[2^level] = n.
+// Valid while every node of the level exists, i.e. level <= floor(log2 n).
+__global__ void level_bounds_kernel(int64_t n, int32_t level, int32_t* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t count = (int64_t)1 << level;
+    if (v > count) return;
+    if (v == count) {
+        out[v] = (int32_t)n;
+        return;
+    }
+    int64_t lo = 0, size = n;
+    for (int32_t t = level - 1; t >= 0; --t) {
+        const int64_t half = size >> 1;
+        if ((v >> t) & 1) {
+            lo += half;
+            size -= half;
+        } else {
+            size = half;
+        }
+    }
+    out[v] = (int32_t)lo;
+}
+
+hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t st) {
+    const int64_t count = ((int64_t)1 << level) + 1;
+    level_bounds_kernel<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(n, level, out);
+    return hipGetLastError();
+}
+
+}  // namespace fsg

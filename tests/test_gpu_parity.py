@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: degrees within 1e-9 relative (the path is FP64 end to end; the stated
+bar is 1e-5), sampled neighbours identical except band-exempt samples (the
+oracle's uniform within 1e-6 of a split boundary), CSR structure identical
+and weights within FP32 rounding.  Sizes span several tiles with ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_common import BAND, compare_neighbours, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_13870_amd as fsg  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = fsg.Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+def _mix(n, d, seed, comps=4, spread=3.0):
+    return workloads.mixture(n, d, comps, seed, (-spread, spread), (0.5, 1.5))
+
+
+@pytest.mark.parametrize("n,d,gamma", [(1, 3, 0.5), (2, 2, 0.5), (17, 5, 0.3), (64, 2, 0.5), (1000, 2, 0.5),
+                                       (2049, 8, 0.1), (3001, 32, 1 / 8), (1500, 33, 0.02), (777, 64, 1 / 18),
+                                       (640, 100, 0.01)])
+def test_degrees(ctx, n, d, gamma):
+    say(f"degrees n={n} d={d}")
+    X = _mix(n, d, 100 + n + d)
+    Xd = to_dev(X)
+    pts = fsg.Points(ctx, Xd)
+    deg = fsg.degrees(ctx, pts, gamma).cpu().numpy()
+    ctx.sync()
+    ref = oracle.degrees(X, gamma)
+    rel = np.abs(deg - ref) / np.maximum(ref, 1e-300)
+    assert np.all(np.isfinite(deg))
+    if n == 1:
+        assert deg[0] == 0.0
+    else:
+        assert rel.max() < 1e-9, f"max rel err {rel.max()}"
+
+
+def test_degrees_identical_points(ctx):
+    X = np.full((300, 7), 0.25, dtype=np.float32)
+    deg = fsg.degrees(ctx, fsg.Points(ctx, to_dev(X)), 3.0).cpu().numpy()
+    # the FP64 norm expansion leaves k = 1 up to an ulp for identical points
+    np.testing.assert_allclose(deg, np.full(300, 299.0), rtol=1e-12)
+
+
+def test_kde_segmented(ctx):
+    rng = np.random.default_rng(7)
+    nx, nq, d, gamma = 2500, 700, 12, 0.05
+    X = _mix(nx, d, 8)
+    Q = _mix(nq, d, 9)
+    segs = [(0, 1250, 2500), (10, 10, 30), (30, 45, 45), (2499, 2499, 2500), (0, 0, 0), (57, 120, 1800),
+            (100, 116, 132), (3, 4, 5), (1000, 1001, 2400)]
+    sizes = [300, 5, 0, 7, 3, 130, 64, 1, 65]
+    q_lists = [rng.integers(0, nq, size=s) for s in sizes]
+    q_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    q_idx = np.concatenate(q_lists).astype(np.int32)
+    self_idx = rng.integers(-1, nx, size=q_idx.shape[0]).astype(np.int32)
+    # make some selves fall inside their segment
+    for s, (a, m, b) in enumerate(segs):
+        for e in range(q_ptr[s], q_ptr[s + 1]):
+            if b > a and rng.random() < 0.5:
+                self_idx[e] = rng.integers(a, b)
+    lo, mid, hi = (np.array(v, dtype=np.int32) for v in zip(*segs))
+    say("kde_segmented")
+    ptsX, ptsQ = fsg.Points(ctx, to_dev(X)), fsg.Points(ctx, to_dev(Q))
+    left, right = fsg.kde_segmented(ctx, ptsQ, ptsX, gamma, to_dev(q_ptr), to_dev(q_idx), to_dev(lo), to_dev(mid),
+                                    to_dev(hi), to_dev(self_idx))
+    left, right = left.cpu().numpy(), right.cpu().numpy()
+    rl, rr = oracle.kde_segmented(Q, X, gamma, q_ptr, q_idx, lo, mid, hi, self_idx)
+    for got, ref in ((left, rl), (right, rr)):
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+        err[ref == 0] = np.abs(got[ref == 0])
+        assert err.max() < 1e-9, f"max err {err.max()}"
+
+
+def _sample_parity(ctx, X, gamma, L, seed, tag):
+    say(f"sample_edges {tag} n={X.shape[0]} d={X.shape[1]} L={L}")
+    pts = fsg.Points(ctx, to_dev(X))
+    nbr, deg, margin = fsg.sample_edges(ctx, pts, gamma, L, seed, want_deg=True, want_margin=True)
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, gamma, L, seed)
+    rel = np.abs(deg - rdeg) / np.maximum(rdeg, 1e-300)
+    rel[rdeg == 0] = np.abs(deg[rdeg == 0])
+    assert rel.max() < 1e-9, f"{tag}: degree max rel err {rel.max()}"
+    mism, exempt, non_exempt = compare_neighbours(nbr, rnbr, rmargin)
+    say(f"  mismatches {mism} (band-exempt {exempt}, non-exempt {non_exempt}) of {nbr.size}")
+    assert non_exempt == 0, f"{tag}: {non_exempt} non-exempt neighbour mismatches"
+    return pts, nbr, deg, rnbr, rdeg
+
+
+@pytest.mark.parametrize("n,d,L", [(1, 2, 3), (2, 2, 4), (3, 1, 5), (17, 3, 6), (64, 2, 7), (65, 2, 7),
+                                   (130, 4, 5), (1000, 2, 10), (4097, 8, 13), (3000, 32, 12), (2000, 64, 8),
+                                   (1111, 17, 9)])
+def test_sample_edges(ctx, n, d, L):
+    X = _mix(n, d, 500 + n + d)
+    gamma = 1.0 / (2.0 * (0.5 * math.sqrt(d)) ** 2)
+    _sample_parity(ctx, X, gamma, L, 1234 + n, f"mix{n}x{d}")
+
+
+def test_sample_edges_tiny_blobs(ctx):
+    w = workloads.tiny_blobs()
+    _sample_parity(ctx, w.points(), w.gamma, w.L, w.philox_seed, w.name)
+
+
+def test_isolated_points(ctx):
+    X = (np.arange(40, dtype=np.float32) * 1000.0).reshape(-1, 1)
+    X[5] = X[4] + 0.5  # one close pair among isolated points
+    pts, nbr, deg, rnbr, rdeg = _sample_parity(ctx, X, 1.0, 4, 3, "isolated")
+    assert np.all(nbr[[4, 5]] == [[5] * 4, [4] * 4])
+    assert np.all(np.delete(nbr, [4, 5], axis=0) == -1)
+
+
+def test_identical_points_uniform(ctx):
+    n, L = 200, 500
+    X = np.zeros((n, 3), dtype=np.float32)
+    pts, nbr, deg, _, _ = _sample_parity(ctx, X, 2.0, L, 11, "identical")
+    np.testing.assert_allclose(deg, np.full(n, n - 1.0), rtol=1e-12)
+    counts = np.bincount(nbr[0], minlength=n)
+    assert counts[0] == 0
+
+
+def test_build_csr(ctx):
+    n, d, L = 3000, 16, 11
+    X = _mix(n, d, 42)
+    gamma = 0.125
+    pts, nbr, deg, rnbr, rdeg = _sample_parity(ctx, X, gamma, L, 77, "csr")
+    say("build_csr")
+    row_ptr, col, w = fsg.build_csr(ctx, pts, gamma, L, to_dev(nbr), to_dev(deg))
+    row_ptr, col, w = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    rrp, rcol, rw = oracle.build_csr(X, gamma, L, nbr, rdeg)  # same neighbours, oracle degrees
+    assert np.array_equal(row_ptr, rrp)
+    assert np.array_equal(col, rcol)
+    np.testing.assert_allclose(w, rw, rtol=1e-6)
+
+
+def test_deterministic(ctx):
+    X = _mix(5000, 16, 5)
+    pts = fsg.Points(ctx, to_dev(X))
+    a = fsg.sample_edges(ctx, pts, 0.1, 9, 5, want_margin=True)
+    b = fsg.sample_edges(ctx, pts, 0.1, 9, 5, want_margin=True)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_invalid_arguments(ctx):
+    X = to_dev(np.zeros((10, 3), dtype=np.float32))
+    pts = fsg.Points(ctx, X)
+    with pytest.raises(fsg.FsgError) as e:
+        fsg.degrees(ctx, pts, -1.0)
+    assert e.value.status == fsg.FSG_E_INVALID
+    with pytest.raises(fsg.FsgError):
+        fsg.sample_edges(ctx, pts, 1.0, 0, 1)
+    with pytest.raises(fsg.FsgError):
+        fsg.degrees(ctx, pts, float("nan"))
+
+
+def test_points_outlive_context():
+    """Destroying a context before its point sets leaves them safe to destroy."""
+    c = fsg.Context(0)
+    pts = fsg.Points(c, to_dev(np.zeros((50, 2), dtype=np.float32)))
+    c.close()
+    pts.close()
