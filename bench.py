@@ -25,8 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+PRECISION_NOTE = {
+    "fp32": "plain: fp32 points, every pair on the fp64 matrix cores, fp64 exp",
+    "bf16_split": "bf16 hi/lo split filter on bf16 matrix cores (fp32 accumulate), kept pairs exact in fp64",
+}
 METRIC = "kernel evals/s + sampled edges/s, BF16-split vs FP32 plain; p50/p99 latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
 def kde_source_hash() -> str:
@@ -81,8 +86,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mix32-n100k")
+    ap.add_argument("--precision", default="bf16_split", choices=["fp32", "bf16_split"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference "
+                         "that scales the HBM byte counters of a profiling run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -101,9 +110,15 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     ctx = fsg.Context(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
-        pts = fsg.Points(ctx, Xd)
+        pts = fsg.Points(ctx, Xd, args.precision)
         nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, L, w.philox_seed)
         row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, L, nbr, deg)
         pts.close()
@@ -124,8 +139,9 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     ctx.set_profiling(False)
+    kept, scanned = ctx.filter_stats()
     stages = {}
-    for name in ("prep", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
+    for name in ("prep", "kde_mask", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
         ms, cnt = ctx.stage_time(name)
         if cnt:
             stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
@@ -138,17 +154,35 @@ def main():
     while math.ceil(n / 2 ** depth_leaf) > 64:
         depth_leaf += 1
     evals = n * (n - 1) + n * L * n / 2 ** depth_leaf if depth_leaf > 0 else n * L * n
+    def split_k(dd):
+        return 32 * ((3 * dd + 2 + 31) // 32)
+
     kde = stages.get("kde_root")
-    roofline = None
+    mask = stages.get("kde_mask")
+    roofline, distance_tiles = None, None
     if kde:
-        flops = 2.0 * d * n * (n - 1)
+        # FP64 matrix-core flops of the exact cross terms: all n(n-1) pairs in the
+        # plain mode, the kept (column, 64-query tile) pairs in the precision mode
+        if args.precision == "fp32":
+            pairs = n * (n - 1)
+        else:
+            pairs = kept / args.steps * 64
+        flops = 2.0 * d * pairs
         achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
         traffic = traffic_from_profile(args.workload)
-        roofline = {"bound": "mfma", "kernel": "kde_bins_kernel (binned KDE over all points)",
+        roofline = {"bound": "mfma", "kernel": "binned exact KDE over all points (FP64 matrix cores)",
                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
-                    "ms_per_launch": kde["ms_per_launch"],
-                    "algorithmic_flops_per_launch": flops}
+                    "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops}
+    if mask:
+        flops = 2.0 * split_k(d) * n * n
+        achieved = flops / (mask["ms_per_launch"] * 1e-3) / 1e12
+        distance_tiles = {"bound": "mfma", "kernel": "BF16 split keep-mask kernel (distance tiles)",
+                          "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "ms_per_launch": mask["ms_per_launch"],
+                          "algorithmic_flops_per_launch": flops}
+        if roofline is None or mask["ms_per_launch"] > kde["ms_per_launch"]:
+            roofline, distance_tiles = distance_tiles, roofline
     times_ms = np.array(times) * 1e3
     out = {
         "metric": METRIC,
@@ -164,13 +198,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": d, "L": L, "sigma": w.sigma, "gamma": w.gamma,
-                   "components": w.n_comp, "precision": "fp32 points, fp64 matrix-core cross term, fp64 exp"},
+                   "components": w.n_comp, "precision": PRECISION_NOTE[args.precision]},
         "kernel_evals_per_s": evals / (total / args.steps),
         "p50_ms": float(np.percentile(times_ms, 50)),
         "p99_ms": float(np.percentile(times_ms, 99)),
         "distinct_edges": nnz // 2,
         "stages": stages,
+        "filter": ({"kept_column_tiles": kept, "scanned_column_tiles": scanned,
+                    "kept_fraction": kept / scanned} if scanned else None),
         "roofline": roofline,
+        "second_kernel_roofline": distance_tiles,
         "cpu_baseline": None,
     }
     ctx.close()

@@ -56,7 +56,18 @@ typedef enum {
 } fsg_status;
 
 typedef enum {
-    FSG_FP32 = 0 /* FP32 points; FP64 matrix-core cross term, FP64 distances, FP64 exp */
+    /* plain: every pair's cross term on the FP64 matrix cores, FP64 distance
+     * and exp */
+    FSG_FP32 = 0,
+    /* precision mode: BF16 hi/lo split operands (hi = bf16(x), lo = bf16(x-hi))
+     * on the BF16 matrix cores with FP32 accumulation give every pair an
+     * approximate exponent with a guaranteed error bound; only pairs that can
+     * carry more than e^-Delta of their row's largest term (Delta = ln n + 30)
+     * are recomputed in FP64 as in FSG_FP32, the others add 0.  The masses then
+     * differ from the exact ones by less than n e^-Delta < 1e-13 relative.
+     * Applies to the pass over all points (fsg_degrees, the first pass of
+     * fsg_sample_edges); d <= 64. */
+    FSG_BF16_SPLIT = 1
 } fsg_precision;
 
 typedef struct fsg_ctx fsg_ctx;
@@ -86,10 +97,22 @@ uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
 fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled);
 fsg_status fsg_ctx_stage_time(fsg_ctx* ctx, const char* stage, double* ms, int64_t* launches);
 fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);
+/* Precision-mode statistics since the last reset: *kept = (data column, wave
+ * tile) pairs recomputed exactly, *scanned = (data column, wave tile) pairs
+ * examined by the BF16 filter.  Synchronises the stream. */
+fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned);
+
+/* Cap the number of tree levels one binned KDE pass resolves (0 restores the
+ * automatic choice, which is bounded by the workspace budget).  Results do not
+ * depend on it; smaller caps trade more passes for less workspace. */
+fsg_status fsg_ctx_set_levels_per_pass(fsg_ctx* ctx, int32_t max_levels);
 
 /* Make a point set resident: X_dev is FP32 row-major n x d (borrowed).  Derives
  * the FP64 matrix-core operand layout and the squared norms (hot-path step
- * "prep").  1 <= n <= 2^31-1, 1 <= d <= 1024. */
+ * "prep"); with FSG_BF16_SPLIT also the split BF16 operands, an upper bound on
+ * each point's smallest squared distance (from 256 pivot points) and an order
+ * of the points by nearest pivot (used to form coherent query tiles).
+ * 1 <= n <= 2^31-1, 1 <= d <= 128 (FSG_FP32) or 64 (FSG_BF16_SPLIT). */
 fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_t d, fsg_precision prec,
                              fsg_points** out);
 void fsg_points_destroy(fsg_points* pts);

@@ -14,7 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsg.so")
 
 FSG_OK, FSG_E_INVALID, FSG_E_NOMEM, FSG_E_DEVICE, FSG_E_UNSUPPORTED, FSG_E_BUDGET = 0, -1, -2, -3, -4, -5
-FSG_FP32 = 0
+FSG_FP32, FSG_BF16_SPLIT = 0, 1
+PRECISIONS = {"fp32": FSG_FP32, "bf16_split": FSG_BF16_SPLIT}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfsg.so is not built ({LIB_PATH}); run paper_2310_13870_amd/build.py")
@@ -37,10 +38,12 @@ _lib_fns = dict(
     fsg_last_error=_sig("fsg_last_error", ctypes.c_char_p, _vp),
     fsg_ctx_sync=_sig("fsg_ctx_sync", ctypes.c_int, _vp),
     fsg_ctx_workspace_bytes=_sig("fsg_ctx_workspace_bytes", _u64, _vp),
+    fsg_ctx_set_levels_per_pass=_sig("fsg_ctx_set_levels_per_pass", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_stage_time=_sig("fsg_ctx_stage_time", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_dbl),
                             ctypes.POINTER(_i64)),
     fsg_ctx_reset_profiling=_sig("fsg_ctx_reset_profiling", ctypes.c_int, _vp),
+    fsg_ctx_filter_stats=_sig("fsg_ctx_filter_stats", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)),
     fsg_points_create=_sig("fsg_points_create", ctypes.c_int, _vp, _vp, _i64, _i32, ctypes.c_int,
                            ctypes.POINTER(_vp)),
     fsg_points_destroy=_sig("fsg_points_destroy", None, _vp),
@@ -100,6 +103,10 @@ class Context:
     def sync(self):
         self.check(_lib.fsg_ctx_sync(self._h))
 
+    def set_levels_per_pass(self, max_levels: int):
+        """Cap the tree levels one binned pass resolves (0 = automatic)."""
+        self.check(_lib.fsg_ctx_set_levels_per_pass(self._h, max_levels))
+
     def set_profiling(self, enabled: bool):
         self.check(_lib.fsg_ctx_set_profiling(self._h, 1 if enabled else 0))
 
@@ -111,6 +118,12 @@ class Context:
         ms, cnt = _dbl(0.0), _i64(0)
         self.check(_lib.fsg_ctx_stage_time(self._h, stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def filter_stats(self):
+        """(kept, scanned) column-tile pairs of the precision-mode filter since the last reset."""
+        kept, scanned = _i64(0), _i64(0)
+        self.check(_lib.fsg_ctx_filter_stats(self._h, ctypes.byref(kept), ctypes.byref(scanned)))
+        return kept.value, scanned.value
 
     @property
     def workspace_bytes(self) -> int:
@@ -131,7 +144,9 @@ class Context:
 class Points:
     """fsg_points: a resident point set.  Keeps a reference to X (borrowed by the library)."""
 
-    def __init__(self, ctx: Context, X: torch.Tensor, precision: int = FSG_FP32):
+    def __init__(self, ctx: Context, X: torch.Tensor, precision=FSG_FP32):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
         _dev_tensor(X, torch.float32, "X")
         if X.dim() != 2:
             raise ValueError("X must be n x d")
@@ -210,9 +225,9 @@ def build_csr(ctx: Context, pts: Points, gamma: float, L: int, nbr: torch.Tensor
     return row_ptr, col[: nnz.value], w[: nnz.value]
 
 
-def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int):
+def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_FP32):
     """Algorithm 2 end to end: prep, sampling, degrees, reweighting and CSR."""
-    pts = Points(ctx, X)
+    pts = Points(ctx, X, precision)
     nbr, deg, _ = sample_edges(ctx, pts, gamma, L, seed)
     row_ptr, col, w = build_csr(ctx, pts, gamma, L, nbr, deg)
     return row_ptr, col, w, nbr, deg

@@ -138,7 +138,7 @@ struct Plan {
     std::vector<std::pair<int, int>> passes;  // (start level, D)
 };
 
-static Plan make_plan(int64_t n, int32_t L, uint64_t budget) {
+static Plan make_plan(int64_t n, int32_t L, uint64_t budget, int cap) {
     Plan p;
     int lv = 0;
     while ((n + ((int64_t)1 << lv) - 1) >> lv > kLeafMax) ++lv;
@@ -148,7 +148,11 @@ static Plan make_plan(int64_t n, int32_t L, uint64_t budget) {
     while (start < lv) {
         const uint64_t rows = (start == 0) ? (uint64_t)n : (uint64_t)n * (uint64_t)L;
         int maxD = floor_log2((int64_t)(per_pass / (rows * 8)));
-        if (maxD > 12) maxD = 12;
+        // the root descent keeps its sum tree in LDS (2^(D+1) doubles); later
+        // passes keep 2^D bins per sample in registers
+        const int hard = (start == 0) ? 11 : 6;
+        if (maxD > hard) maxD = hard;
+        if (cap > 0 && maxD > cap) maxD = cap;
         if (maxD < 1) maxD = 1;
         int D = lv - start;
         if (D > maxD) D = maxD;
@@ -156,6 +160,12 @@ static Plan make_plan(int64_t n, int32_t L, uint64_t budget) {
         start += D;
     }
     return p;
+}
+
+static int tree_depth(int64_t n) {
+    int dpt = 0;
+    while (((int64_t)1 << dpt) < n) ++dpt;
+    return dpt;
 }
 
 static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma) {
@@ -203,6 +213,49 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     a.n_items = n_items_dev;
     a.out = M;
     a.out_stride = nbins;
+    if (X->prec == FSG_BF16_SPLIT) {
+        // entries in pivot order, so that each wave's 64 queries are close
+        // together and keep few columns; rows are written by point
+        a.q_idx = X->order;
+        a.out_rows = X->order;
+        MaskArgs m;
+        std::memset(&m, 0, sizeof(m));
+        m.Xb = X->Xb;
+        m.Qb = X->Qb;
+        m.KB = X->KB;
+        m.q_idx = X->order;
+        m.n_entries = n;
+        m.n_query = n;
+        m.n_data = n;
+        m.qnorm = X->norm;
+        m.dmin = X->dmin;
+        m.xmax = X->xmax;
+        m.margin_z = std::log((double)n) + 30.0;
+        m.eps = 1.0 / 1024.0;
+        m.gamma = gamma;
+        m.n_tiles = tiles;
+        m.n_blocks = X->n_pad / 16;
+        m.blocks_per_chunk = 512;
+        m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+        if ((st = ws(ctx, "keep_mask", (size_t)(m.n_tiles * m.n_blocks), &m.mask)) != FSG_OK) return st;
+        if (ctx->filter_counts == nullptr) {
+            if (hipMalloc(&ctx->filter_counts, 2 * sizeof(int64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(ctx, FSG_E_NOMEM, "hipMalloc of filter statistics failed");
+            }
+            FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
+        }
+        m.kept = ctx->filter_counts;
+        // columns examined: every data column once per 64-query tile
+        FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, tiles * n, ctx->stream));
+        {
+            StageTimer t(ctx, "kde_mask");
+            FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));
+        }
+        StageTimer t(ctx, "kde_root");
+        FSG_HIP(ctx, launch_exact_kept(a, m.mask, m.n_blocks, n_items, ctx->num_cus, ctx->stream));
+        return FSG_OK;
+    }
     {
         StageTimer t(ctx, "kde_root");
         FSG_HIP(ctx, launch_kde(a, n_items, ctx->num_cus, ctx->stream));
@@ -242,6 +295,37 @@ static fsg_status group_by_node(fsg_ctx* ctx, const int32_t* node, int64_t ns, i
     FSG_HIP(ctx, launch_node_starts(keys, ns, n_nodes, start, ctx->stream));
     *sorted = vals;
     *starts = start;
+    return FSG_OK;
+}
+
+// Precision-mode arrays of a point set: split BF16 operands, distance bounds
+// from pivots and the pivot order of the points.
+static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
+    const int KB = filter_steps(p->D4);
+    p->KB = KB;
+    const size_t split_bytes = (size_t)(p->n_pad / 16) * KB * 64 * 16;
+    const int64_t n = p->n;
+    uint32_t* label = nullptr;
+    auto fail = [&](const char* what) {
+        (void)hipGetLastError();
+        return set_error(ctx, FSG_E_NOMEM, std::string("hipMalloc of ") + what + " failed");
+    };
+    if (hipMalloc(&p->Xb, split_bytes) != hipSuccess) return fail("split operands");
+    if (hipMalloc(&p->Qb, split_bytes) != hipSuccess) return fail("split operands");
+    if (hipMalloc(&p->dmin, n * sizeof(double)) != hipSuccess) return fail("distance bounds");
+    if (hipMalloc(&p->order, n * sizeof(int32_t)) != hipSuccess) return fail("pivot order");
+    if (hipMalloc(&p->xmax, sizeof(double)) != hipSuccess) return fail("norm bound");
+    p->bytes += 2 * split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double);
+    fsg_status st;
+    if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
+    SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
+    if (st != FSG_OK) return st;
+    StageTimer t(ctx, "prep");
+    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->Qb, ctx->stream));
+    const int32_t P = (int32_t)(n < 256 ? n : 256);
+    FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
+    FSG_HIP(ctx, radix_sort_u32(label, p->order, n, 8, b, ctx->stream));
+    FSG_HIP(ctx, launch_max_norm(p->norm, n, p->xmax, ctx->stream));
     return FSG_OK;
 }
 
@@ -301,6 +385,7 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
         (void)hipEventDestroy(m.second.second);
     }
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->filter_counts) (void)hipFree(ctx->filter_counts);
     if (ctx->host_scratch) (void)hipHostFree(ctx->host_scratch);
     delete ctx;
 }
@@ -316,6 +401,13 @@ fsg_status fsg_ctx_sync(fsg_ctx* ctx) {
 
 uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx) { return ctx ? ctx->held : 0; }
 
+fsg_status fsg_ctx_set_levels_per_pass(fsg_ctx* ctx, int32_t max_levels) {
+    if (!ctx) return FSG_E_INVALID;
+    if (max_levels < 0) return set_error(ctx, FSG_E_INVALID, "max_levels must be >= 0");
+    ctx->max_levels_per_pass = max_levels;
+    return FSG_OK;
+}
+
 fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled) {
     if (!ctx) return FSG_E_INVALID;
     ctx->profiling = enabled != 0;
@@ -330,6 +422,20 @@ fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx) {
         ctx->free_events.push_back(m.second.second);
     }
     ctx->marks.clear();
+    if (ctx->filter_counts != nullptr) FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned) {
+    if (!ctx || !kept || !scanned) return FSG_E_INVALID;
+    *kept = 0;
+    *scanned = 0;
+    if (ctx->filter_counts == nullptr) return FSG_OK;
+    FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, ctx->filter_counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *kept = ctx->host_scratch[0];
+    *scanned = ctx->host_scratch[1];
     return FSG_OK;
 }
 
@@ -357,9 +463,11 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
     if (!X_dev) return set_error(ctx, FSG_E_INVALID, "X_dev is NULL");
     if (n < 1 || n > 2147483647LL) return set_error(ctx, FSG_E_INVALID, "n must be in [1, 2^31-1]");
     if (d < 1 || d > 1024) return set_error(ctx, FSG_E_INVALID, "d must be in [1, 1024]");
-    if (prec != FSG_FP32) return set_error(ctx, FSG_E_INVALID, "unknown precision");
+    if (prec != FSG_FP32 && prec != FSG_BF16_SPLIT) return set_error(ctx, FSG_E_INVALID, "unknown precision");
     const int D4 = feature_steps(d);
     if (D4 < 0) return set_error(ctx, FSG_E_UNSUPPORTED, "d > 128 is not built in this version");
+    if (prec == FSG_BF16_SPLIT && filter_steps(D4) < 0)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "the precision mode is built for d <= 64");
     fsg_points* p = new (std::nothrow) fsg_points();
     if (!p) return set_error(ctx, FSG_E_NOMEM, "host allocation failed");
     p->ctx = ctx;
@@ -389,6 +497,13 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
         return set_error(ctx, FSG_E_DEVICE, std::string("prep: ") + hipGetErrorString(e));
     }
     }
+    if (prec == FSG_BF16_SPLIT) {
+        fsg_status st = prep_precision_mode(ctx, p);
+        if (st != FSG_OK) {
+            fsg_points_destroy(p);
+            return st;
+        }
+    }
     ctx->points.insert(p);
     *out = p;
     return FSG_OK;
@@ -404,6 +519,11 @@ void fsg_points_destroy(fsg_points* p) {
     }
     if (p->Xp) (void)hipFree(p->Xp);
     if (p->norm) (void)hipFree(p->norm);
+    if (p->Xb) (void)hipFree(p->Xb);
+    if (p->Qb) (void)hipFree(p->Qb);
+    if (p->dmin) (void)hipFree(p->dmin);
+    if (p->order) (void)hipFree(p->order);
+    if (p->xmax) (void)hipFree(p->xmax);
     for (auto& kv : p->levels) (void)hipFree(kv.second);
     delete p;
 }
@@ -487,7 +607,13 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
     if (ns > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "n*L must be < 2^31");
     const double s = gamma * 1.442695040888963407359924681001892137;
     fsg_status st;
-    const Plan plan = make_plan(n, L, ctx->budget);
+    const Plan plan = make_plan(n, L, ctx->budget, ctx->max_levels_per_pass);
+    // uniforms of the leaf levels, produced by the last binned pass
+    const int32_t n_uleaf = tree_depth(n) - plan.leaf_level;
+    double* uleaf = nullptr;
+    if (!plan.passes.empty() && n_uleaf > 0) {
+        if ((st = ws(ctx, "smp_uleaf", (size_t)ns * n_uleaf, &uleaf)) != FSG_OK) return st;
+    }
 
     int32_t* node;
     if ((st = ws(ctx, "smp_node", (size_t)ns, &node)) != FSG_OK) return st;
@@ -504,6 +630,10 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
         da.seed = seed;
         da.node = node;
         da.margin = margin_dev;
+        if (p + 1 == plan.passes.size() && uleaf != nullptr) {
+            da.uleaf = uleaf;
+            da.n_uleaf = n_uleaf;
+        }
         if (p == 0) {
             double* M;
             if ((st = ws(ctx, "pass_masses", (size_t)n << D, &M)) != FSG_OK) return st;
@@ -599,6 +729,8 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
         la.n_items = n_items;
         la.nbr = nbr_dev;
         la.margin = margin_dev;
+        la.uleaf = uleaf;
+        la.n_uleaf = n_uleaf;
         FSG_HIP(ctx, launch_leaf(la, max_items, ctx->num_cus, ctx->stream));
         FSG_HIP(ctx, launch_finish_inactive(node, ns, nbr_dev, ctx->stream));
     }

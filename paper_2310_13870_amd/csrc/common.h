@@ -58,8 +58,33 @@ struct KdeArgs {
     const WorkItem* items;
     const int32_t* n_items;  // device-side count
     double s;                // gamma * log2(e)
-    double* out;             // out[e * out_stride + bin]
+    double* out;             // out[row * out_stride + bin]
     int64_t out_stride;
+    const int32_t* out_rows; // entry -> output row (NULL: the entry index)
+};
+
+// Filtered KDE (precision mode): BF16 split operands decide which pairs are
+// recomputed exactly; the rest add 0 (provably below e^-Delta of the row).
+struct MaskArgs {
+    const void* Xb;            // data-side split fragments [n_pad/16][KB][64] x 8 bf16
+    const void* Qb;            // query-side split fragments
+    int32_t KB;                // 32-wide K steps of the split operands
+    const int32_t* q_idx;      // entry -> query point (NULL: the entry itself)
+    int64_t n_entries;
+    int64_t n_query;
+    int64_t n_data;
+    const double* qnorm;       // ||q||^2
+    const double* dmin;        // query point -> upper bound on its smallest squared distance
+    const double* xmax;        // device scalar: max |x| over the data set
+    double margin_z;           // Delta
+    double eps;                // relative error bound of the split cross term
+    double gamma;
+    int64_t n_tiles;           // 64-entry query tiles
+    int64_t n_blocks;          // 16-column data blocks
+    int64_t blocks_per_chunk;
+    int64_t n_chunks;
+    uint16_t* mask;            // [n_tiles][n_blocks]
+    int64_t* kept;             // optional: number of (column, tile) pairs kept
 };
 
 // ---------------------------------------------------------------------------
@@ -84,6 +109,10 @@ struct fsg_ctx {
     bool profiling = false;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> marks;
     std::vector<hipEvent_t> free_events;
+    // cap on the tree levels one binned pass resolves (0: automatic)
+    int max_levels_per_pass = 0;
+    // precision-mode statistics (device counters)
+    int64_t* filter_counts = nullptr;  // [kept, scanned]
     // live point sets; detached (their ctx cleared) when the context is destroyed
     std::set<fsg_points*> points;
 };
@@ -98,6 +127,13 @@ struct fsg_points {
     fsg_precision prec = FSG_FP32;
     double* Xp = nullptr;      // FP64 operand fragments [n_pad/16][D4][64]
     double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
+    // precision mode (FSG_BF16_SPLIT)
+    int32_t KB = 0;            // 32-wide K steps of the split operands
+    void* Xb = nullptr;        // data-side split fragments
+    void* Qb = nullptr;        // query-side split fragments
+    double* dmin = nullptr;    // upper bound on each point's smallest squared distance
+    int32_t* order = nullptr;  // points ordered by nearest pivot
+    double* xmax = nullptr;    // device scalar: max |x|
     // tree level boundaries, computed on demand: level -> int32 [2^level + 1]
     std::map<int, int32_t*> levels;
     size_t bytes = 0;
@@ -140,6 +176,18 @@ hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t s
 
 // KDE over a work list; grid = waves / 4 blocks of 256 threads.
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
+hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);
+hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items, int num_cus,
+                             hipStream_t st);
+int split_steps(int d);
+hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
+                             void* Xb, void* Qb, hipStream_t st);
+hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double* dmin, uint32_t* label, int32_t* ids,
+                         hipStream_t st);
+hipError_t launch_max_norm(const double* norm, int64_t n, double* out, hipStream_t st);
+int filter_steps(int D4);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t st);
 // Work list for segments given by q_ptr (device, int64 [n_seg+1]); every
 // segment has `nbins` bins split into chunks of `bins_per_chunk`.
 hipError_t launch_build_items(const int64_t* q_ptr, int64_t n_seg, int32_t nbins, int32_t bins_per_chunk,
@@ -165,6 +213,10 @@ struct DescArgs {
     int32_t* node;             // sample -> node index at the current level (in/out)
     float* margin;             // sample -> running min margin (in/out), may be NULL
     double* deg;               // root pass: point -> degree, may be NULL
+    // uniforms of the levels after this pass, for the leaf stage (may be NULL):
+    // uleaf[sample * n_uleaf + k] = u(level = start_level + D + k)
+    double* uleaf;
+    int32_t n_uleaf;
 };
 hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st);
 
@@ -183,6 +235,8 @@ struct LeafArgs {
     const int32_t* n_items;
     int32_t* nbr;
     float* margin;
+    const double* uleaf;            // precomputed uniforms of the leaf levels (NULL: computed here)
+    int32_t n_uleaf;
 };
 hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st);
 

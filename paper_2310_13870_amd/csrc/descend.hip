@@ -12,64 +12,168 @@
 
 namespace fsg {
 
-// One wave per entry; dynamic LDS holds the sum tree (2^(D+1) doubles).
-__global__ __launch_bounds__(64) void descend_bins_kernel(DescArgs a) {
-    extern __shared__ double tree[];
-    const int lane = threadIdx.x;
+// Root pass: one block of 256 threads per point.  LDS holds the sum tree
+// (2^(D+1) doubles) and the Philox blocks of up to 64 of the point's samples.
+constexpr int kDescThreads = 256;
+constexpr int kDescChunk = 64;
+
+__global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a, int32_t n_groups) {
+    // LDS: the internal nodes of the sum tree, tree[k] for k in [1, 2^D)
+    // (children 2k, 2k+1; the bins are the leaves 2^D + b and stay in global
+    // memory), then the Philox blocks of up to 64 samples.
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
     const int32_t nb = 1 << a.D;
+    double* tree = smem;
+    uint64_t* words = (uint64_t*)(smem + nb);  // [kDescChunk][n_groups][4]
+    const int32_t g0 = a.start_level >> 2;
+    // bins summed per thread in registers before the LDS levels
+    const int32_t per = (nb >= 8 * kDescThreads) ? 8 : ((nb >= 2 * kDescThreads) ? nb / kDescThreads : 1);
     for (int64_t e = blockIdx.x; e < a.n_entries; e += gridDim.x) {
         const double* M = a.M + e * nb;
-        for (int32_t b = lane; b < nb; b += 64) tree[nb + b] = M[b];
+        int32_t top;  // the LDS levels built below start at nodes [top, 2 top)
+        if (per >= 2) {
+            // thread t owns bins [per t, per t + per): its local subtree
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = (k < per) ? M[tid * per + k] : 0.0;
+            int32_t cnt = per, lvl_nodes = nb;  // nodes on the current level
+            while (cnt > 1) {
+                cnt >>= 1;
+                lvl_nodes >>= 1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < cnt) v[k] = v[2 * k] + v[2 * k + 1];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < cnt) tree[lvl_nodes + tid * cnt + k] = v[k];
+            }
+            top = lvl_nodes;  // = nb / per = number of threads that own bins
+        } else {
+            // fewer bins than 2 per thread: the first internal level from global
+            for (int32_t k = tid; k < nb / 2; k += kDescThreads) tree[nb / 2 + k] = M[2 * k] + M[2 * k + 1];
+            top = nb / 2;
+        }
         __syncthreads();
-        for (int32_t t = a.D - 1; t >= 0; --t) {
-            const int32_t cnt = 1 << t;
-            for (int32_t k = lane; k < cnt; k += 64) tree[cnt + k] = tree[2 * (cnt + k)] + tree[2 * (cnt + k) + 1];
+        for (int32_t cnt = top >> 1; cnt >= 1; cnt >>= 1) {
+            for (int32_t k = tid; k < cnt; k += kDescThreads) tree[cnt + k] = tree[2 * (cnt + k)] + tree[2 * (cnt + k) + 1];
             __syncthreads();
         }
-        const double root = tree[1];
-        int32_t first_sample, n_samp;
-        if (a.entry_sample == nullptr) {
-            first_sample = (int32_t)(e * a.L);
-            n_samp = a.L;
-            if (a.deg != nullptr && lane == 0) a.deg[e] = root;
-        } else {
-            first_sample = -1;
-            n_samp = 1;
-        }
-        for (int32_t k = lane; k < n_samp; k += 64) {
-            const int32_t smp = (a.entry_sample == nullptr) ? first_sample + k : a.entry_sample[e];
-            const int32_t i = smp / a.L, l = smp - i * a.L;
-            int32_t v = a.node[smp];
-            if (v < 0) continue;
-            if (!(root > 0.0)) {
-                a.node[smp] = -1;  // isolated point: no neighbour
-                continue;
+        const double root = (nb >= 2) ? tree[1] : M[0];
+        if (a.deg != nullptr && tid == 0) a.deg[e] = root;
+        for (int32_t c0 = 0; c0 < a.L; c0 += kDescChunk) {
+            const int32_t cn = min(kDescChunk, a.L - c0);
+            // Philox blocks of every (sample, level group) of this chunk, spread over the block
+            for (int32_t c = tid; c < cn * n_groups; c += kDescThreads) {
+                const int32_t k = c / n_groups, g = g0 + (c - k * n_groups);
+                const PhiloxWords w = philox4x64_10((uint64_t)e, (uint64_t)(c0 + k), (uint64_t)g, 0, a.seed, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) words[c * 4 + q] = w.w[q];
             }
-            float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
-            SampleUniforms uni;
-            uni.init(a.seed, (uint64_t)i, (uint64_t)l);
-            int32_t m = 0;
-            for (int32_t t = 0; t < a.D; ++t) {
-                const double u = uni.at(a.start_level + t);
-                const int32_t c = (1 << (t + 1)) + 2 * m;
-                double margin;
-                const bool left = choose_left(u, tree[c], tree[c + 1], &margin);
-                mg = fminf(mg, (float)margin);
-                m = 2 * m + (left ? 0 : 1);
+            __syncthreads();
+            if (tid < cn) {
+                const int32_t l = c0 + tid;
+                const int64_t smp = e * a.L + l;
+                const uint64_t* wk = words + (int64_t)tid * n_groups * 4;
+                if (!(root > 0.0)) {
+                    a.node[smp] = -1;  // isolated point: no neighbour
+                } else {
+                    float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+                    int32_t m = 0;
+                    for (int32_t t = 0; t < a.D; ++t) {
+                        const int32_t level = a.start_level + t;
+                        const double u = word_to_uniform(wk[((level >> 2) - g0) * 4 + (level & 3)]);
+                        const int32_t c = (1 << (t + 1)) + 2 * m;
+                        double mL, mR;
+                        if (t + 1 < a.D) {
+                            mL = tree[c];
+                            mR = tree[c + 1];
+                        } else {
+                            mL = M[2 * m];  // the children are bins
+                            mR = M[2 * m + 1];
+                        }
+                        double margin;
+                        const bool left = choose_left(u, mL, mR, &margin);
+                        mg = fminf(mg, (float)margin);
+                        m = 2 * m + (left ? 0 : 1);
+                    }
+                    a.node[smp] = m;
+                    if (a.margin != nullptr) a.margin[smp] = mg;
+                    if (a.uleaf != nullptr) {
+                        for (int32_t q = 0; q < a.n_uleaf; ++q) {
+                            const int32_t level = a.start_level + a.D + q;
+                            a.uleaf[smp * a.n_uleaf + q] = word_to_uniform(wk[((level >> 2) - g0) * 4 + (level & 3)]);
+                        }
+                    }
+                }
             }
-            a.node[smp] = (v << a.D) + m;
-            if (a.margin != nullptr) a.margin[smp] = mg;
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
+// Later passes: one thread per entry (a single sample); the 2^D bin masses are
+// held in registers and each level's child masses are summed directly.
+template <int D>
+__global__ __launch_bounds__(256) void descend_entries_kernel(DescArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.n_entries) return;
+    const int32_t smp = a.entry_sample[e];
+    const int32_t v = a.node[smp];
+    if (v < 0) return;
+    constexpr int NB = 1 << D;
+    double bins[NB];
+    const double* M = a.M + e * NB;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bins[b] = M[b];
+    const int32_t i = smp / a.L, l = smp - i * a.L;
+    SampleUniforms uni;
+    uni.init(a.seed, (uint64_t)i, (uint64_t)l);
+    float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+    int32_t m = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int w = NB >> (t + 1);  // bins per child
+        const int lo = 2 * m * w;
+        double mL = 0.0, mR = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            mL += (b >= lo && b < lo + w) ? bins[b] : 0.0;
+            mR += (b >= lo + w && b < lo + 2 * w) ? bins[b] : 0.0;
+        }
+        double margin;
+        const bool left = choose_left(uni.at(a.start_level + t), mL, mR, &margin);
+        mg = fminf(mg, (float)margin);
+        m = 2 * m + (left ? 0 : 1);
+    }
+    a.node[smp] = (v << D) + m;
+    if (a.margin != nullptr) a.margin[smp] = mg;
+    if (a.uleaf != nullptr)
+        for (int32_t q = 0; q < a.n_uleaf; ++q) a.uleaf[(int64_t)smp * a.n_uleaf + q] = uni.at(a.start_level + D + q);
+}
+
 hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
-    int64_t blocks = a.n_entries;
-    if (blocks > 65536) blocks = 65536;
-    if (blocks < 1) return hipSuccess;
-    const size_t lds = sizeof(double) * ((size_t)2 << a.D);
-    descend_bins_kernel<<<(unsigned)blocks, 64, lds, st>>>(a);
+    if (a.n_entries < 1) return hipSuccess;
+    if (a.entry_sample == nullptr) {
+        if (a.D < 1 || a.D > 11) return hipErrorInvalidValue;  // the tree build assumes 2 <= 2^D <= 8 * 256
+        const int32_t last_level = a.start_level + a.D - 1 + (a.uleaf != nullptr ? a.n_uleaf : 0);
+        const int32_t n_groups = (last_level >> 2) - (a.start_level >> 2) + 1;
+        const size_t lds = sizeof(double) * ((size_t)1 << a.D) + sizeof(uint64_t) * 4 * kDescChunk * n_groups;
+        int64_t blocks = a.n_entries;
+        if (blocks > (1 << 20)) blocks = 1 << 20;
+        descend_root_kernel<<<(unsigned)blocks, kDescThreads, lds, st>>>(a, n_groups);
+        return hipGetLastError();
+    }
+    const unsigned blocks = (unsigned)((a.n_entries + 255) / 256);
+    switch (a.D) {
+        case 1: descend_entries_kernel<1><<<blocks, 256, 0, st>>>(a); break;
+        case 2: descend_entries_kernel<2><<<blocks, 256, 0, st>>>(a); break;
+        case 3: descend_entries_kernel<3><<<blocks, 256, 0, st>>>(a); break;
+        case 4: descend_entries_kernel<4><<<blocks, 256, 0, st>>>(a); break;
+        case 5: descend_entries_kernel<5><<<blocks, 256, 0, st>>>(a); break;
+        case 6: descend_entries_kernel<6><<<blocks, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -80,6 +184,7 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
 template <int DMAX>
 __global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
     __shared__ double row[kLeafMax * 64];  // row[j * 64 + lane]: kernel of sample `lane` to node point j
+    __shared__ double xs[DMAX > 0 ? (kLeafMax + 3) * DMAX : 1];  // the node's points, FP64 (+3 rows of slack)
     const int lane = threadIdx.x;
     const int32_t n_items = *a.n_items;
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -88,33 +193,55 @@ __global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
         const int32_t lo = a.bounds[v];
         const int32_t hi = min(a.bounds[v + 1], lo + kLeafMax);  // the planner keeps nodes within kLeafMax
         const int32_t pos = p0 + lane;
-        const bool active = pos < p1 && lane < 64;
+        const bool active = pos < p1;
         const int32_t smp = active ? a.sorted_samples[pos] : a.sorted_samples[p0];
         const int32_t i = smp / a.L, l = smp - i * a.L;
         const float* xi = a.X + (int64_t)i * a.d;
-        double q[DMAX > 0 ? DMAX : 1];
         if (DMAX > 0) {
+            // stage the node's points (contiguous rows lo..hi-1) in LDS
+            const int32_t cnt = (hi - lo) * a.d;
+            const float* src = a.X + (int64_t)lo * a.d;
+            for (int32_t k = lane; k < cnt; k += 64) {
+                const int32_t r = k / a.d, t = k - r * a.d;
+                xs[r * DMAX + t] = (double)src[k];
+            }
+            __syncthreads();
+            double q[DMAX > 0 ? DMAX : 1];
 #pragma unroll
             for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? (double)xi[t] : 0.0;
-        }
-        for (int32_t j = lo; j < hi; ++j) {
-            const float* xj = a.X + (int64_t)j * a.d;
-            double D = 0.0;
-            if (DMAX > 0) {
+            // four node points at a time: four independent FP64 chains
+            for (int32_t j0 = lo; j0 < hi; j0 += 4) {
+                double D[4] = {0.0, 0.0, 0.0, 0.0};
+                const double* xj = xs + (j0 - lo) * DMAX;  // rows past hi read stale LDS, never stored
 #pragma unroll
                 for (int t = 0; t < DMAX; ++t) {
                     if (t < a.d) {
-                        const double df = q[t] - (double)xj[t];
-                        D = __builtin_fma(df, df, D);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double df = q[t] - xj[u * DMAX + t];
+                            D[u] = __builtin_fma(df, df, D[u]);
+                        }
                     }
                 }
-            } else {
+                double k[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) k[u] = exp2_fp64(-a.s * D[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t j = j0 + u;
+                    if (j < hi) row[(j - lo) * 64 + lane] = (j == i) ? 0.0 : k[u];
+                }
+            }
+        } else {
+            for (int32_t j = lo; j < hi; ++j) {
+                const float* xj = a.X + (int64_t)j * a.d;
+                double D = 0.0;
                 for (int32_t t = 0; t < a.d; ++t) {
                     const double df = (double)xi[t] - (double)xj[t];
                     D = __builtin_fma(df, df, D);
                 }
+                row[(j - lo) * 64 + lane] = (j == i) ? 0.0 : exp2_fp64(-a.s * D);
             }
-            row[(j - lo) * 64 + lane] = (j == i) ? 0.0 : exp2_fp64(-a.s * D);
         }
         __syncthreads();
         if (active) {
@@ -127,6 +254,7 @@ __global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
             } else {
                 SampleUniforms uni;
                 uni.init(a.seed, (uint64_t)i, (uint64_t)l);
+                const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
                 float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
                 int32_t na = lo, nbd = hi, level = a.level;
                 while (nbd - na > 1) {
@@ -134,8 +262,9 @@ __global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
                     double mL = 0.0, mR = 0.0;
                     for (int32_t j = na; j < mid; ++j) mL += row[(j - lo) * 64 + lane];
                     for (int32_t j = mid; j < nbd; ++j) mR += row[(j - lo) * 64 + lane];
+                    const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
                     double margin;
-                    const bool left = choose_left(uni.at(level), mL, mR, &margin);
+                    const bool left = choose_left(u, mL, mR, &margin);
                     mg = fminf(mg, (float)margin);
                     if (left) nbd = mid; else na = mid;
                     ++level;
@@ -148,15 +277,113 @@ __global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
     }
 }
 
+// Leaf stage for d <= 32: each lane keeps its sample's (<= 64) kernel values
+// in registers; the child masses of every level are summed with static
+// predicates, so the descent has no dependent memory chains.
+template <int DMAX>
+__global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
+    __shared__ double xs[(kLeafMax + 3) * DMAX];  // the node's points, FP64 (+3 rows of slack)
+    const int lane = threadIdx.x;
+    const int32_t n_items = *a.n_items;
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int32_t v = a.items[2 * it], p0 = a.items[2 * it + 1];
+        const int32_t p1 = a.node_start[v + 1];
+        const int32_t lo = a.bounds[v];
+        const int32_t hi = min(a.bounds[v + 1], lo + kLeafMax);  // the planner keeps nodes within kLeafMax
+        const int32_t cnt = hi - lo;
+        const int32_t pos = p0 + lane;
+        const bool active = pos < p1;
+        const int32_t smp = active ? a.sorted_samples[pos] : a.sorted_samples[p0];
+        const int32_t i = smp / a.L, l = smp - i * a.L;
+        const float* xi = a.X + (int64_t)i * a.d;
+        {
+            const int32_t total = cnt * a.d;
+            const float* src = a.X + (int64_t)lo * a.d;
+            for (int32_t k = lane; k < total; k += 64) {
+                const int32_t r = k / a.d, t = k - r * a.d;
+                xs[r * DMAX + t] = (double)src[k];
+            }
+        }
+        __syncthreads();
+        double q[DMAX];
+#pragma unroll
+        for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? (double)xi[t] : 0.0;
+        const int32_t self = i - lo;  // the sample's own point, if it lies in the node
+        double kv[kLeafMax];
+#pragma unroll
+        for (int j0 = 0; j0 < kLeafMax; j0 += 4) {
+            if (j0 < cnt) {
+                double D[4] = {0.0, 0.0, 0.0, 0.0};
+                const double* xj = xs + j0 * DMAX;
+#pragma unroll
+                for (int t = 0; t < DMAX; ++t) {
+                    if (t < a.d) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double df = q[t] - xj[u * DMAX + t];
+                            D[u] = __builtin_fma(df, df, D[u]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double k = exp2_fp64(-a.s * D[u]);
+                    kv[j0 + u] = (j0 + u < cnt && j0 + u != self) ? k : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) kv[j0 + u] = 0.0;
+            }
+        }
+        __syncthreads();  // xs is reused by the next item
+        if (active) {
+            double total = 0.0;
+#pragma unroll
+            for (int j = 0; j < kLeafMax; ++j) total += kv[j];
+            if (!(total > 0.0)) {
+                // only reachable at the root (a sample never enters a node of
+                // zero mass): an isolated point has no neighbour
+                a.nbr[smp] = -1;
+            } else {
+                SampleUniforms uni;
+                uni.init(a.seed, (uint64_t)i, (uint64_t)l);
+                const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
+                float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+                int32_t na = 0, nbd = cnt, level = a.level;
+                while (nbd - na > 1) {
+                    const int32_t mid = tree_split(na, nbd);
+                    double mL = 0.0, mR = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kLeafMax; ++j) {
+                        const bool in_node = (j >= na) && (j < nbd);
+                        const bool left = j < mid;
+                        mL += (in_node && left) ? kv[j] : 0.0;
+                        mR += (in_node && !left) ? kv[j] : 0.0;
+                    }
+                    const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
+                    double margin;
+                    const bool go_left = choose_left(u, mL, mR, &margin);
+                    mg = fminf(mg, (float)margin);
+                    if (go_left) nbd = mid; else na = mid;
+                    ++level;
+                }
+                a.nbr[smp] = lo + na;
+                if (a.margin != nullptr) a.margin[smp] = mg;
+            }
+        }
+    }
+}
+
 hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
     int64_t blocks = max_items;
-    const int64_t cap = (int64_t)num_cus * 16;
+    const int64_t cap = (int64_t)num_cus * 32;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    if (a.d <= 4) leaf_kernel<4><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 8) leaf_kernel<8><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 16) leaf_kernel<16><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 32) leaf_kernel<32><<<(unsigned)blocks, 64, 0, st>>>(a);
+    if (a.d <= 2) leaf_reg_kernel<2><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 4) leaf_reg_kernel<4><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 8) leaf_reg_kernel<8><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 16) leaf_reg_kernel<16><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 32) leaf_reg_kernel<32><<<(unsigned)blocks, 64, 0, st>>>(a);
     else if (a.d <= 64) leaf_kernel<64><<<(unsigned)blocks, 64, 0, st>>>(a);
     else leaf_kernel<0><<<(unsigned)blocks, 64, 0, st>>>(a);
     return hipGetLastError();

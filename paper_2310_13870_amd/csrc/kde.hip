@@ -14,6 +14,7 @@
 // are bit-reproducible.
 #include "common.h"
 #include "device.h"
+#include "kde_epilogue.h"
 
 namespace fsg {
 
@@ -35,7 +36,6 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
         double qf[RQ][D4];
         double hq[RQ];
         int32_t selfv[RQ], smin[RQ], smax[RQ];
-        bool rowok[RQ];
 #pragma unroll
         for (int qb = 0; qb < RQ; ++qb) {
             const int32_t t = 16 * qb + r;
@@ -46,7 +46,6 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             int32_t sf = -1;
             if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
             selfv[qb] = sf;
-            rowok[qb] = ok;
             hq[qb] = -a.s * a.qnorm[p];
             const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
 #pragma unroll
@@ -61,26 +60,11 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             smax[qb] = mx;
         }
 
-        const int32_t b0 = w.b0, b1 = w.b1;
         // never read outside the data set, whatever the boundaries say
-        const int32_t col_end = min(max(bnd[b1], 0), (int32_t)a.n_data);
-        const int32_t col_begin = min(max(bnd[b0], 0), col_end);
-        int32_t cur = b0 - 1;  // bin being accumulated (b0-1: before the first bin)
-        int32_t nxt = col_begin;
-        double acc[RQ];
-#pragma unroll
-        for (int qb = 0; qb < RQ; ++qb) acc[qb] = 0.0;
-
-        auto flush = [&](int32_t bin) {
-#pragma unroll
-            for (int qb = 0; qb < RQ; ++qb) {
-                double v = acc[qb];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
-                if (lane < 16 && rowok[qb]) a.out[(w.e0 + 16 * qb + lane) * a.out_stride + bin] = v;
-                acc[qb] = 0.0;
-            }
-        };
+        const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
+        const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
+        BinAccumulator<RQ> bins;
+        bins.init(bnd, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
 
         for (int32_t c0 = col_begin & ~15; c0 < col_end; c0 += 16) {
             double xf[D4];
@@ -94,51 +78,18 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
                 jj[i] = c0 + grp + 4 * i;
                 hx[i] = -a.s * a.xnorm[jj[i]];
             }
-            double kv[RQ][4];
+            double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
-                double4_t c = {0.0, 0.0, 0.0, 0.0};
+                c[qb] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int kk = 0; kk < D4; ++kk) c = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c, 0, 0, 0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) kv[qb][i] = exp2_fp64(__builtin_fma(two_s, c[i], hq[qb] + hx[i]));
-                if (smax[qb] >= c0 && smin[qb] < c0 + 16) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (jj[i] == selfv[qb]) kv[qb][i] = 0.0;
-                }
+                for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
             }
-            // bin boundaries inside this block (uniform across the wave)
-            while (nxt < c0 + 16) {
-                if (cur >= b0) {
-#pragma unroll
-                    for (int qb = 0; qb < RQ; ++qb) {
-                        double part = 0.0;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            if (jj[i] < nxt) part += kv[qb][i];
-                        acc[qb] += part;
-                    }
-                    flush(cur);
-                }
-#pragma unroll
-                for (int qb = 0; qb < RQ; ++qb)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (jj[i] < nxt) kv[qb][i] = 0.0;
-                ++cur;
-                nxt = (cur < b1) ? bnd[cur + 1] : INT32_MAX;
-            }
-            if (cur >= b0 && cur < b1) {
-#pragma unroll
-                for (int qb = 0; qb < RQ; ++qb) acc[qb] += (kv[qb][0] + kv[qb][1]) + (kv[qb][2] + kv[qb][3]);
-            }
+            double kv[RQ][4];
+            exact_values<RQ>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, kv);
+            bins.add(kv, jj, c0 + 15);
         }
-        // the bin still open and any empty bins after the last column
-        while (cur < b1) {
-            if (cur >= b0) flush(cur);
-            ++cur;
-        }
+        bins.finish();
     }
 }
 

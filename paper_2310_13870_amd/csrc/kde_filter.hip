@@ -1,0 +1,451 @@
+// Filtered segmented KDE on the BF16 matrix cores (precision mode).
+//
+// Every pair first gets an approximate cross term from BF16 hi/lo split
+// operands (hi = bf16(x), lo = bf16(x - hi); one contraction over K = 3d + 2
+// gives hi.hi + hi.lo + lo.hi plus an augmented term -|x|^2/2), accumulated in
+// FP32 by v_mfma_f32_16x16x32_bf16.  A pair can change a row's masses only if
+// its exponent z = gamma |q-x|^2 is within Delta of the row's smallest one
+// (a term e^-Delta times the largest term of the row is negligible); with a
+// guaranteed bound E on the error of the approximate cross term, the test
+//     c~ - |x|^2/2 >= |q|^2/2 - (T_q/(2 gamma)) - E,   T_q = gamma dmin_q + Delta
+// keeps every such pair (dmin_q is an upper bound on the row's smallest
+// squared distance).  Stage 1 writes, per 64-query tile and 16-column block,
+// the mask of columns kept for any query of the tile; stage 2 queues the kept
+// columns, gathers every 16 of them into one block whose cross terms are
+// recomputed on the FP64 matrix cores, and sends them through the same FP64
+// epilogue and bin accumulation as the plain kernel.  Pairs not kept add 0:
+// their total is below (n-1) e^-Delta of the row's mass.
+#include "common.h"
+#include "device.h"
+#include "kde_epilogue.h"
+
+namespace fsg {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Stage 1: keep masks.  For query tile t (64 entries) and data block b (16
+// columns) mask[t * n_blocks + b] has bit c set when column 16b + c is kept
+// for at least one query of the tile.  Work item = (tile, run of blocks); the
+// next block's operands are loaded while the current one is processed.
+// ---------------------------------------------------------------------------
+// occupancy targets that fit without spilling
+template <int KB>
+constexpr int mask_waves() { return KB <= 4 ? 3 : 2; }
+template <int D4>
+constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
+
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<KB>()))) void kde_keep_mask_kernel(MaskArgs m) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    const int grp = lane >> 4;
+    const int r = lane & 15;
+    const double xmax = *m.xmax;
+    const double half_margin = m.margin_z / (2.0 * m.gamma);
+    const int64_t n_items = m.n_tiles * m.n_chunks;
+    int64_t kept = 0;
+    for (int64_t it = wave; it < n_items; it += n_waves) {
+        const int64_t chunk = it / m.n_tiles, tile = it - chunk * m.n_tiles;
+        const int64_t e0 = tile * kTileQ;
+        const int32_t ne = (int32_t)min((int64_t)kTileQ, m.n_entries - e0);
+        bf16x8_t qb16[4][KB];
+        float theta[4];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+            const int32_t t = 16 * qb + r;
+            const bool ok = t < ne;
+            int32_t p = m.q_idx ? m.q_idx[e0 + (ok ? t : 0)] : (int32_t)(e0 + (ok ? t : 0));
+            p = min(max(p, 0), (int32_t)(m.n_query - 1));
+            const bf16x8_t* bsrc = (const bf16x8_t*)m.Qb + (int64_t)(p >> 4) * KB * 64 + grp * 16 + (p & 15);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) qb16[qb][kb] = bsrc[kb * 64];
+            // keep-threshold on c~ - |x|^2/2, rounded down to FP32
+            const double nq = m.qnorm[p];
+            const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
+            const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - half_margin - err;
+            float thf = (float)th;
+            if ((double)thf > th) {  // step one FP32 ulp down
+                int32_t bits = __float_as_int(thf);
+                bits = (thf > 0.0f) ? bits - 1 : ((thf < 0.0f) ? bits + 1 : (int32_t)0x80000001);
+                thf = __int_as_float(bits);
+            }
+            theta[qb] = ok ? thf : __builtin_inff();
+        }
+        const int64_t bb = chunk * m.blocks_per_chunk;
+        const int64_t be = min(m.n_blocks, bb + m.blocks_per_chunk);
+        uint16_t* mrow = m.mask + tile * m.n_blocks;
+        bf16x8_t xb[KB], xn[KB];
+        const bf16x8_t* X16 = (const bf16x8_t*)m.Xb;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(bb * KB + kb) * 64 + lane];
+        uint32_t pending = 0;  // lane (b mod 64) keeps the mask of block b until 64 are ready
+        for (int64_t b = bb; b < be; ++b) {
+            if (b + 1 < be) {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) xn[kb] = X16[((b + 1) * KB + kb) * 64 + lane];
+            }
+            uint64_t mk[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+                float4_t cc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[kb], qb16[qb][kb], cc, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) mk[i] |= __ballot(cc[i] >= theta[qb]);
+            }
+            // column 4g + i of the block is kept if any query keeps it
+            uint32_t keep = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    if ((mk[i] >> (16 * g)) & 0xFFFFull) keep |= 1u << (4 * g + i);
+            if (16 * (b + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * b)) - 1u;
+            kept += __popc(keep);
+            if ((b & 63) == lane) pending = keep;
+            if ((b & 63) == 63 || b + 1 == be) {
+                const int64_t base = b & ~(int64_t)63;
+                if (base + lane >= bb && base + lane <= b) mrow[base + lane] = (uint16_t)pending;
+            }
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) xb[kb] = xn[kb];
+        }
+    }
+    if (m.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m.kept, (unsigned long long)kept);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: exact recompute of the kept columns.  Work item = (query tile,
+// run of bins); kept columns of its blocks are queued in order and every 16 of
+// them form one gathered block for the FP64 matrix cores and the binned
+// epilogue.
+// ---------------------------------------------------------------------------
+template <int D4, int RQ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(KdeArgs a, const uint16_t* __restrict__ mask,
+                                                             int64_t n_blocks) {
+    __shared__ int32_t queue_all[4][40];
+    int32_t* queue = queue_all[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    const int32_t n_items = *a.n_items;
+    const double two_s = 2.0 * a.s;
+    const int grp = lane >> 4;
+    const int r = lane & 15;
+
+    for (int64_t it = wave; it < n_items; it += n_waves) {
+        const WorkItem w = a.items[it];
+        const SegDesc sg = a.segs[w.seg];
+        const int32_t* bnd = a.bounds + sg.bound_off;
+        double qf[RQ][D4];
+        double hq[RQ];
+        int32_t selfv[RQ], smin[RQ], smax[RQ];
+#pragma unroll
+        for (int qb = 0; qb < RQ; ++qb) {
+            const int32_t t = 16 * qb + r;
+            const bool ok = t < w.ne;
+            const int64_t e = w.e0 + (ok ? t : 0);
+            int32_t p = a.q_idx ? a.q_idx[e] : (int32_t)e;
+            p = min(max(p, 0), (int32_t)(a.n_query - 1));
+            int32_t sf = -1;
+            if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
+            selfv[qb] = sf;
+            hq[qb] = -a.s * a.qnorm[p];
+            const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
+#pragma unroll
+            for (int kk = 0; kk < D4; ++kk) qf[qb][kk] = src[kk * 64];
+            int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                mn = min(mn, __shfl_xor(mn, off));
+                mx = max(mx, __shfl_xor(mx, off));
+            }
+            smin[qb] = mn;
+            smax[qb] = mx;
+        }
+        const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
+        const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
+        BinAccumulator<RQ> bins;
+        bins.init(bnd, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
+        const uint16_t* mrow = mask + (w.e0 / kTileQ) * n_blocks;
+        int32_t qn = 0;
+
+        auto exact_block = [&](int32_t cnt) {
+            const int32_t gl = queue[(r < cnt) ? r : 0];
+            double xf[D4];
+            const double* xs = a.Xp + (int64_t)(gl >> 4) * D4 * 64 + grp * 16 + (gl & 15);
+#pragma unroll
+            for (int kk = 0; kk < D4; ++kk) xf[kk] = xs[kk * 64];
+            int32_t jj[4];
+            double hx[4];
+            const int32_t first = queue[0];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t idx = grp + 4 * i;
+                jj[i] = (idx < cnt) ? queue[idx] : INT32_MAX;
+                hx[i] = -a.s * a.xnorm[(idx < cnt) ? jj[i] : first];
+            }
+            const int32_t last = queue[cnt - 1];
+            double4_t c[RQ];
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb) {
+                c[qb] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
+            }
+            double kv[RQ][4];
+            exact_values<RQ>(c, hq, hx, two_s, jj, selfv, smin, smax, first, last, kv);
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (jj[i] == INT32_MAX) kv[qb][i] = 0.0;
+            bins.add(kv, jj, last);
+        };
+
+        const int64_t blk0 = col_begin >> 4, blk1 = (col_end + 15) >> 4;
+        for (int64_t base = blk0; base < blk1; base += 64) {
+            // the masks of up to 64 blocks, one per lane
+            const int64_t myb = base + lane;
+            const uint32_t mine = (myb < blk1) ? (uint32_t)mrow[myb] : 0u;
+            const int64_t nb = min((int64_t)64, blk1 - base);
+            for (int64_t k = 0; k < nb; ++k) {
+                uint32_t keep = (uint32_t)__shfl(mine, (int)k);
+                const int32_t c0 = (int32_t)((base + k) << 4);
+                if (c0 < col_begin) keep &= ~((1u << (col_begin - c0)) - 1u);
+                if (c0 + 16 > col_end) keep &= (1u << (col_end - c0)) - 1u;
+                if (keep == 0) continue;
+                if (lane < 16 && ((keep >> lane) & 1u)) queue[qn + __popc(keep & ((1u << lane) - 1u))] = c0 + lane;
+                __builtin_amdgcn_wave_barrier();
+                qn += __popc(keep);
+                if (qn >= 16) {
+                    exact_block(16);
+                    const int32_t rest = qn - 16;
+                    const int32_t v = (lane < rest) ? queue[16 + lane] : 0;
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < rest) queue[lane] = v;
+                    __builtin_amdgcn_wave_barrier();
+                    qn = rest;
+                }
+            }
+        }
+        if (qn > 0) exact_block(qn);
+        bins.finish();
+    }
+}
+
+template <int KB>
+static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) {
+    const int64_t n_items = m.n_tiles * m.n_chunks;
+    int64_t waves = (int64_t)num_cus * 4 * mask_waves<KB>();
+    if (n_items < waves) waves = n_items;
+    if (waves < 1) waves = 1;
+    kde_keep_mask_kernel<KB><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    return hipGetLastError();
+}
+
+hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
+    switch (m.KB) {
+        case 1: return launch_mask_t<1>(m, num_cus, st);
+        case 2: return launch_mask_t<2>(m, num_cus, st);
+        case 4: return launch_mask_t<4>(m, num_cus, st);
+        case 7: return launch_mask_t<7>(m, num_cus, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D4>
+static hipError_t launch_exact_t(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
+                                 int num_cus, hipStream_t st) {
+    int64_t waves = (int64_t)num_cus * 8;
+    if (max_items < waves) waves = max_items;
+    if (waves < 1) waves = 1;
+    kde_exact_kept_kernel<D4, 4><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, mask, n_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items, int num_cus,
+                             hipStream_t st) {
+    switch (a.D4) {
+        case 1: return launch_exact_t<1>(a, mask, n_blocks, max_items, num_cus, st);
+        case 2: return launch_exact_t<2>(a, mask, n_blocks, max_items, num_cus, st);
+        case 4: return launch_exact_t<4>(a, mask, n_blocks, max_items, num_cus, st);
+        case 8: return launch_exact_t<8>(a, mask, n_blocks, max_items, num_cus, st);
+        case 16: return launch_exact_t<16>(a, mask, n_blocks, max_items, num_cus, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int split_steps(int d) { return (3 * d + 2 + 31) / 32; }
+
+// K steps the filter kernel is built for, per feature-step class (the split
+// operands of smaller d are zero-padded up to it).
+int filter_steps(int D4) {
+    switch (D4) {
+        case 1: return 1;
+        case 2: return 1;
+        case 4: return 2;
+        case 8: return 4;
+        case 16: return 7;
+        default: return -1;
+    }
+}
+
+__global__ void fill_i64_kernel(int64_t* p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+    fill_i64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void add_i64_kernel(int64_t* p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
+}
+
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t st) {
+    add_i64_kernel<<<1, 64, 0, st>>>(p, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Point-set preparation for the filter.
+// ---------------------------------------------------------------------------
+// Split fragments in the operand layout of v_mfma_f32_16x16x32_bf16: lane l
+// holds 8 consecutive K entries 8(l/16).. of row 16b + l%16.  Data rows are
+// [hi(x), lo(x), hi(x), hi(a), lo(a), 0...] with a = -|x|^2/2, query rows
+// [hi(q), hi(q), lo(q), 1, 1, 0...]; their contraction is hi.hi + hi.lo +
+// lo.hi - |x|^2/2.
+__global__ void prep_split_kernel(const float* __restrict__ X, const double* __restrict__ norm, int64_t n, int32_t d,
+                                  int32_t KB, int64_t total, bf16x8_t* __restrict__ Xb, bf16x8_t* __restrict__ Qb) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t per_blk = (int64_t)KB * 64;
+    const int64_t blk = idx / per_blk;
+    const int32_t rem = (int32_t)(idx - blk * per_blk);
+    const int32_t kb = rem >> 6, lane = rem & 63;
+    const int64_t row = blk * 16 + (lane & 15);
+    bf16x8_t dv, qv;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int32_t k = kb * 32 + (lane >> 4) * 8 + t;
+        float xd = 0.0f, xq = 0.0f;
+        __bf16 bd = (__bf16)0.0f, bq = (__bf16)0.0f;
+        if (row < n) {
+            if (k < 3 * d) {
+                const int32_t f = k % d;
+                const float x = X[row * d + f];
+                const __bf16 hi = (__bf16)x;
+                const __bf16 lo = (__bf16)(x - (float)hi);
+                const int32_t part = k / d;  // 0, 1, 2
+                bd = (part == 1) ? lo : hi;
+                bq = (part == 2) ? lo : hi;
+            } else if (k == 3 * d || k == 3 * d + 1) {
+                const double av = -0.5 * norm[row];
+                const __bf16 ahi = (__bf16)(float)av;
+                const __bf16 alo = (__bf16)(float)(av - (double)(float)ahi);
+                bd = (k == 3 * d) ? ahi : alo;
+                bq = (__bf16)1.0f;
+            }
+        }
+        (void)xd;
+        (void)xq;
+        dv[t] = bd;
+        qv[t] = bq;
+    }
+    Xb[idx] = dv;
+    Qb[idx] = qv;
+}
+
+// dmin[i] = an upper bound on min_{j != i} |x_i - x_j|^2 over P pivot points
+// (indices floor(p n / P)); label[i] = the nearest pivot.  The squared
+// distances are summed in FP32 in the difference form; their relative error is
+// below (d + 3) 2^-24, so scaling by 1 + (d + 4) 2^-23 gives an upper bound.
+template <int DMAX>
+__global__ __launch_bounds__(256) void pivot_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t P,
+                                                    double* __restrict__ dmin, uint32_t* __restrict__ label,
+                                                    int32_t* __restrict__ ids) {
+    constexpr int CH = 64;  // pivots staged per round
+    __shared__ float piv[CH * DMAX];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    float xi[DMAX];
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t) xi[t] = (valid && t < d) ? X[i * d + t] : 0.0f;
+    float best = __builtin_inff();
+    uint32_t arg = 0;
+    for (int32_t p0 = 0; p0 < P; p0 += CH) {
+        const int32_t pc = min(CH, P - p0);
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < pc * DMAX; k += blockDim.x) {
+            const int32_t pp = k / DMAX, t = k - pp * DMAX;
+            const int64_t j = ((int64_t)(p0 + pp) * n) / P;
+            piv[k] = (t < d) ? X[j * d + t] : 0.0f;
+        }
+        __syncthreads();
+        for (int32_t pp = 0; pp < pc; ++pp) {
+            const float* pj = piv + pp * DMAX;
+            float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < DMAX; ++t) {
+                const float df = xi[t] - pj[t];
+                acc[t & 3] = __builtin_fmaf(df, df, acc[t & 3]);
+            }
+            const float D = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            const int64_t j = ((int64_t)(p0 + pp) * n) / P;
+            if (j != i && D < best) {
+                best = D;
+                arg = (uint32_t)(p0 + pp);
+            }
+        }
+    }
+    if (!valid) return;
+    dmin[i] = (double)best * (1.0 + (double)(d + 4) * 0x1p-23);
+    label[i] = arg;
+    ids[i] = (int32_t)i;
+}
+
+__global__ void max_norm_kernel(const double* norm, int64_t n, double* out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, norm[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = __builtin_sqrt(red[0]);
+}
+
+hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
+                             void* Xb, void* Qb, hipStream_t st) {
+    const int64_t total = (n_pad / 16) * KB * 64;
+    prep_split_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, norm, n, d, KB, total, (bf16x8_t*)Xb,
+                                                                       (bf16x8_t*)Qb);
+    return hipGetLastError();
+}
+
+hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double* dmin, uint32_t* label, int32_t* ids,
+                         hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (d <= 4) pivot_kernel<4><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else if (d <= 8) pivot_kernel<8><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else if (d <= 16) pivot_kernel<16><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else if (d <= 32) pivot_kernel<32><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else if (d <= 64) pivot_kernel<64><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_max_norm(const double* norm, int64_t n, double* out, hipStream_t st) {
+    max_norm_kernel<<<1, 256, 0, st>>>(norm, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace fsg

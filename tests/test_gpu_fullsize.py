@@ -41,3 +41,23 @@ def test_mix32_n100k_sampled_rows():
     assert rp[0] == 0 and rp[-1] == c.size and c.size <= 2 * n * L
     assert np.all(np.diff(rp) >= 0) and np.all(wt > 0)
     ctx.close()
+
+
+def test_mix32_n100k_bf16_split_sampled_rows():
+    import paper_2310_13870_amd as fsg
+    w = workloads.mixture32()
+    X = w.points()
+    ctx = fsg.Context(0)
+    say(f"full size {w.name} bf16_split")
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, w.L, w.philox_seed)
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rows = workloads.subsample(w.n, 96, 78)
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows)
+    rel = np.abs(deg[rows] - rdeg) / rdeg
+    assert rel.max() < 1e-9, f"degree max rel err {rel.max()}"
+    mism, exempt, non_exempt = compare_neighbours(nbr[rows], rnbr, rmargin)
+    say(f"sampled-row mismatches {mism} (exempt {exempt}, non-exempt {non_exempt})")
+    assert non_exempt == 0
+    pts.close()
+    ctx.close()

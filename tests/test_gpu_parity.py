@@ -176,3 +176,66 @@ def test_points_outlive_context():
     pts = fsg.Points(c, to_dev(np.zeros((50, 2), dtype=np.float32)))
     c.close()
     pts.close()
+
+
+@pytest.mark.parametrize("cap", [1, 2, 3, 5])
+def test_multi_pass_plans(ctx, cap):
+    """Capping the levels per binned pass forces later passes (gathered
+    queries per tree node, per-sample descent) without changing any result."""
+    n, d, L = 5000, 8, 6
+    X = _mix(n, d, 321)
+    gamma = 0.25
+    try:
+        ctx.set_levels_per_pass(cap)
+        _sample_parity(ctx, X, gamma, L, 99, f"cap{cap}")
+    finally:
+        ctx.set_levels_per_pass(0)
+
+
+# --------------------------------------------------------------------------
+# Precision mode (BF16 split filter + exact FP64 recompute)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,gamma", [(2, 2, 0.5), (17, 5, 0.3), (1000, 2, 0.5), (2049, 8, 0.1),
+                                       (3001, 32, 1 / 8), (1500, 33, 0.02), (777, 64, 1 / 18), (4000, 16, 0.3)])
+def test_degrees_bf16_split(ctx, n, d, gamma):
+    say(f"degrees bf16_split n={n} d={d}")
+    X = _mix(n, d, 700 + n + d)
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    deg = fsg.degrees(ctx, pts, gamma).cpu().numpy()
+    ref = oracle.degrees(X, gamma)
+    rel = np.abs(deg - ref) / np.maximum(ref, 1e-300)
+    assert rel.max() < 1e-9, f"max rel err {rel.max()}"
+
+
+@pytest.mark.parametrize("n,d,L", [(2, 2, 4), (65, 2, 7), (1000, 2, 10), (4097, 8, 13), (3000, 32, 12),
+                                   (2000, 64, 8), (1111, 17, 9)])
+def test_sample_edges_bf16_split(ctx, n, d, L):
+    X = _mix(n, d, 900 + n + d)
+    gamma = 1.0 / (2.0 * (0.5 * math.sqrt(d)) ** 2)
+    say(f"sample_edges bf16_split n={n} d={d}")
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 4321 + n)
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, gamma, L, 4321 + n)
+    rel = np.abs(deg - rdeg) / np.maximum(rdeg, 1e-300)
+    assert rel.max() < 1e-9, f"degree max rel err {rel.max()}"
+    mism, exempt, non_exempt = compare_neighbours(nbr, rnbr, rmargin)
+    say(f"  mismatches {mism} (band-exempt {exempt}, non-exempt {non_exempt})")
+    assert non_exempt == 0
+
+
+def test_bf16_split_matches_plain_and_prunes(ctx):
+    w = workloads.Workload("mix16-n20k", 20_000, 16, 2.0, 9, 55, 66, 12, (-6.0, 6.0), (0.5, 1.2))
+    X = w.points()
+    Xd = to_dev(X)
+    p32 = fsg.Points(ctx, Xd)
+    pbf = fsg.Points(ctx, Xd, "bf16_split")
+    ctx.reset_profiling()
+    a = fsg.sample_edges(ctx, p32, w.gamma, w.L, w.philox_seed)
+    b = fsg.sample_edges(ctx, pbf, w.gamma, w.L, w.philox_seed)
+    kept, scanned = ctx.filter_stats()
+    say(f"filter kept {kept} of {scanned} ({kept / max(scanned, 1):.3f})")
+    assert torch.equal(a[0], b[0])
+    rel = ((a[1] - b[1]).abs() / a[1]).max().item()
+    assert rel < 1e-12, rel
+    assert 0 < kept < scanned  # how much is pruned depends on how separated the clusters are
