@@ -62,9 +62,10 @@ typedef enum {
     /* precision mode: BF16 hi/lo split operands (hi = bf16(x), lo = bf16(x-hi))
      * on the BF16 matrix cores with FP32 accumulation give every pair an
      * approximate exponent with a guaranteed error bound; only pairs that can
-     * carry more than e^-Delta of their row's largest term (Delta = ln n + 30)
-     * are recomputed in FP64 as in FSG_FP32, the others add 0.  The masses then
-     * differ from the exact ones by less than n e^-Delta < 1e-13 relative.
+     * carry more than e^-Delta of their row's largest term (Delta = ln n + 25)
+     * are recomputed in FP64 as in FSG_FP32, the others add 0.  Every degree
+     * and node mass then differs from the exact one by less than
+     * (n-1) e^-Delta < e^-25 = 1.4e-11 of the degree.
      * Applies to the pass over all points (fsg_degrees, the first pass of
      * fsg_sample_edges); d <= 64. */
     FSG_BF16_SPLIT = 1

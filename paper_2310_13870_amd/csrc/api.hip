@@ -182,6 +182,11 @@ static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma) 
     return a;
 }
 
+// Precision-mode margin: pairs whose exponent exceeds the row's smallest by
+// more than ln(n) + kMarginExtra are dropped; their total is below
+// e^-kMarginExtra (1.4e-11) of the row's degree.
+constexpr double kMarginExtra = 25.0;
+
 // Binned KDE of all n points against the nodes of tree level D (one segment).
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
@@ -230,7 +235,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         m.qnorm = X->norm;
         m.dmin = X->dmin;
         m.xmax = X->xmax;
-        m.margin_z = std::log((double)n) + 30.0;
+        m.margin_z = std::log((double)n) + kMarginExtra;
         m.eps = 1.0 / 1024.0;
         m.gamma = gamma;
         m.n_tiles = tiles;

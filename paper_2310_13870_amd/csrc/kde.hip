@@ -20,7 +20,9 @@ namespace fsg {
 
 template <int D4, int RQ>
 __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
+    __shared__ int32_t win_all[4][kBinWindow];
     const int lane = threadIdx.x & 63;
+    int32_t* win = win_all[threadIdx.x >> 6];
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
@@ -64,7 +66,9 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
         const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
         const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
         BinAccumulator<RQ> bins;
-        bins.init(bnd, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
+        __builtin_amdgcn_wave_barrier();
+        load_bin_window(win, bnd, w.b0, w.b1, lane);
+        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
 
         for (int32_t c0 = col_begin & ~15; c0 < col_end; c0 += 16) {
             double xf[D4];

@@ -13,38 +13,50 @@
 
 namespace fsg {
 
+// Boundaries of a work item's bins are copied into a per-wave LDS window so
+// that reading the next boundary never waits behind vector-memory prefetches.
+constexpr int kBinWindow = 512;
+
+__device__ __forceinline__ void load_bin_window(int32_t* win, const int32_t* bnd, int32_t b0, int32_t b1, int lane) {
+    const int32_t cnt = min(b1 - b0 + 1, kBinWindow);
+    for (int32_t k = lane; k < cnt; k += 64) win[k] = bnd[b0 + k];
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int RQ>
 struct BinAccumulator {
     const int32_t* bnd;   // boundaries of the segment's bins
+    const int32_t* win;   // LDS copy of bnd[b0 .. b0 + kBinWindow)
     int32_t b0, b1;       // bins [b0, b1) of this work item
     int32_t cur;          // bin being accumulated (b0 - 1: before the first)
     int32_t nxt;          // first column of the next bin
-    int64_t e0;           // first query entry of the item
-    int32_t ne;           // valid entries
     int64_t stride;
     double* out;
-    const int32_t* out_rows;  // entry -> output row (NULL: the entry itself)
+    int64_t orow[RQ];     // output row of this lane's query row in each query block (-1: none)
     int lane;
     double acc[RQ];
     double pend[RQ];
 
-    __device__ void init(const int32_t* bnd_, int32_t b0_, int32_t b1_, int32_t col_begin, int64_t e0_, int32_t ne_,
-                         int64_t stride_, double* out_, const int32_t* out_rows_, int lane_) {
+    __device__ void init(const int32_t* bnd_, const int32_t* win_, int32_t b0_, int32_t b1_, int32_t col_begin,
+                         int64_t e0_, int32_t ne_, int64_t stride_, double* out_, const int32_t* out_rows_, int lane_) {
         bnd = bnd_;
+        win = win_;
         b0 = b0_;
         b1 = b1_;
         cur = b0_ - 1;
         nxt = col_begin;
-        e0 = e0_;
-        ne = ne_;
         stride = stride_;
         out = out_;
-        out_rows = out_rows_;
         lane = lane_;
 #pragma unroll
         for (int qb = 0; qb < RQ; ++qb) {
             acc[qb] = 0.0;
             pend[qb] = 0.0;
+            // output rows are resolved once, so that flushes issue no loads
+            // (a vector load there would wait for every prefetch in flight)
+            const int32_t t = 16 * qb + (lane & 15);
+            const int64_t e = e0_ + t;
+            orow[qb] = (t < ne_) ? (out_rows_ ? (int64_t)out_rows_[e] : e) : -1;
         }
     }
 
@@ -54,14 +66,8 @@ struct BinAccumulator {
         const int32_t b = base + (lane >> 4);
         if (b < b0 || b > last) return;
 #pragma unroll
-        for (int qb = 0; qb < RQ; ++qb) {
-            const int32_t t = 16 * qb + (lane & 15);
-            if (t < ne) {
-                const int64_t e = e0 + t;
-                const int64_t row = out_rows ? (int64_t)out_rows[e] : e;
-                out[row * stride + b] = pend[qb];
-            }
-        }
+        for (int qb = 0; qb < RQ; ++qb)
+            if (orow[qb] >= 0) out[orow[qb] * stride + b] = pend[qb];
     }
 
     __device__ void flush(int32_t bin) {
@@ -98,7 +104,12 @@ struct BinAccumulator {
                 for (int i = 0; i < 4; ++i)
                     if (jj[i] < nxt) kv[qb][i] = 0.0;
             ++cur;
-            nxt = (cur < b1) ? bnd[cur + 1] : INT32_MAX;
+            if (cur < b1) {
+                const int32_t k = cur + 1 - b0;
+                nxt = (k < kBinWindow) ? win[k] : bnd[cur + 1];
+            } else {
+                nxt = INT32_MAX;
+            }
         }
         if (cur >= b0 && cur < b1) {
 #pragma unroll

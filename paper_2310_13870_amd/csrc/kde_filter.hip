@@ -36,9 +36,14 @@ constexpr int mask_waves() { return KB <= 4 ? 3 : 2; }
 template <int D4>
 constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
 
-template <int KB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<KB>()))) void kde_keep_mask_kernel(MaskArgs m) {
+template <int KB, bool PREFETCH, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m) {
+    // Queries are the A operand and data the B operand, so lane l receives
+    // query rows 4(l/16) + i of a query block and data column l % 16: a column
+    // is kept when any of the 4 lane groups sees a compare succeed.
+    __shared__ float4_t theta_all[4][4][64];  // [wave][query block][lane]: thresholds of rows 4(l/16)+i
     const int lane = threadIdx.x & 63;
+    float4_t* theta_lds = &theta_all[threadIdx.x >> 6][0][0];
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int grp = lane >> 4;
@@ -52,28 +57,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<
         const int64_t e0 = tile * kTileQ;
         const int32_t ne = (int32_t)min((int64_t)kTileQ, m.n_entries - e0);
         bf16x8_t qb16[4][KB];
-        float theta[4];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) {
-            const int32_t t = 16 * qb + r;
-            const bool ok = t < ne;
-            int32_t p = m.q_idx ? m.q_idx[e0 + (ok ? t : 0)] : (int32_t)(e0 + (ok ? t : 0));
-            p = min(max(p, 0), (int32_t)(m.n_query - 1));
-            const bf16x8_t* bsrc = (const bf16x8_t*)m.Qb + (int64_t)(p >> 4) * KB * 64 + grp * 16 + (p & 15);
+            {
+                // operand rows: query 16 qb + r
+                const int32_t t = 16 * qb + r;
+                const int64_t e = e0 + ((t < ne) ? t : 0);
+                int32_t p = m.q_idx ? m.q_idx[e] : (int32_t)e;
+                p = min(max(p, 0), (int32_t)(m.n_query - 1));
+                const bf16x8_t* bsrc = (const bf16x8_t*)m.Qb + (int64_t)(p >> 4) * KB * 64 + grp * 16 + (p & 15);
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) qb16[qb][kb] = bsrc[kb * 64];
-            // keep-threshold on c~ - |x|^2/2, rounded down to FP32
-            const double nq = m.qnorm[p];
-            const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
-            const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - half_margin - err;
-            float thf = (float)th;
-            if ((double)thf > th) {  // step one FP32 ulp down
-                int32_t bits = __float_as_int(thf);
-                bits = (thf > 0.0f) ? bits - 1 : ((thf < 0.0f) ? bits + 1 : (int32_t)0x80000001);
-                thf = __int_as_float(bits);
+                for (int kb = 0; kb < KB; ++kb) qb16[qb][kb] = bsrc[kb * 64];
             }
-            theta[qb] = ok ? thf : __builtin_inff();
+            float4_t thq;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // result rows: query 16 qb + 4 grp + i; keep-threshold on
+                // c~ - |x|^2/2, rounded down to FP32
+                const int32_t t = 16 * qb + 4 * grp + i;
+                const bool ok = t < ne;
+                const int64_t e = e0 + (ok ? t : 0);
+                int32_t p = m.q_idx ? m.q_idx[e] : (int32_t)e;
+                p = min(max(p, 0), (int32_t)(m.n_query - 1));
+                const double nq = m.qnorm[p];
+                const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
+                const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - half_margin - err;
+                float thf = (float)th;
+                if ((double)thf > th) {  // step one FP32 ulp down
+                    int32_t bits = __float_as_int(thf);
+                    bits = (thf > 0.0f) ? bits - 1 : ((thf < 0.0f) ? bits + 1 : (int32_t)0x80000001);
+                    thf = __int_as_float(bits);
+                }
+                thq[i] = ok ? thf : __builtin_inff();
+            }
+            theta_lds[qb * 64 + lane] = thq;
         }
+        __builtin_amdgcn_wave_barrier();
         const int64_t bb = chunk * m.blocks_per_chunk;
         const int64_t be = min(m.n_blocks, bb + m.blocks_per_chunk);
         uint16_t* mrow = m.mask + tile * m.n_blocks;
@@ -83,26 +103,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<
         for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(bb * KB + kb) * 64 + lane];
         uint32_t pending = 0;  // lane (b mod 64) keeps the mask of block b until 64 are ready
         for (int64_t b = bb; b < be; ++b) {
-            if (b + 1 < be) {
+            if (PREFETCH && b + 1 < be) {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) xn[kb] = X16[((b + 1) * KB + kb) * 64 + lane];
             }
-            uint64_t mk[4] = {0, 0, 0, 0};
+            if (!PREFETCH && b > bb) {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(b * KB + kb) * 64 + lane];
+            }
+            uint64_t any = 0;
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb) {
                 float4_t cc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb) cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[kb], qb16[qb][kb], cc, 0, 0, 0);
+                for (int kb = 0; kb < KB; ++kb) cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], xb[kb], cc, 0, 0, 0);
+                const float4_t th = theta_lds[qb * 64 + lane];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) mk[i] |= __ballot(cc[i] >= theta[qb]);
+                for (int i = 0; i < 4; ++i) any |= __ballot(cc[i] >= th[i]);
             }
-            // column 4g + i of the block is kept if any query keeps it
-            uint32_t keep = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    if ((mk[i] >> (16 * g)) & 0xFFFFull) keep |= 1u << (4 * g + i);
+            uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & 0xFFFFull);
             if (16 * (b + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * b)) - 1u;
             kept += __popc(keep);
             if ((b & 63) == lane) pending = keep;
@@ -110,8 +129,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<
                 const int64_t base = b & ~(int64_t)63;
                 if (base + lane >= bb && base + lane <= b) mrow[base + lane] = (uint16_t)pending;
             }
+            if (PREFETCH) {
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) xb[kb] = xn[kb];
+                for (int kb = 0; kb < KB; ++kb) xb[kb] = xn[kb];
+            }
         }
     }
     if (m.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m.kept, (unsigned long long)kept);
@@ -119,16 +140,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mask_waves<
 
 // ---------------------------------------------------------------------------
 // Stage 2: exact recompute of the kept columns.  Work item = (query tile,
-// run of bins); kept columns of its blocks are queued in order and every 16 of
-// them form one gathered block for the FP64 matrix cores and the binned
-// epilogue.
+// run of bins).  Kept columns enter a circular queue in index order; every 16
+// of them form one gathered block for the FP64 matrix cores and the binned
+// epilogue.  The operands of the next block are loaded while the current one
+// is computed; the FP64 query fragments live in LDS.
 // ---------------------------------------------------------------------------
+template <int D4>
+struct Gathered {
+    double xf[D4];
+    double xn[4];  // |x|^2 of the four columns (scaled only when used, so that
+                   // the loads stay in flight while the previous block computes)
+    int32_t jj[4];
+    int32_t cnt, first, last;
+};
+
 template <int D4, int RQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(KdeArgs a, const uint16_t* __restrict__ mask,
-                                                             int64_t n_blocks) {
-    __shared__ int32_t queue_all[4][40];
-    int32_t* queue = queue_all[threadIdx.x >> 6];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
+    KdeArgs a, const uint16_t* __restrict__ mask, int64_t n_blocks) {
+    constexpr int QN = 64;  // circular queue length (at most 31 entries are pending)
+    __shared__ int32_t queue_all[4][QN];
+    __shared__ double qf_all[4][RQ * D4 * 64];
+    __shared__ int32_t win_all[4][kBinWindow];
     const int lane = threadIdx.x & 63;
+    int32_t* win = win_all[threadIdx.x >> 6];
+    int32_t* queue = queue_all[threadIdx.x >> 6];
+    double* qf = qf_all[threadIdx.x >> 6];  // [qb][kk][lane]
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
@@ -140,9 +176,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         const WorkItem w = a.items[it];
         const SegDesc sg = a.segs[w.seg];
         const int32_t* bnd = a.bounds + sg.bound_off;
-        double qf[RQ][D4];
         double hq[RQ];
         int32_t selfv[RQ], smin[RQ], smax[RQ];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int qb = 0; qb < RQ; ++qb) {
             const int32_t t = 16 * qb + r;
@@ -156,7 +192,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             hq[qb] = -a.s * a.qnorm[p];
             const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) qf[qb][kk] = src[kk * 64];
+            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = src[kk * 64];
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -166,85 +202,123 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             smin[qb] = mn;
             smax[qb] = mx;
         }
+        __builtin_amdgcn_wave_barrier();
         const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
         const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
         BinAccumulator<RQ> bins;
-        bins.init(bnd, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
+        __builtin_amdgcn_wave_barrier();
+        load_bin_window(win, bnd, w.b0, w.b1, lane);
+        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
         const uint16_t* mrow = mask + (w.e0 / kTileQ) * n_blocks;
-        int32_t qn = 0;
+        const int64_t blk0 = col_begin >> 4, blk1 = (col_end + 15) >> 4;
 
-        auto exact_block = [&](int32_t cnt) {
-            const int32_t gl = queue[(r < cnt) ? r : 0];
-            double xf[D4];
+        // queue state (uniform): entries [head, tail) are pending
+        int32_t head = 0, tail = 0;
+        int64_t blk = blk0;  // next block whose mask is to be read
+        uint32_t batch = 0;  // masks of blocks [blk & ~63, +64) held one per lane
+        int64_t batch_base = -1;
+
+        // append the kept columns of further blocks until 16 are pending or the range ends
+        auto fill = [&]() {
+            while (tail - head < 16 && blk < blk1) {
+                const int64_t bb = blk & ~(int64_t)63;
+                if (bb != batch_base) {
+                    batch_base = bb;
+                    const int64_t myb = bb + lane;
+                    batch = (myb >= blk0 && myb < blk1) ? (uint32_t)mrow[myb] : 0u;
+                }
+                uint32_t keep = (uint32_t)__shfl(batch, (int)(blk - bb));
+                const int32_t c0 = (int32_t)(blk << 4);
+                if (c0 < col_begin) keep &= ~((1u << (col_begin - c0)) - 1u);
+                if (c0 + 16 > col_end) keep &= (1u << (col_end - c0)) - 1u;
+                if (keep != 0) {
+                    if (lane < 16 && ((keep >> lane) & 1u))
+                        queue[(tail + __popc(keep & ((1u << lane) - 1u))) & (QN - 1)] = c0 + lane;
+                    tail += __popc(keep);
+                }
+                ++blk;
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+
+        // gather the operands of the block of queue entries [pos, pos + cnt)
+        auto prepare = [&](Gathered<D4>& g, int32_t pos, int32_t cnt) {
+            g.cnt = cnt;
+            const int32_t gl = queue[(pos + ((r < cnt) ? r : 0)) & (QN - 1)];
             const double* xs = a.Xp + (int64_t)(gl >> 4) * D4 * 64 + grp * 16 + (gl & 15);
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) xf[kk] = xs[kk * 64];
-            int32_t jj[4];
-            double hx[4];
-            const int32_t first = queue[0];
+            for (int kk = 0; kk < D4; ++kk) g.xf[kk] = xs[kk * 64];
+            g.first = queue[pos & (QN - 1)];
+            g.last = queue[(pos + cnt - 1) & (QN - 1)];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int32_t idx = grp + 4 * i;
-                jj[i] = (idx < cnt) ? queue[idx] : INT32_MAX;
-                hx[i] = -a.s * a.xnorm[(idx < cnt) ? jj[i] : first];
+                g.jj[i] = (idx < cnt) ? queue[(pos + idx) & (QN - 1)] : INT32_MAX;
+                g.xn[i] = a.xnorm[(idx < cnt) ? g.jj[i] : g.first];
             }
-            const int32_t last = queue[cnt - 1];
+        };
+
+        auto compute = [&](const Gathered<D4>& g) {
+            double hx[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hx[i] = -a.s * g.xn[i];
             double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
+                double qv[D4];
+#pragma unroll
+                for (int kk = 0; kk < D4; ++kk) qv[kk] = qf[(qb * D4 + kk) * 64 + lane];
                 c[qb] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
+                for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ>(c, hq, hx, two_s, jj, selfv, smin, smax, first, last, kv);
+            exact_values<RQ>(c, hq, hx, two_s, g.jj, selfv, smin, smax, g.first, g.last, kv);
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (jj[i] == INT32_MAX) kv[qb][i] = 0.0;
-            bins.add(kv, jj, last);
+                    if (g.jj[i] == INT32_MAX) kv[qb][i] = 0.0;
+            bins.add(kv, g.jj, g.last);
         };
 
-        const int64_t blk0 = col_begin >> 4, blk1 = (col_end + 15) >> 4;
-        for (int64_t base = blk0; base < blk1; base += 64) {
-            // the masks of up to 64 blocks, one per lane
-            const int64_t myb = base + lane;
-            const uint32_t mine = (myb < blk1) ? (uint32_t)mrow[myb] : 0u;
-            const int64_t nb = min((int64_t)64, blk1 - base);
-            for (int64_t k = 0; k < nb; ++k) {
-                uint32_t keep = (uint32_t)__shfl(mine, (int)k);
-                const int32_t c0 = (int32_t)((base + k) << 4);
-                if (c0 < col_begin) keep &= ~((1u << (col_begin - c0)) - 1u);
-                if (c0 + 16 > col_end) keep &= (1u << (col_end - c0)) - 1u;
-                if (keep == 0) continue;
-                if (lane < 16 && ((keep >> lane) & 1u)) queue[qn + __popc(keep & ((1u << lane) - 1u))] = c0 + lane;
-                __builtin_amdgcn_wave_barrier();
-                qn += __popc(keep);
-                if (qn >= 16) {
-                    exact_block(16);
-                    const int32_t rest = qn - 16;
-                    const int32_t v = (lane < rest) ? queue[16 + lane] : 0;
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < rest) queue[lane] = v;
-                    __builtin_amdgcn_wave_barrier();
-                    qn = rest;
+        fill();
+        if (tail > head) {
+            Gathered<D4> cur, nxt;
+            int32_t n0 = min(16, tail - head);
+            prepare(cur, head, n0);
+            head += n0;
+            while (true) {
+                fill();
+                const int32_t n1 = min(16, tail - head);
+                if (n1 > 0) {
+                    prepare(nxt, head, n1);
+                    head += n1;
                 }
+                compute(cur);
+                if (n1 == 0) break;
+                cur = nxt;
             }
         }
-        if (qn > 0) exact_block(qn);
         bins.finish();
     }
 }
 
-template <int KB>
-static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) {
+template <int KB, bool PREFETCH, int WAVES>
+static hipError_t launch_mask_v(const MaskArgs& m, int num_cus, hipStream_t st) {
     const int64_t n_items = m.n_tiles * m.n_chunks;
-    int64_t waves = (int64_t)num_cus * 4 * mask_waves<KB>();
+    int64_t waves = (int64_t)num_cus * 4 * WAVES;
     if (n_items < waves) waves = n_items;
     if (waves < 1) waves = 1;
-    kde_keep_mask_kernel<KB><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    kde_keep_mask_kernel<KB, PREFETCH, WAVES><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
     return hipGetLastError();
+}
+
+// Measured on the MI355X (n = 100k, d = 32): next-block prefetch at 3 waves per
+// SIMD beats no prefetch at 3 or 4 waves and prefetch at 2 waves.
+template <int KB>
+static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) {
+    return launch_mask_v<KB, true, mask_waves<KB>()>(m, num_cus, st);
 }
 
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {

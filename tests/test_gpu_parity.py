@@ -236,6 +236,7 @@ def test_bf16_split_matches_plain_and_prunes(ctx):
     kept, scanned = ctx.filter_stats()
     say(f"filter kept {kept} of {scanned} ({kept / max(scanned, 1):.3f})")
     assert torch.equal(a[0], b[0])
+    # the precision mode drops at most e^-25 = 1.4e-11 of each degree
     rel = ((a[1] - b[1]).abs() / a[1]).max().item()
-    assert rel < 1e-12, rel
+    assert rel < 2e-11, rel
     assert 0 < kept < scanned  # how much is pruned depends on how separated the clusters are
