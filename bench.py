@@ -34,23 +34,31 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
-def kde_source_hash() -> str:
+# the dominant kernel of each precision mode, the source files that define it
+# and the committed counter summary that holds its HBM traffic per launch
+DOMINANT = {
+    "fp32": ("kde_bins", ("kde.hip", "kde_epilogue.h", "device.h", "common.h")),
+    "bf16_split": ("kde_exact_kept", ("kde_filter.hip", "kde_epilogue.h", "device.h", "common.h")),
+}
+
+
+def kernel_source_hash(precision: str) -> str:
     h = hashlib.sha256()
-    for name in ("kde.hip", "device.h", "common.h"):
+    for name in DOMINANT[precision][1]:
         with open(os.path.join(ROOT, "paper_2310_13870_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str):
-    """HBM bytes per launch of the root KDE from the committed counter summary,
-    if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"kde_root_{workload}_traffic.json")
+def traffic_from_profile(workload: str, precision: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{DOMINANT[precision][0]}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256_16") != kde_source_hash():
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(precision):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -169,8 +177,10 @@ def main():
             pairs = kept / args.steps * 64
         flops = 2.0 * d * pairs
         achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
-        traffic = traffic_from_profile(args.workload)
-        roofline = {"bound": "mfma", "kernel": "binned exact KDE over all points (FP64 matrix cores)",
+        traffic = traffic_from_profile(args.workload, args.precision)
+        label = ("binned KDE over all point pairs (FP64 matrix cores)" if args.precision == "fp32"
+                 else "exact FP64 recompute of the kept pairs (FP64 matrix cores)")
+        roofline = {"bound": "mfma", "kernel": label,
                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
                     "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops}

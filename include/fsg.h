@@ -98,9 +98,10 @@ uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
 fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled);
 fsg_status fsg_ctx_stage_time(fsg_ctx* ctx, const char* stage, double* ms, int64_t* launches);
 fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);
-/* Precision-mode statistics since the last reset: *kept = (data column, wave
- * tile) pairs recomputed exactly, *scanned = (data column, wave tile) pairs
- * examined by the BF16 filter.  Synchronises the stream. */
+/* Precision-mode statistics since the last reset: *kept = (data column,
+ * 64-query tile) pairs that the BF16 filter keeps for exact recomputation,
+ * *scanned = (data column, 64-query tile) pairs it examined.  Synchronises the
+ * stream. */
 fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned);
 
 /* Cap the number of tree levels one binned KDE pass resolves (0 restores the

@@ -120,7 +120,8 @@ class Context:
         return ms.value, cnt.value
 
     def filter_stats(self):
-        """(kept, scanned) column-tile pairs of the precision-mode filter since the last reset."""
+        """(kept, scanned) (data column, 64-query tile) pairs of the precision-mode
+        filter since the last reset."""
         kept, scanned = _i64(0), _i64(0)
         self.check(_lib.fsg_ctx_filter_stats(self._h, ctypes.byref(kept), ctypes.byref(scanned)))
         return kept.value, scanned.value

@@ -251,14 +251,18 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
             FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
         }
         m.kept = ctx->filter_counts;
-        // columns examined: every data column once per 64-query tile
+        // pairs examined: every data column once per 64-query tile
         FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, tiles * n, ctx->stream));
         {
             StageTimer t(ctx, "kde_mask");
             FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));
         }
+        int64_t* next_item;
+        if ((st = ws(ctx, "exact_next_item", 1, &next_item)) != FSG_OK) return st;
+        FSG_HIP(ctx, launch_fill_i64(next_item, 1, 0, ctx->stream));
         StageTimer t(ctx, "kde_root");
-        FSG_HIP(ctx, launch_exact_kept(a, m.mask, m.n_blocks, n_items, ctx->num_cus, ctx->stream));
+        FSG_HIP(ctx, launch_exact_kept(a, m.mask, m.n_blocks, n_items, (unsigned long long*)next_item, ctx->num_cus,
+                                       ctx->stream));
         return FSG_OK;
     }
     {

@@ -14,11 +14,13 @@ namespace fsg {
 // ---------------------------------------------------------------------------
 // Geometry of the FP64 matrix-core operand layout.
 // v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
-// receives C[l/16 + 4i][l%16] in element i.  Points are stored so that one
-// 64-lane load of 512 contiguous bytes is one operand fragment:
-//   Xp[((p >> 4) * D4 + kk) * 64 + lane] = X[16*(p>>4) + (lane & 15)][4*kk + (lane >> 4)]
-// with D4 = number of 4-wide feature steps (features zero-padded to 4*D4) and
-// rows zero-padded to a multiple of 16.
+// receives C[l/16 + 4i][l%16] in element i.  Each point is one FP64 row of
+// 4*D4 values (D4 = number of 4-wide feature steps, features zero-padded to
+// 4*D4, rows zero-padded to a multiple of 16) in feature-step-minor order:
+//   Xp[p * 4 * D4 + g * D4 + kk] = X[p][4*kk + g]
+// so the lane that supplies feature row g of a point reads its D4 operands of
+// all steps as one contiguous run, and a gathered point is 32*D4 contiguous
+// bytes.
 // ---------------------------------------------------------------------------
 constexpr int kLeafMax = 64;     // largest node the leaf stage resolves
 constexpr int kTileQ = 64;       // query entries per wave in the KDE kernel
@@ -43,9 +45,9 @@ struct SegDesc {
 enum SelfMode : int32_t { SELF_NONE = 0, SELF_POINT = 1, SELF_ARRAY = 2 };
 
 struct KdeArgs {
-    const double* Qp;        // query operand fragments
+    const double* Qp;        // query operand rows
     const double* qnorm;     // ||q||^2, FP64
-    const double* Xp;        // data operand fragments
+    const double* Xp;        // data operand rows
     const double* xnorm;     // ||x||^2, FP64 (padded rows hold 0)
     int32_t D4;              // feature steps
     int64_t n_query;         // points in the query set (indices are clamped into range)
@@ -83,7 +85,7 @@ struct MaskArgs {
     int64_t n_blocks;          // 16-column data blocks
     int64_t blocks_per_chunk;
     int64_t n_chunks;
-    uint16_t* mask;            // [n_tiles][n_blocks]
+    uint16_t* mask;            // [n_tiles][n_blocks]: bit c = column c of the block kept for the tile
     int64_t* kept;             // optional: number of (column, tile) pairs kept
 };
 
@@ -125,7 +127,7 @@ struct fsg_points {
     int32_t D4 = 0;            // padded feature steps
     int64_t n_pad = 0;         // rows padded to a multiple of 16
     fsg_precision prec = FSG_FP32;
-    double* Xp = nullptr;      // FP64 operand fragments [n_pad/16][D4][64]
+    double* Xp = nullptr;      // FP64 operand rows [n_pad][4][D4] (feature 4*kk+g at g*D4+kk)
     double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
     // precision mode (FSG_BF16_SPLIT)
     int32_t KB = 0;            // 32-wide K steps of the split operands
@@ -177,8 +179,10 @@ hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t s
 // KDE over a work list; grid = waves / 4 blocks of 256 threads.
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);
-hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items, int num_cus,
-                             hipStream_t st);
+// next_item: a counter that must read 0 when the kernel starts (work items
+// beyond the first wave of the grid are claimed from it)
+hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
+                             unsigned long long* next_item, int num_cus, hipStream_t st);
 int split_steps(int d);
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
                              void* Xb, void* Qb, hipStream_t st);

@@ -49,38 +49,50 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
             selfv[qb] = sf;
             hq[qb] = -a.s * a.qnorm[p];
-            const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
-#pragma unroll
-            for (int kk = 0; kk < D4; ++kk) qf[qb][kk] = src[kk * 64];
+            load_row_part<D4>(qf[qb], a.Qp, p, grp);
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 mn = min(mn, __shfl_xor(mn, off));
                 mx = max(mx, __shfl_xor(mx, off));
             }
-            smin[qb] = mn;
-            smax[qb] = mx;
+            smin[qb] = uniform(mn);
+            smax[qb] = uniform(mx);
         }
 
         // never read outside the data set, whatever the boundaries say
-        const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
-        const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
+        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)a.n_data));
+        const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
         BinAccumulator<RQ> bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
         bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
 
-        for (int32_t c0 = col_begin & ~15; c0 < col_end; c0 += 16) {
-            double xf[D4];
-            const double* xs = a.Xp + (int64_t)(c0 >> 4) * D4 * 64 + lane;
+        // the operands of the next block are loaded while the current one is
+        // computed
+        const int32_t cfirst = col_begin & ~15;
+        double xf[D4], xn[4];
+        if (cfirst < col_end) {
+            load_row_part<D4>(xf, a.Xp, cfirst + perm_row(r), grp);
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) xf[kk] = xs[kk * 64];
+            for (int i = 0; i < 4; ++i) xn[i] = a.xnorm[cfirst + 4 * grp + i];
+        }
+        for (int32_t c0 = cfirst; c0 < col_end; c0 += 16) {
+            double xf_next[D4], xn_next[4];
+            // (d > 64: the query fragments fill the register file, no prefetch)
+            constexpr bool kPrefetch = D4 <= 16;
+            const bool more = c0 + 16 < col_end;
+            if (kPrefetch && more) {
+                load_row_part<D4>(xf_next, a.Xp, c0 + 16 + perm_row(r), grp);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xn_next[i] = a.xnorm[c0 + 16 + 4 * grp + i];
+            }
             int32_t jj[4];
             double hx[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                jj[i] = c0 + grp + 4 * i;
-                hx[i] = -a.s * a.xnorm[jj[i]];
+                jj[i] = c0 + 4 * grp + i;
+                hx[i] = -a.s * xn[i];
             }
             double4_t c[RQ];
 #pragma unroll
@@ -92,6 +104,18 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             double kv[RQ][4];
             exact_values<RQ>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, kv);
             bins.add(kv, jj, c0 + 15);
+            if (more) {
+                if (kPrefetch) {
+#pragma unroll
+                    for (int kk = 0; kk < D4; ++kk) xf[kk] = xf_next[kk];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xn[i] = xn_next[i];
+                } else {
+                    load_row_part<D4>(xf, a.Xp, c0 + 16 + perm_row(r), grp);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xn[i] = a.xnorm[c0 + 16 + 4 * grp + i];
+                }
+            }
         }
         bins.finish();
     }

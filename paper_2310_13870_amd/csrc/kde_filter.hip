@@ -148,15 +148,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
 template <int D4>
 struct Gathered {
     double xf[D4];
-    double xn[4];  // |x|^2 of the four columns (scaled only when used, so that
-                   // the loads stay in flight while the previous block computes)
+    double xn[4];  // |x|^2 of the lane's four columns, +inf for padding (scaled
+                   // only when used, so that the loads stay in flight while
+                   // the previous block computes)
     int32_t jj[4];
-    int32_t cnt, first, last;
+    int32_t first, last;  // smallest and largest column (uniform)
 };
 
 template <int D4, int RQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
-    KdeArgs a, const uint16_t* __restrict__ mask, int64_t n_blocks) {
+    KdeArgs a, const uint16_t* __restrict__ mask, int64_t n_blocks, unsigned long long* __restrict__ next_item) {
     constexpr int QN = 64;  // circular queue length (at most 31 entries are pending)
     __shared__ int32_t queue_all[4][QN];
     __shared__ double qf_all[4][RQ * D4 * 64];
@@ -171,8 +172,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     const double two_s = 2.0 * a.s;
     const int grp = lane >> 4;
     const int r = lane & 15;
+    const int pr = perm_row(r);
 
-    for (int64_t it = wave; it < n_items; it += n_waves) {
+    // items [0, n_waves) are taken in wave order, later ones from the counter
+    int64_t it = wave;
+    while (it < n_items) {
+        // claim the next item now; the answer is needed only at the end
+        unsigned long long claim = 0;
+        if (lane == 0) claim = atomicAdd(next_item, 1ull);
         const WorkItem w = a.items[it];
         const SegDesc sg = a.segs[w.seg];
         const int32_t* bnd = a.bounds + sg.bound_off;
@@ -190,21 +197,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
             selfv[qb] = sf;
             hq[qb] = -a.s * a.qnorm[p];
-            const double* src = a.Qp + (int64_t)(p >> 4) * D4 * 64 + grp * 16 + (p & 15);
+            double qv[D4];
+            load_row_part<D4>(qv, a.Qp, p, grp);
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = src[kk * 64];
+            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = qv[kk];
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 mn = min(mn, __shfl_xor(mn, off));
                 mx = max(mx, __shfl_xor(mx, off));
             }
-            smin[qb] = mn;
-            smax[qb] = mx;
+            smin[qb] = uniform(mn);
+            smax[qb] = uniform(mx);
         }
         __builtin_amdgcn_wave_barrier();
-        const int32_t col_end = min(max(bnd[w.b1], 0), (int32_t)a.n_data);
-        const int32_t col_begin = min(max(bnd[w.b0], 0), col_end);
+        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)a.n_data));
+        const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
         BinAccumulator<RQ> bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
@@ -215,25 +223,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         // queue state (uniform): entries [head, tail) are pending
         int32_t head = 0, tail = 0;
         int64_t blk = blk0;  // next block whose mask is to be read
-        uint32_t batch = 0;  // masks of blocks [blk & ~63, +64) held one per lane
-        int64_t batch_base = -1;
+        // masks of blocks [base, base + 64) and of the 64 after them, one per
+        // lane; the second batch is loaded one batch ahead
+        int64_t base = blk0 & ~(int64_t)63;
+        auto load_batch = [&](int64_t b) -> uint32_t {
+            const int64_t myb = b + lane;
+            return (myb >= blk0 && myb < blk1) ? (uint32_t)mrow[myb] : 0u;
+        };
+        uint32_t batch = load_batch(base);
+        uint32_t batch_next = load_batch(base + 64);
 
         // append the kept columns of further blocks until 16 are pending or the range ends
         auto fill = [&]() {
             while (tail - head < 16 && blk < blk1) {
-                const int64_t bb = blk & ~(int64_t)63;
-                if (bb != batch_base) {
-                    batch_base = bb;
-                    const int64_t myb = bb + lane;
-                    batch = (myb >= blk0 && myb < blk1) ? (uint32_t)mrow[myb] : 0u;
+                if (blk >= base + 64) {
+                    base += 64;
+                    batch = batch_next;
+                    batch_next = load_batch(base + 64);
                 }
-                uint32_t keep = (uint32_t)__shfl(batch, (int)(blk - bb));
+                uint32_t keep = (uint32_t)__builtin_amdgcn_readlane((int)batch, (int)(blk - base));
                 const int32_t c0 = (int32_t)(blk << 4);
                 if (c0 < col_begin) keep &= ~((1u << (col_begin - c0)) - 1u);
                 if (c0 + 16 > col_end) keep &= (1u << (col_end - c0)) - 1u;
                 if (keep != 0) {
                     if (lane < 16 && ((keep >> lane) & 1u))
-                        queue[(tail + __popc(keep & ((1u << lane) - 1u))) & (QN - 1)] = c0 + lane;
+                        queue[(tail + (int32_t)__builtin_amdgcn_mbcnt_lo(keep, 0u)) & (QN - 1)] = c0 + lane;
                     tail += __popc(keep);
                 }
                 ++blk;
@@ -241,24 +255,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             __builtin_amdgcn_wave_barrier();
         };
 
-        // gather the operands of the block of queue entries [pos, pos + cnt)
+        // gather the operands of the block of queue entries [pos, pos + cnt):
+        // A row r holds entry perm_row(r), so that lane group g receives the
+        // consecutive entries 4g .. 4g+3
         auto prepare = [&](Gathered<D4>& g, int32_t pos, int32_t cnt) {
-            g.cnt = cnt;
-            const int32_t gl = queue[(pos + ((r < cnt) ? r : 0)) & (QN - 1)];
-            const double* xs = a.Xp + (int64_t)(gl >> 4) * D4 * 64 + grp * 16 + (gl & 15);
-#pragma unroll
-            for (int kk = 0; kk < D4; ++kk) g.xf[kk] = xs[kk * 64];
-            g.first = queue[pos & (QN - 1)];
-            g.last = queue[(pos + cnt - 1) & (QN - 1)];
+            const int32_t gl = queue[(pos + ((pr < cnt) ? pr : 0)) & (QN - 1)];
+            load_row_part<D4>(g.xf, a.Xp, gl, grp);
+            g.first = uniform(queue[pos & (QN - 1)]);
+            g.last = uniform(queue[(pos + cnt - 1) & (QN - 1)]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int32_t idx = grp + 4 * i;
+                const int32_t idx = 4 * grp + i;
                 g.jj[i] = (idx < cnt) ? queue[(pos + idx) & (QN - 1)] : INT32_MAX;
-                g.xn[i] = a.xnorm[(idx < cnt) ? g.jj[i] : g.first];
+                const double v = a.xnorm[(idx < cnt) ? g.jj[i] : g.first];
+                g.xn[i] = (idx < cnt) ? v : __builtin_inf();
             }
         };
 
         auto compute = [&](const Gathered<D4>& g) {
+            // padding columns: |x|^2 = +inf gives exponent -inf and value 0
             double hx[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) hx[i] = -a.s * g.xn[i];
@@ -274,11 +289,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             }
             double kv[RQ][4];
             exact_values<RQ>(c, hq, hx, two_s, g.jj, selfv, smin, smax, g.first, g.last, kv);
-#pragma unroll
-            for (int qb = 0; qb < RQ; ++qb)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (g.jj[i] == INT32_MAX) kv[qb][i] = 0.0;
             bins.add(kv, g.jj, g.last);
         };
 
@@ -301,6 +311,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             }
         }
         bins.finish();
+        it = n_waves + (int64_t)(uint32_t)uniform((int32_t)(uint32_t)__shfl(claim, 0));
     }
 }
 
@@ -333,22 +344,22 @@ hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
 
 template <int D4>
 static hipError_t launch_exact_t(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
-                                 int num_cus, hipStream_t st) {
+                                 unsigned long long* next_item, int num_cus, hipStream_t st) {
     int64_t waves = (int64_t)num_cus * 8;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
-    kde_exact_kept_kernel<D4, 4><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, mask, n_blocks);
+    kde_exact_kept_kernel<D4, 4><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, mask, n_blocks, next_item);
     return hipGetLastError();
 }
 
-hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items, int num_cus,
-                             hipStream_t st) {
+hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
+                             unsigned long long* next_item, int num_cus, hipStream_t st) {
     switch (a.D4) {
-        case 1: return launch_exact_t<1>(a, mask, n_blocks, max_items, num_cus, st);
-        case 2: return launch_exact_t<2>(a, mask, n_blocks, max_items, num_cus, st);
-        case 4: return launch_exact_t<4>(a, mask, n_blocks, max_items, num_cus, st);
-        case 8: return launch_exact_t<8>(a, mask, n_blocks, max_items, num_cus, st);
-        case 16: return launch_exact_t<16>(a, mask, n_blocks, max_items, num_cus, st);
+        case 1: return launch_exact_t<1>(a, mask, n_blocks, max_items, next_item, num_cus, st);
+        case 2: return launch_exact_t<2>(a, mask, n_blocks, max_items, next_item, num_cus, st);
+        case 4: return launch_exact_t<4>(a, mask, n_blocks, max_items, next_item, num_cus, st);
+        case 8: return launch_exact_t<8>(a, mask, n_blocks, max_items, next_item, num_cus, st);
+        case 16: return launch_exact_t<16>(a, mask, n_blocks, max_items, next_item, num_cus, st);
         default: return hipErrorInvalidValue;
     }
 }

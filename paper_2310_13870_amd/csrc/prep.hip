@@ -1,4 +1,4 @@
-// Hot-path step "prep": FP64 matrix-core operand fragments, squared norms,
+// Hot-path step "prep": FP64 matrix-core operand rows, squared norms,
 // and the node boundaries of one level of the index-order partition tree.
 #include "common.h"
 #include "device.h"
@@ -9,12 +9,11 @@ __global__ void prep_fragments_kernel(const float* __restrict__ X, int64_t n, in
                                       double* __restrict__ Xp) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int64_t per_blk = (int64_t)D4 * 64;
-    const int64_t blk = idx / per_blk;
-    const int32_t rem = (int32_t)(idx - blk * per_blk);
-    const int32_t kk = rem >> 6, lane = rem & 63;
-    const int64_t row = blk * 16 + (lane & 15);
-    const int32_t col = kk * 4 + (lane >> 4);
+    const int64_t per_row = (int64_t)D4 * 4;
+    const int64_t row = idx / per_row;
+    const int32_t rem = (int32_t)(idx - row * per_row);
+    const int32_t g = rem / D4, kk = rem - g * D4;
+    const int32_t col = kk * 4 + g;
     Xp[idx] = (row < n && col < d) ? (double)X[row * d + col] : 0.0;
 }
 
