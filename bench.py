@@ -162,8 +162,6 @@ def main():
     while math.ceil(n / 2 ** depth_leaf) > 64:
         depth_leaf += 1
     evals = n * (n - 1) + n * L * n / 2 ** depth_leaf if depth_leaf > 0 else n * L * n
-    def split_k(dd):
-        return 32 * ((3 * dd + 2 + 31) // 32)
 
     kde = stages.get("kde_root")
     mask = stages.get("kde_mask")
@@ -185,7 +183,9 @@ def main():
                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
                     "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops}
     if mask:
-        flops = 2.0 * split_k(d) * n * n
+        # the split contraction over K = 3d (hi.hi + hi.lo + lo.hi) for every
+        # (query, column) pair; zero padding of K is not counted
+        flops = 2.0 * 3 * d * n * n
         achieved = flops / (mask["ms_per_launch"] * 1e-3) / 1e12
         distance_tiles = {"bound": "mfma", "kernel": "BF16 split keep-mask kernel (distance tiles)",
                           "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -227,6 +227,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         std::memset(&m, 0, sizeof(m));
         m.Xb = X->Xb;
         m.Qb = X->Qb;
+        m.xa = X->xa;
         m.KB = X->KB;
         m.q_idx = X->order;
         m.n_entries = n;
@@ -324,17 +325,20 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if (hipMalloc(&p->dmin, n * sizeof(double)) != hipSuccess) return fail("distance bounds");
     if (hipMalloc(&p->order, n * sizeof(int32_t)) != hipSuccess) return fail("pivot order");
     if (hipMalloc(&p->xmax, sizeof(double)) != hipSuccess) return fail("norm bound");
-    p->bytes += 2 * split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double);
+    if (hipMalloc(&p->xa, p->n_pad * sizeof(float)) != hipSuccess) return fail("norm terms");
+    p->bytes += 2 * split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) + p->n_pad * sizeof(float);
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
     if (st != FSG_OK) return st;
+    double* part;
+    if ((st = ws(ctx, "max_norm_parts", (size_t)max_norm_parts(n), &part)) != FSG_OK) return st;
     StageTimer t(ctx, "prep");
-    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->Qb, ctx->stream));
+    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->Qb, p->xa, ctx->stream));
     const int32_t P = (int32_t)(n < 256 ? n : 256);
     FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
     FSG_HIP(ctx, radix_sort_u32(label, p->order, n, 8, b, ctx->stream));
-    FSG_HIP(ctx, launch_max_norm(p->norm, n, p->xmax, ctx->stream));
+    FSG_HIP(ctx, launch_max_norm(p->norm, n, part, p->xmax, ctx->stream));
     return FSG_OK;
 }
 
@@ -533,6 +537,7 @@ void fsg_points_destroy(fsg_points* p) {
     if (p->dmin) (void)hipFree(p->dmin);
     if (p->order) (void)hipFree(p->order);
     if (p->xmax) (void)hipFree(p->xmax);
+    if (p->xa) (void)hipFree(p->xa);
     for (auto& kv : p->levels) (void)hipFree(kv.second);
     delete p;
 }

@@ -16,11 +16,12 @@ namespace fsg {
 // v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
 // receives C[l/16 + 4i][l%16] in element i.  Each point is one FP64 row of
 // 4*D4 values (D4 = number of 4-wide feature steps, features zero-padded to
-// 4*D4, rows zero-padded to a multiple of 16) in feature-step-minor order:
-//   Xp[p * 4 * D4 + g * D4 + kk] = X[p][4*kk + g]
-// so the lane that supplies feature row g of a point reads its D4 operands of
-// all steps as one contiguous run, and a gathered point is 32*D4 contiguous
-// bytes.
+// 4*D4, rows zero-padded to a multiple of 16); feature 4*kk + g of point p is
+//   Xp[p * 4 * D4 + (kk / 2) * 8 + g * 2 + kk % 2]   (D4 >= 2),
+//   Xp[p * 4 + g]                                     (D4 = 1),
+// so the four lanes that supply feature rows 0-3 of a point read 64
+// contiguous bytes per 16-byte load, and a gathered point is 32*D4
+// contiguous bytes.
 // ---------------------------------------------------------------------------
 constexpr int kLeafMax = 64;     // largest node the leaf stage resolves
 constexpr int kTileQ = 64;       // query entries per wave in the KDE kernel
@@ -70,6 +71,7 @@ struct KdeArgs {
 struct MaskArgs {
     const void* Xb;            // data-side split fragments [n_pad/16][KB][64] x 8 bf16
     const void* Qb;            // query-side split fragments
+    const float* xa;           // -|x|^2/2 of the data points [n_pad]
     int32_t KB;                // 32-wide K steps of the split operands
     const int32_t* q_idx;      // entry -> query point (NULL: the entry itself)
     int64_t n_entries;
@@ -127,12 +129,13 @@ struct fsg_points {
     int32_t D4 = 0;            // padded feature steps
     int64_t n_pad = 0;         // rows padded to a multiple of 16
     fsg_precision prec = FSG_FP32;
-    double* Xp = nullptr;      // FP64 operand rows [n_pad][4][D4] (feature 4*kk+g at g*D4+kk)
+    double* Xp = nullptr;      // FP64 operand rows [n_pad][4*D4] (layout above)
     double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
     // precision mode (FSG_BF16_SPLIT)
     int32_t KB = 0;            // 32-wide K steps of the split operands
     void* Xb = nullptr;        // data-side split fragments
     void* Qb = nullptr;        // query-side split fragments
+    float* xa = nullptr;       // -|x|^2/2 in FP32 [n_pad]
     double* dmin = nullptr;    // upper bound on each point's smallest squared distance
     int32_t* order = nullptr;  // points ordered by nearest pivot
     double* xmax = nullptr;    // device scalar: max |x|
@@ -185,10 +188,11 @@ hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_b
                              unsigned long long* next_item, int num_cus, hipStream_t st);
 int split_steps(int d);
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
-                             void* Xb, void* Qb, hipStream_t st);
+                             void* Xb, void* Qb, float* xa, hipStream_t st);
 hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double* dmin, uint32_t* label, int32_t* ids,
                          hipStream_t st);
-hipError_t launch_max_norm(const double* norm, int64_t n, double* out, hipStream_t st);
+int max_norm_parts(int64_t n);  // partial maxima launch_max_norm needs in `part`
+hipError_t launch_max_norm(const double* norm, int64_t n, double* part, double* out, hipStream_t st);
 int filter_steps(int D4);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t st);

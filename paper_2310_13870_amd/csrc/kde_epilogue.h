@@ -28,18 +28,19 @@ __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_
 __device__ __forceinline__ int perm_row(int rho) { return 4 * (rho & 3) + (rho >> 2); }
 
 // The D4 operands that the lanes of feature row g supply for point p, one
-// per feature step, from the point's FP64 row (16-byte loads).
+// per feature step, from the point's FP64 row: step pair k of feature row g
+// is the 16 bytes at 64 k + 16 g, so the four feature rows of a point read 64
+// contiguous bytes per load.
 template <int D4>
 __device__ __forceinline__ void load_row_part(double (&dst)[D4], const double* base, int64_t p, int g) {
-    const double* src = base + p * (4 * D4) + g * D4;
     if constexpr (D4 == 1) {
-        dst[0] = src[0];
+        dst[0] = base[p * 4 + g];
     } else {
         typedef double double2_t __attribute__((ext_vector_type(2)));
-        const double2_t* s2 = (const double2_t*)src;
+        const double2_t* s2 = (const double2_t*)(base + p * (4 * D4)) + g;
 #pragma unroll
         for (int k = 0; k < D4 / 2; ++k) {
-            const double2_t v = s2[k];
+            const double2_t v = s2[4 * k];
             dst[2 * k] = v[0];
             dst[2 * k + 1] = v[1];
         }

@@ -1,9 +1,9 @@
 // Filtered segmented KDE on the BF16 matrix cores (precision mode).
 //
 // Every pair first gets an approximate cross term from BF16 hi/lo split
-// operands (hi = bf16(x), lo = bf16(x - hi); one contraction over K = 3d + 2
-// gives hi.hi + hi.lo + lo.hi plus an augmented term -|x|^2/2), accumulated in
-// FP32 by v_mfma_f32_16x16x32_bf16.  A pair can change a row's masses only if
+// operands (hi = bf16(x), lo = bf16(x - hi); one contraction over K = 3d
+// gives hi.hi + hi.lo + lo.hi), accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16 onto an accumulator that starts at -|x|^2/2.  A pair can change a row's masses only if
 // its exponent z = gamma |q-x|^2 is within Delta of the row's smallest one
 // (a term e^-Delta times the largest term of the row is negligible); with a
 // guaranteed bound E on the error of the approximate cross term, the test
@@ -32,7 +32,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // occupancy targets that fit without spilling
 template <int KB>
-constexpr int mask_waves() { return KB <= 4 ? 3 : 2; }
+constexpr int mask_waves() { return KB <= 3 ? 3 : 2; }
 template <int D4>
 constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
 
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 // result rows: query 16 qb + 4 grp + i; keep-threshold on
-                // c~ - |x|^2/2, rounded down to FP32
+                // -|x|^2/2 + c~, rounded down to FP32
                 const int32_t t = 16 * qb + 4 * grp + i;
                 const bool ok = t < ne;
                 const int64_t e = e0 + (ok ? t : 0);
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
         const int64_t be = min(m.n_blocks, bb + m.blocks_per_chunk);
         uint16_t* mrow = m.mask + tile * m.n_blocks;
         bf16x8_t xb[KB], xn[KB];
+        float xa = m.xa[bb * 16 + r], xan = 0.0f;  // -|x|^2/2 of this lane's data column
         const bf16x8_t* X16 = (const bf16x8_t*)m.Xb;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(bb * KB + kb) * 64 + lane];
@@ -106,20 +107,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             if (PREFETCH && b + 1 < be) {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) xn[kb] = X16[((b + 1) * KB + kb) * 64 + lane];
+                xan = m.xa[(b + 1) * 16 + r];
             }
             if (!PREFETCH && b > bb) {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(b * KB + kb) * 64 + lane];
+                xa = m.xa[b * 16 + r];
             }
+            // four independent accumulators, K step outer, so that no matrix
+            // op waits for the previous one's result
+            float4_t cc[4];
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) cc[qb] = float4_t{xa, xa, xa, xa};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb)
+                    cc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], xb[kb], cc[qb], 0, 0, 0);
             uint64_t any = 0;
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb) {
-                float4_t cc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) cc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], xb[kb], cc, 0, 0, 0);
                 const float4_t th = theta_lds[qb * 64 + lane];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) any |= __ballot(cc[i] >= th[i]);
+                for (int i = 0; i < 4; ++i) any |= __ballot(cc[qb][i] >= th[i]);
             }
             uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & 0xFFFFull);
             if (16 * (b + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * b)) - 1u;
@@ -132,6 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             if (PREFETCH) {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) xb[kb] = xn[kb];
+                xa = xan;
             }
         }
     }
@@ -336,8 +347,8 @@ hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
     switch (m.KB) {
         case 1: return launch_mask_t<1>(m, num_cus, st);
         case 2: return launch_mask_t<2>(m, num_cus, st);
-        case 4: return launch_mask_t<4>(m, num_cus, st);
-        case 7: return launch_mask_t<7>(m, num_cus, st);
+        case 3: return launch_mask_t<3>(m, num_cus, st);
+        case 6: return launch_mask_t<6>(m, num_cus, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -364,7 +375,7 @@ hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_b
     }
 }
 
-int split_steps(int d) { return (3 * d + 2 + 31) / 32; }
+int split_steps(int d) { return (3 * d + 31) / 32; }
 
 // K steps the filter kernel is built for, per feature-step class (the split
 // operands of smaller d are zero-padded up to it).
@@ -373,8 +384,8 @@ int filter_steps(int D4) {
         case 1: return 1;
         case 2: return 1;
         case 4: return 2;
-        case 8: return 4;
-        case 16: return 7;
+        case 8: return 3;
+        case 16: return 6;
         default: return -1;
     }
 }
@@ -403,12 +414,14 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Split fragments in the operand layout of v_mfma_f32_16x16x32_bf16: lane l
 // holds 8 consecutive K entries 8(l/16).. of row 16b + l%16.  Data rows are
-// [hi(x), lo(x), hi(x), hi(a), lo(a), 0...] with a = -|x|^2/2, query rows
-// [hi(q), hi(q), lo(q), 1, 1, 0...]; their contraction is hi.hi + hi.lo +
-// lo.hi - |x|^2/2.
+// [hi(x), lo(x), hi(x), 0...], query rows [hi(q), hi(q), lo(q), 0...]; their
+// contraction is hi.hi + hi.lo + lo.hi.  xa = -|x|^2/2 in FP32 seeds the
+// accumulator of each data column.
 __global__ void prep_split_kernel(const float* __restrict__ X, const double* __restrict__ norm, int64_t n, int32_t d,
-                                  int32_t KB, int64_t total, bf16x8_t* __restrict__ Xb, bf16x8_t* __restrict__ Qb) {
+                                  int32_t KB, int64_t total, bf16x8_t* __restrict__ Xb, bf16x8_t* __restrict__ Qb,
+                                  float* __restrict__ xa, int64_t n_pad) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n_pad) xa[idx] = (idx < n) ? (float)(-0.5 * norm[idx]) : 0.0f;
     if (idx >= total) return;
     const int64_t per_blk = (int64_t)KB * 64;
     const int64_t blk = idx / per_blk;
@@ -430,12 +443,6 @@ __global__ void prep_split_kernel(const float* __restrict__ X, const double* __r
                 const int32_t part = k / d;  // 0, 1, 2
                 bd = (part == 1) ? lo : hi;
                 bq = (part == 2) ? lo : hi;
-            } else if (k == 3 * d || k == 3 * d + 1) {
-                const double av = -0.5 * norm[row];
-                const __bf16 ahi = (__bf16)(float)av;
-                const __bf16 alo = (__bf16)(float)(av - (double)(float)ahi);
-                bd = (k == 3 * d) ? ahi : alo;
-                bq = (__bf16)1.0f;
             }
         }
         (void)xd;
@@ -457,6 +464,7 @@ __global__ __launch_bounds__(256) void pivot_kernel(const float* __restrict__ X,
                                                     int32_t* __restrict__ ids) {
     constexpr int CH = 64;  // pivots staged per round
     __shared__ float piv[CH * DMAX];
+    __shared__ int64_t pidx[CH];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
     float xi[DMAX];
@@ -467,10 +475,11 @@ __global__ __launch_bounds__(256) void pivot_kernel(const float* __restrict__ X,
     for (int32_t p0 = 0; p0 < P; p0 += CH) {
         const int32_t pc = min(CH, P - p0);
         __syncthreads();
+        if ((int32_t)threadIdx.x < pc) pidx[threadIdx.x] = ((int64_t)(p0 + threadIdx.x) * n) / P;
+        __syncthreads();
         for (int32_t k = threadIdx.x; k < pc * DMAX; k += blockDim.x) {
             const int32_t pp = k / DMAX, t = k - pp * DMAX;
-            const int64_t j = ((int64_t)(p0 + pp) * n) / P;
-            piv[k] = (t < d) ? X[j * d + t] : 0.0f;
+            piv[k] = (t < d) ? X[pidx[pp] * d + t] : 0.0f;
         }
         __syncthreads();
         for (int32_t pp = 0; pp < pc; ++pp) {
@@ -482,8 +491,7 @@ __global__ __launch_bounds__(256) void pivot_kernel(const float* __restrict__ X,
                 acc[t & 3] = __builtin_fmaf(df, df, acc[t & 3]);
             }
             const float D = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-            const int64_t j = ((int64_t)(p0 + pp) * n) / P;
-            if (j != i && D < best) {
+            if (pidx[pp] != i && D < best) {
                 best = D;
                 arg = (uint32_t)(p0 + pp);
             }
@@ -495,10 +503,29 @@ __global__ __launch_bounds__(256) void pivot_kernel(const float* __restrict__ X,
     ids[i] = (int32_t)i;
 }
 
-__global__ void max_norm_kernel(const double* norm, int64_t n, double* out) {
+// Largest |x|^2 in two stages: block maxima, then one block over them.
+constexpr int kMaxNormBlocks = 512;
+
+__global__ __launch_bounds__(256) void max_norm_kernel(const double* __restrict__ norm, int64_t n,
+                                                       double* __restrict__ part) {
     __shared__ double red[256];
     double m = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, norm[i]);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = fmax(m, norm[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void max_norm_final_kernel(const double* __restrict__ part, int32_t np,
+                                                             double* __restrict__ out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int32_t i = threadIdx.x; i < np; i += 256) m = fmax(m, part[i]);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -509,10 +536,11 @@ __global__ void max_norm_kernel(const double* norm, int64_t n, double* out) {
 }
 
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
-                             void* Xb, void* Qb, hipStream_t st) {
+                             void* Xb, void* Qb, float* xa, hipStream_t st) {
     const int64_t total = (n_pad / 16) * KB * 64;
-    prep_split_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, norm, n, d, KB, total, (bf16x8_t*)Xb,
-                                                                       (bf16x8_t*)Qb);
+    const int64_t threads = total > n_pad ? total : n_pad;
+    prep_split_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(X, norm, n, d, KB, total, (bf16x8_t*)Xb,
+                                                                         (bf16x8_t*)Qb, xa, n_pad);
     return hipGetLastError();
 }
 
@@ -528,8 +556,17 @@ hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double
     return hipGetLastError();
 }
 
-hipError_t launch_max_norm(const double* norm, int64_t n, double* out, hipStream_t st) {
-    max_norm_kernel<<<1, 256, 0, st>>>(norm, n, out);
+int max_norm_parts(int64_t n) {
+    const int64_t b = (n + 2047) / 2048;
+    return (int)(b < 1 ? 1 : (b > kMaxNormBlocks ? kMaxNormBlocks : b));
+}
+
+hipError_t launch_max_norm(const double* norm, int64_t n, double* part, double* out, hipStream_t st) {
+    const int np = max_norm_parts(n);
+    max_norm_kernel<<<np, 256, 0, st>>>(norm, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    max_norm_final_kernel<<<1, 256, 0, st>>>(part, np, out);
     return hipGetLastError();
 }
 

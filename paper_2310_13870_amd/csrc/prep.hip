@@ -9,10 +9,18 @@ __global__ void prep_fragments_kernel(const float* __restrict__ X, int64_t n, in
                                       double* __restrict__ Xp) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
+    // position within the row: (kk / 2) * 8 + g * 2 + kk % 2 (D4 >= 2), g (D4 = 1)
     const int64_t per_row = (int64_t)D4 * 4;
     const int64_t row = idx / per_row;
     const int32_t rem = (int32_t)(idx - row * per_row);
-    const int32_t g = rem / D4, kk = rem - g * D4;
+    int32_t g, kk;
+    if (D4 == 1) {
+        g = rem;
+        kk = 0;
+    } else {
+        g = (rem & 7) >> 1;
+        kk = ((rem >> 3) << 1) | (rem & 1);
+    }
     const int32_t col = kk * 4 + g;
     Xp[idx] = (row < n && col < d) ? (double)X[row * d + col] : 0.0;
 }
