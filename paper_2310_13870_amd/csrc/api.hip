@@ -85,6 +85,82 @@ static fsg_status ws(fsg_ctx* ctx, const char* name, size_t count, T** out) {
 
 static bool gamma_ok(double g) { return std::isfinite(g) && g > 0.0; }
 
+// Largest total of cached point-set blocks; beyond it released blocks are freed.
+constexpr size_t kPoolCacheCap = (size_t)16 << 30;
+
+hipError_t pool_alloc(fsg_ctx* ctx, size_t bytes, void** out) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    auto it = ctx->pool_free.lower_bound(bytes);
+    if (it != ctx->pool_free.end() && it->first <= 2 * bytes) {
+        *out = it->second;
+        ctx->pool_cached -= it->first;
+        ctx->pool_free.erase(it);
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess && !ctx->pool_free.empty()) {
+        // drop the cache and try once more
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& kv : ctx->pool_free) {
+            ctx->pool_size.erase(kv.second);
+            (void)hipFree(kv.second);
+        }
+        ctx->pool_free.clear();
+        ctx->pool_cached = 0;
+        e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) return e;
+    ctx->pool_size[p] = bytes;
+    *out = p;
+    return hipSuccess;
+}
+
+void pool_release(fsg_ctx* ctx, void* p) {
+    if (!p) return;
+    auto it = ctx->pool_size.find(p);
+    if (it == ctx->pool_size.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    if (ctx->pool_cached + it->second > kPoolCacheCap) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(p);
+        ctx->pool_size.erase(it);
+        return;
+    }
+    ctx->pool_free.emplace(it->second, p);
+    ctx->pool_cached += it->second;
+}
+
+void pool_clear(fsg_ctx* ctx) {
+    for (auto& kv : ctx->pool_free) (void)hipFree(kv.second);
+    ctx->pool_free.clear();
+    ctx->pool_size.clear();
+    ctx->pool_cached = 0;
+}
+
+// a point-set array: pooled while the point set is attached to its context
+template <typename T>
+static hipError_t pts_alloc(fsg_points* p, size_t count, T** out) {
+    void* v = nullptr;
+    hipError_t e = p->ctx ? pool_alloc(p->ctx, count * sizeof(T), &v) : hipMalloc(&v, count * sizeof(T));
+    *out = (T*)v;
+    return e;
+}
+
+static void pts_free(fsg_points* p, void* v) {
+    if (!v) return;
+    if (p->ctx) {
+        pool_release(p->ctx, v);
+    } else {
+        (void)hipFree(v);
+    }
+}
+
 static const int32_t* level_bounds(fsg_points* pts, int level, fsg_status* st) {
     auto it = pts->levels.find(level);
     if (it != pts->levels.end()) {
@@ -93,7 +169,7 @@ static const int32_t* level_bounds(fsg_points* pts, int level, fsg_status* st) {
     }
     int32_t* p = nullptr;
     const size_t count = ((size_t)1 << level) + 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(int32_t));
+    hipError_t e = pts_alloc(pts, count, &p);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *st = set_error(pts->ctx, FSG_E_NOMEM, "hipMalloc of tree level boundaries failed");
@@ -101,7 +177,7 @@ static const int32_t* level_bounds(fsg_points* pts, int level, fsg_status* st) {
     }
     e = launch_level_bounds(pts->n, level, p, pts->ctx->stream);
     if (e != hipSuccess) {
-        hipFree(p);
+        pts_free(pts, p);
         *st = set_error(pts->ctx, FSG_E_DEVICE, std::string("level bounds: ") + hipGetErrorString(e));
         return nullptr;
     }
@@ -320,12 +396,16 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
         (void)hipGetLastError();
         return set_error(ctx, FSG_E_NOMEM, std::string("hipMalloc of ") + what + " failed");
     };
-    if (hipMalloc(&p->Xb, split_bytes) != hipSuccess) return fail("split operands");
-    if (hipMalloc(&p->Qb, split_bytes) != hipSuccess) return fail("split operands");
-    if (hipMalloc(&p->dmin, n * sizeof(double)) != hipSuccess) return fail("distance bounds");
-    if (hipMalloc(&p->order, n * sizeof(int32_t)) != hipSuccess) return fail("pivot order");
-    if (hipMalloc(&p->xmax, sizeof(double)) != hipSuccess) return fail("norm bound");
-    if (hipMalloc(&p->xa, p->n_pad * sizeof(float)) != hipSuccess) return fail("norm terms");
+    char* xb = nullptr;
+    char* qb = nullptr;
+    if (pts_alloc(p, split_bytes, &xb) != hipSuccess) return fail("split operands");
+    p->Xb = xb;
+    if (pts_alloc(p, split_bytes, &qb) != hipSuccess) return fail("split operands");
+    p->Qb = qb;
+    if (pts_alloc(p, (size_t)n, &p->dmin) != hipSuccess) return fail("distance bounds");
+    if (pts_alloc(p, (size_t)n, &p->order) != hipSuccess) return fail("pivot order");
+    if (pts_alloc(p, 1, &p->xmax) != hipSuccess) return fail("norm bound");
+    if (pts_alloc(p, (size_t)p->n_pad, &p->xa) != hipSuccess) return fail("norm terms");
     p->bytes += 2 * split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) + p->n_pad * sizeof(float);
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
@@ -391,7 +471,15 @@ fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes
 void fsg_ctx_destroy(fsg_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    for (fsg_points* p : ctx->points) p->ctx = nullptr;  // they stay valid; their destroy syncs the device
+    // live point sets stay valid: their pooled blocks become theirs to free
+    for (fsg_points* p : ctx->points) {
+        for (void* v : {(void*)p->Xp, (void*)p->norm, (void*)p->Xb, (void*)p->Qb, (void*)p->dmin, (void*)p->order,
+                        (void*)p->xmax, (void*)p->xa})
+            if (v) ctx->pool_size.erase(v);
+        for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
+        p->ctx = nullptr;
+    }
+    pool_clear(ctx);
     for (auto& kv : ctx->bufs) (void)hipFree(kv.second.first);
     for (auto& m : ctx->marks) {
         (void)hipEventDestroy(m.second.first);
@@ -492,9 +580,10 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
     p->prec = prec;
     const size_t frag = (size_t)p->n_pad * D4 * 4 * sizeof(double);
     const size_t nrm = (size_t)p->n_pad * sizeof(double);
-    if (hipMalloc(&p->Xp, frag) != hipSuccess || hipMalloc(&p->norm, nrm) != hipSuccess) {
+    if (pts_alloc(p, frag / sizeof(double), &p->Xp) != hipSuccess ||
+        pts_alloc(p, nrm / sizeof(double), &p->norm) != hipSuccess) {
         (void)hipGetLastError();
-        if (p->Xp) hipFree(p->Xp);
+        pts_free(p, p->Xp);
         delete p;
         return set_error(ctx, FSG_E_NOMEM, "hipMalloc of point arrays failed");
     }
@@ -504,8 +593,8 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
         StageTimer t(ctx, "prep");
         e = launch_prep(X_dev, n, d, D4, p->n_pad, p->Xp, p->norm, ctx->stream);
     if (e != hipSuccess) {
-        hipFree(p->Xp);
-        hipFree(p->norm);
+        pts_free(p, p->Xp);
+        pts_free(p, p->norm);
         delete p;
         return set_error(ctx, FSG_E_DEVICE, std::string("prep: ") + hipGetErrorString(e));
     }
@@ -525,20 +614,21 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
 void fsg_points_destroy(fsg_points* p) {
     if (!p) return;
     if (p->ctx) {
-        (void)hipStreamSynchronize(p->ctx->stream);
+        // the arrays go back to the context's pool: work already enqueued on
+        // its stream finishes before any later use of them on that stream
         p->ctx->points.erase(p);
     } else {
         (void)hipDeviceSynchronize();
     }
-    if (p->Xp) (void)hipFree(p->Xp);
-    if (p->norm) (void)hipFree(p->norm);
-    if (p->Xb) (void)hipFree(p->Xb);
-    if (p->Qb) (void)hipFree(p->Qb);
-    if (p->dmin) (void)hipFree(p->dmin);
-    if (p->order) (void)hipFree(p->order);
-    if (p->xmax) (void)hipFree(p->xmax);
-    if (p->xa) (void)hipFree(p->xa);
-    for (auto& kv : p->levels) (void)hipFree(kv.second);
+    pts_free(p, p->Xp);
+    pts_free(p, p->norm);
+    pts_free(p, p->Xb);
+    pts_free(p, p->Qb);
+    pts_free(p, p->dmin);
+    pts_free(p, p->order);
+    pts_free(p, p->xmax);
+    pts_free(p, p->xa);
+    for (auto& kv : p->levels) pts_free(p, kv.second);
     delete p;
 }
 
@@ -765,6 +855,52 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
     const int64_t m = 2 * n * (int64_t)L;
     if (m > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "2*n*L must be < 2^31");
     fsg_status st;
+    // row-sorted construction
+    {
+        int32_t* ent;
+        uint32_t *cnt, *fillc, *off, *off_part;
+        int64_t *uniq, *uniq_part;
+        int32_t* n_long;
+        if ((st = ws(ctx, "csr_ent", (size_t)m + 1, &ent)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_cnt", (size_t)n + 1, &cnt)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_fillc", (size_t)n + 1, &fillc)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_off", (size_t)n + 1, &off)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_off_part", (size_t)scan_partials(n) + 1, &off_part)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_uniq", (size_t)n + 1, &uniq)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_uniq_part", (size_t)scan_partials(n) + 1, &uniq_part)) != FSG_OK) return st;
+        if ((st = ws(ctx, "csr_nlong", 1, &n_long)) != FSG_OK) return st;
+        CsrRowArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.ent = ent;
+        a.off = off;
+        a.n = n;
+        a.d = X->d;
+        a.X = X->X;
+        a.deg = deg_dev;
+        a.s = gamma * 1.442695040888963407359924681001892137;
+        a.L = L;
+        a.row_ptr = row_ptr_dev;
+        a.col = col_dev;
+        a.w = w_dev;
+        a.cap = cap;
+        {
+            StageTimer t(ctx, "csr");
+            FSG_HIP(ctx, launch_csr_rows(a, nbr_dev, L, cnt, fillc, off, off_part, uniq, uniq_part, n_long,
+                                         ctx->stream));
+        }
+        FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, row_ptr_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 1, n_long, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const int32_t longs = (int32_t)(ctx->host_scratch[1] & 0xFFFFFFFF);
+        if (longs == 0) {
+            *nnz = ctx->host_scratch[0];
+            if (*nnz > cap) return set_error(ctx, FSG_E_INVALID, "cap is smaller than 2|E|");
+            return FSG_OK;
+        }
+    }
+    // some row has more than 2048 entries: global sort of all entries
     uint64_t* keys;
     int32_t* vals;
     int64_t* flags;

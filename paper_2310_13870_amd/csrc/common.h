@@ -119,7 +119,13 @@ struct fsg_ctx {
     int64_t* filter_counts = nullptr;  // [kept, scanned]
     // live point sets; detached (their ctx cleared) when the context is destroyed
     std::set<fsg_points*> points;
+    // device blocks of destroyed point sets, kept for reuse by later point
+    // sets on the same stream (size -> block); sizes of every pooled block
+    std::multimap<size_t, void*> pool_free;
+    std::map<void*, size_t> pool_size;
+    size_t pool_cached = 0;
 };
+
 
 struct fsg_points {
     fsg_ctx* ctx = nullptr;
@@ -145,6 +151,12 @@ struct fsg_points {
 };
 
 namespace fsg {
+
+// Point-set memory: stream-ordered reuse of the blocks of destroyed point sets
+// (no hipMalloc / hipFree, hence no device synchronisation, in the steady state).
+hipError_t pool_alloc(fsg_ctx* ctx, size_t bytes, void** out);
+void pool_release(fsg_ctx* ctx, void* p);
+void pool_clear(fsg_ctx* ctx);
 
 // Error helpers: every API function funnels HIP failures through these.
 fsg_status set_error(fsg_ctx* ctx, fsg_status s, const std::string& msg);
@@ -300,6 +312,24 @@ struct CsrArgs {
     float* w;
     int64_t cap;
 };
+
+struct CsrRowArgs {
+    int32_t* ent;            // entries grouped by row, sorted and unique at the start of each row
+    const uint32_t* off;     // start of each row's entries in ent [n + 1]
+    int64_t n;
+    int32_t d;
+    const float* X;
+    const double* deg;
+    double s;                // gamma * log2(e)
+    int32_t L;
+    int64_t* row_ptr;        // [n + 1]: exclusive scan of the unique counts (written by the caller)
+    int32_t* col;
+    float* w;
+    int64_t cap;
+};
+hipError_t launch_csr_rows(const CsrRowArgs& a, const int32_t* nbr, int32_t L, uint32_t* cnt, uint32_t* fillc,
+                           uint32_t* off, uint32_t* off_partials, int64_t* uniq, int64_t* uniq_partials,
+                           int32_t* n_long, hipStream_t st);
 hipError_t launch_csr_fill(const CsrArgs& a, hipStream_t st);
 
 }  // namespace fsg

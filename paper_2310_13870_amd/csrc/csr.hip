@@ -101,4 +101,186 @@ hipError_t launch_csr_fill(const CsrArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Row-sorted construction (no global sort).  Every sample (i, y) adds one
+// entry to row i and one to row y: rows are counted with atomics, scanned,
+// filled in arbitrary order, then each row is sorted and deduplicated by one
+// wave (bitonic sort in registers for rows of <= 64 entries, in LDS up to
+// kRowSortMax); a scan of the unique counts gives row_ptr, and a last pass
+// writes columns and weights.  Rows longer than kRowSortMax are counted in
+// *n_long and left empty; the caller then builds the CSR by the global sort.
+// ---------------------------------------------------------------------------
+__global__ void csr_zero_kernel(uint32_t* cnt, uint32_t* fillc, int64_t n, int32_t* n_long) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) {
+        cnt[i] = 0;
+        fillc[i] = 0;
+    }
+    if (i == 0) *n_long = 0;
+}
+
+__global__ void csr_count_kernel(const int32_t* __restrict__ nbr, int64_t n, int32_t L, uint32_t* __restrict__ cnt) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n * L) return;
+    const int64_t i = s / L;
+    const int32_t y = nbr[s];
+    if (y >= 0 && y < n && y != i) {
+        atomicAdd(&cnt[i], 1u);
+        atomicAdd(&cnt[y], 1u);
+    }
+}
+
+__global__ void csr_scatter_kernel(const int32_t* __restrict__ nbr, int64_t n, int32_t L,
+                                   const uint32_t* __restrict__ off, uint32_t* __restrict__ fillc,
+                                   int32_t* __restrict__ ent) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n * L) return;
+    const int64_t i = s / L;
+    const int32_t y = nbr[s];
+    if (y >= 0 && y < n && y != i) {
+        ent[off[i] + atomicAdd(&fillc[i], 1u)] = y;
+        ent[off[y] + atomicAdd(&fillc[y], 1u)] = (int32_t)i;
+    }
+}
+
+constexpr int kRowSortMax = 2048;
+
+__global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __restrict__ off, int32_t* __restrict__ ent,
+                                                           int64_t* __restrict__ uniq, int64_t n,
+                                                           int32_t* __restrict__ n_long) {
+    __shared__ int32_t buf_all[4][kRowSortMax];
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;  // uniform per wave
+    const uint32_t b = off[row];
+    const int32_t len = (int32_t)(off[row + 1] - b);
+    int32_t* seg = ent + b;
+    if (len <= 64) {
+        int32_t v = lane < len ? seg[lane] : INT32_MAX;
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int32_t o = __shfl_xor(v, j);
+                const bool up = (lane & k) == 0;
+                const bool lower = (lane & j) == 0;
+                v = (lower == up) ? min(v, o) : max(v, o);
+            }
+        }
+        const int32_t prev = __shfl_up(v, 1);
+        const bool keep = lane < len && (lane == 0 || prev != v);
+        const uint64_t mask = __ballot(keep);
+        if (keep) seg[__popcll(mask & ((1ull << lane) - 1ull))] = v;
+        if (lane == 0) uniq[row] = __popcll(mask);
+        return;
+    }
+    if (len > kRowSortMax) {
+        if (lane == 0) {
+            atomicAdd(n_long, 1);
+            uniq[row] = 0;
+        }
+        return;
+    }
+    // LDS bitonic sort of the row padded to a power of two; a wave's own LDS
+    // accesses complete in order, so no barrier beyond the wave is needed
+    int32_t* buf = buf_all[threadIdx.x >> 6];
+    int32_t P = 128;
+    while (P < len) P <<= 1;
+    for (int32_t k = lane; k < P; k += 64) buf[k] = (k < len) ? seg[k] : INT32_MAX;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t k = 2; k <= P; k <<= 1) {
+        for (int32_t j = k >> 1; j > 0; j >>= 1) {
+            for (int32_t t = lane; t < P / 2; t += 64) {
+                const int32_t lo = 2 * t - (t & (j - 1));  // lo has bit j clear
+                const int32_t hi = lo + j;
+                const int32_t x = buf[lo], y = buf[hi];
+                const bool up = (lo & k) == 0;
+                if ((x > y) == up) {
+                    buf[lo] = y;
+                    buf[hi] = x;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    int32_t count = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+        const int32_t k = base + lane;
+        const int32_t v = (k < len) ? buf[k] : INT32_MAX;
+        const int32_t pv = (k > 0 && k < len) ? buf[k - 1] : INT32_MIN;
+        const bool keep = k < len && (k == 0 || pv != v);
+        const uint64_t mask = __ballot(keep);
+        if (keep) seg[count + __popcll(mask & ((1ull << lane) - 1ull))] = v;
+        count += __popcll(mask);
+    }
+    if (lane == 0) uniq[row] = count;
+}
+
+// Columns and weights of row i from its sorted unique entries; the kernel
+// value uses the difference form in FP64 summed in feature order, so both
+// directions of an edge get bit-identical weights.
+__global__ __launch_bounds__(256) void csr_row_fill_kernel(CsrRowArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= a.n) return;
+    const int64_t rp = a.row_ptr[row];
+    const int64_t cnt = a.row_ptr[row + 1] - rp;
+    const int32_t* seg = a.ent + a.off[row];
+    const float* xi = a.X + row * a.d;
+    const bool vec = (a.d & 3) == 0 && (((uintptr_t)a.X) & 15) == 0;
+    for (int64_t k = lane; k < cnt; k += 64) {
+        const int64_t j = seg[k];
+        const float* xj = a.X + j * a.d;
+        double D = 0.0;
+        if (vec) {
+            const float4* vi = (const float4*)xi;
+            const float4* vj = (const float4*)xj;
+            for (int32_t t4 = 0; t4 < (a.d >> 2); ++t4) {
+                const float4 p = vi[t4], q = vj[t4];
+                double df = (double)p.x - (double)q.x;
+                D = __builtin_fma(df, df, D);
+                df = (double)p.y - (double)q.y;
+                D = __builtin_fma(df, df, D);
+                df = (double)p.z - (double)q.z;
+                D = __builtin_fma(df, df, D);
+                df = (double)p.w - (double)q.w;
+                D = __builtin_fma(df, df, D);
+            }
+        } else {
+            for (int32_t t = 0; t < a.d; ++t) {
+                const double df = (double)xi[t] - (double)xj[t];
+                D = __builtin_fma(df, df, D);
+            }
+        }
+        const double kv = exp2_fp64(-a.s * D);
+        const double pi = fmin((double)a.L * kv / a.deg[row], 1.0);
+        const double pj = fmin((double)a.L * kv / a.deg[j], 1.0);
+        const double ph = pi + pj - pi * pj;
+        if (rp + k < a.cap) {
+            a.col[rp + k] = (int32_t)j;
+            a.w[rp + k] = (float)(kv / ph);
+        }
+    }
+}
+
+hipError_t launch_csr_rows(const CsrRowArgs& a, const int32_t* nbr, int32_t L, uint32_t* cnt, uint32_t* fillc,
+                           uint32_t* off, uint32_t* off_partials, int64_t* uniq, int64_t* uniq_partials,
+                           int32_t* n_long, hipStream_t st) {
+    const int64_t n = a.n, ns = n * (int64_t)L;
+    hipError_t e;
+    csr_zero_kernel<<<(unsigned)((n + 1 + 255) / 256), 256, 0, st>>>(cnt, fillc, n, n_long);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    csr_count_kernel<<<(unsigned)((ns + 255) / 256 + 1), 256, 0, st>>>(nbr, n, L, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan_u32(cnt, off, n, off + n, off_partials, st)) != hipSuccess) return e;
+    csr_scatter_kernel<<<(unsigned)((ns + 255) / 256 + 1), 256, 0, st>>>(nbr, n, L, off, fillc, a.ent);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned row_blocks = (unsigned)((n + 1 + 3) / 4);
+    csr_row_sort_kernel<<<row_blocks, 256, 0, st>>>(off, a.ent, uniq, n, n_long);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan_i64(uniq, a.row_ptr, n, a.row_ptr + n, uniq_partials, st)) != hipSuccess) return e;
+    csr_row_fill_kernel<<<row_blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 }  // namespace fsg

@@ -61,3 +61,36 @@ def test_mix32_n100k_bf16_split_sampled_rows():
     assert non_exempt == 0
     pts.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_mix64_n1m_sampled_rows(prec):
+    """n = 1,000,000 points in R^64 (50 components, sigma 3, L 20): a seeded
+    sample of rows against the oracle, each row against all 1e6 points."""
+    import paper_2310_13870_amd as fsg
+    w = workloads.mixture64()
+    X = w.points()
+    ctx = fsg.Context(0)
+    say(f"full size {w.name} {prec}")
+    pts = fsg.Points(ctx, to_dev(X), prec)
+    nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, w.L, w.philox_seed)
+    row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, w.L, nbr, deg)
+    ctx.sync()
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rows = workloads.subsample(w.n, 48, w.extra["subsample_seed"])
+    say("oracle rows")
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows)
+    rel = np.abs(deg[rows] - rdeg) / rdeg
+    say(f"degree max rel err {rel.max():.3e}")
+    assert rel.max() < 1e-9, f"degree max rel err {rel.max()}"
+    mism, exempt, non_exempt = compare_neighbours(nbr[rows], rnbr, rmargin)
+    say(f"sampled-row mismatches {mism} (exempt {exempt}, non-exempt {non_exempt})")
+    assert non_exempt == 0
+    n, L = w.n, w.L
+    assert nbr.min() >= 0 and nbr.max() < n
+    assert not np.any(nbr == np.arange(n)[:, None])
+    rp, c, wt = row_ptr.cpu().numpy(), col.cpu().numpy(), wt.cpu().numpy()
+    assert rp[0] == 0 and rp[-1] == c.size and c.size <= 2 * n * L
+    assert np.all(np.diff(rp) >= 0) and np.all(wt > 0)
+    pts.close()
+    ctx.close()

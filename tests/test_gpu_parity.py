@@ -149,6 +149,36 @@ def test_build_csr(ctx):
     np.testing.assert_allclose(w, rw, rtol=1e-6)
 
 
+@pytest.mark.parametrize("n,L", [(1000, 1), (3000, 5)])
+def test_build_csr_star(ctx, n, L):
+    """A centre that every other point samples: its row holds about n L
+    entries before deduplication (sorted in LDS for n L <= 2048, by the global
+    sort beyond), every other row a handful."""
+    say(f"csr star n={n} L={L}")
+    rng = np.random.default_rng(n + L)
+    d = 128
+    u = rng.standard_normal((n, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    u[0] = 0.0
+    X = u.astype(np.float32)
+    # the centre is at squared distance 1 from every point; random directions
+    # in 128 dimensions are about sqrt(2) apart, so with gamma 100 every point
+    # samples the centre with probability above 0.99
+    gamma = 100.0
+    pts = fsg.Points(ctx, to_dev(X))
+    nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 3)
+    nbr_h = nbr.cpu().numpy()
+    assert (nbr_h[1:] == 0).mean() > 0.99
+    row_ptr, col, w = fsg.build_csr(ctx, pts, gamma, L, nbr, deg)
+    rdeg = oracle.degrees(X, gamma)
+    rrp, rcol, rw = oracle.build_csr(X, gamma, L, nbr_h, rdeg)
+    row_ptr, col, w = row_ptr.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    assert row_ptr[1] - row_ptr[0] >= 0.99 * (n - 1)
+    assert np.array_equal(row_ptr, rrp)
+    assert np.array_equal(col, rcol)
+    np.testing.assert_allclose(w, rw, rtol=1e-6)
+
+
 def test_deterministic(ctx):
     X = _mix(5000, 16, 5)
     pts = fsg.Points(ctx, to_dev(X))
@@ -176,6 +206,35 @@ def test_points_outlive_context():
     pts = fsg.Points(c, to_dev(np.zeros((50, 2), dtype=np.float32)))
     c.close()
     pts.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_pooled_point_arrays_reused(prec):
+    """A point set built from blocks another point set released (the
+    context's pool) gives exactly what it gives on a fresh context."""
+    say(f"pool reuse {prec}")
+    XA = _mix(3000, 32, 11)
+    XB = _mix(2500, 16, 12)
+    gamma, L, seed = 0.1, 5, 77
+    fresh = fsg.Context(0)
+    pb = fsg.Points(fresh, to_dev(XB), prec)
+    ref_nbr, ref_deg, _ = fsg.sample_edges(fresh, pb, gamma, L, seed)
+    ref_nbr, ref_deg = ref_nbr.cpu().numpy(), ref_deg.cpu().numpy()
+    pb.close()
+    fresh.close()
+    c = fsg.Context(0)
+    try:
+        for _ in range(2):
+            pa = fsg.Points(c, to_dev(XA), prec)
+            fsg.sample_edges(c, pa, gamma, L, seed)
+            pa.close()
+            pb = fsg.Points(c, to_dev(XB), prec)
+            nbr, deg, _ = fsg.sample_edges(c, pb, gamma, L, seed)
+            pb.close()
+            assert np.array_equal(nbr.cpu().numpy(), ref_nbr)
+            assert np.array_equal(deg.cpu().numpy(), ref_deg)
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("cap", [1, 2, 3, 5])
