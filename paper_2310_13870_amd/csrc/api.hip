@@ -872,7 +872,7 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
         CsrRowArgs a;
         std::memset(&a, 0, sizeof(a));
         a.ent = ent;
-        a.off = off;
+        a.in_off = off;
         a.n = n;
         a.d = X->d;
         a.X = X->X;

@@ -315,7 +315,7 @@ struct CsrArgs {
 
 struct CsrRowArgs {
     int32_t* ent;            // entries grouped by row, sorted and unique at the start of each row
-    const uint32_t* off;     // start of each row's entries in ent [n + 1]
+    const uint32_t* in_off;  // exclusive scan of the incoming counts [n + 1]; row i starts at L i + in_off[i]
     int64_t n;
     int32_t d;
     const float* X;

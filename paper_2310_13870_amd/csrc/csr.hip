@@ -102,13 +102,15 @@ hipError_t launch_csr_fill(const CsrArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Row-sorted construction (no global sort).  Every sample (i, y) adds one
-// entry to row i and one to row y: rows are counted with atomics, scanned,
-// filled in arbitrary order, then each row is sorted and deduplicated by one
-// wave (bitonic sort in registers for rows of <= 64 entries, in LDS up to
-// kRowSortMax); a scan of the unique counts gives row_ptr, and a last pass
-// writes columns and weights.  Rows longer than kRowSortMax are counted in
-// *n_long and left empty; the caller then builds the CSR by the global sort.
+// Row-sorted construction (no global sort).  Row i of the entry array holds
+// L slots for i's own samples (INT32_MAX where a sample gave no edge) followed
+// by one slot per sample (j, i) of another point: the incoming entries are
+// counted with atomics, scanned and filled in arbitrary order, then each row
+// is sorted and deduplicated by one wave (bitonic sort in registers for rows
+// of <= 64 slots, in LDS up to kRowSortMax); a scan of the unique counts gives
+// row_ptr, and a last pass writes columns and weights.  Rows longer than
+// kRowSortMax are counted in *n_long and left empty; the caller then builds
+// the CSR by the global sort.  Row i starts at L i + in_off[i].
 // ---------------------------------------------------------------------------
 __global__ void csr_zero_kernel(uint32_t* cnt, uint32_t* fillc, int64_t n, int32_t* n_long) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,36 +126,32 @@ __global__ void csr_count_kernel(const int32_t* __restrict__ nbr, int64_t n, int
     if (s >= n * L) return;
     const int64_t i = s / L;
     const int32_t y = nbr[s];
-    if (y >= 0 && y < n && y != i) {
-        atomicAdd(&cnt[i], 1u);
-        atomicAdd(&cnt[y], 1u);
-    }
+    if (y >= 0 && y < n && y != i) atomicAdd(&cnt[y], 1u);
 }
 
 __global__ void csr_scatter_kernel(const int32_t* __restrict__ nbr, int64_t n, int32_t L,
-                                   const uint32_t* __restrict__ off, uint32_t* __restrict__ fillc,
+                                   const uint32_t* __restrict__ in_off, uint32_t* __restrict__ fillc,
                                    int32_t* __restrict__ ent) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n * L) return;
     const int64_t i = s / L;
     const int32_t y = nbr[s];
-    if (y >= 0 && y < n && y != i) {
-        ent[off[i] + atomicAdd(&fillc[i], 1u)] = y;
-        ent[off[y] + atomicAdd(&fillc[y], 1u)] = (int32_t)i;
-    }
+    const bool ok = y >= 0 && y < n && y != i;
+    ent[(int64_t)in_off[i] + s] = ok ? y : INT32_MAX;  // own slot l of row i: L i + in_off[i] + l
+    if (ok) ent[(int64_t)L * y + in_off[y] + L + atomicAdd(&fillc[y], 1u)] = (int32_t)i;
 }
 
 constexpr int kRowSortMax = 2048;
 
-__global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __restrict__ off, int32_t* __restrict__ ent,
-                                                           int64_t* __restrict__ uniq, int64_t n,
-                                                           int32_t* __restrict__ n_long) {
+__global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __restrict__ in_off, int32_t L,
+                                                           int32_t* __restrict__ ent, int64_t* __restrict__ uniq,
+                                                           int64_t n, int32_t* __restrict__ n_long) {
     __shared__ int32_t buf_all[4][kRowSortMax];
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;  // uniform per wave
-    const uint32_t b = off[row];
-    const int32_t len = (int32_t)(off[row + 1] - b);
+    const int64_t b = (int64_t)L * row + in_off[row];
+    const int32_t len = (int32_t)(L + in_off[row + 1] - in_off[row]);
     int32_t* seg = ent + b;
     if (len <= 64) {
         int32_t v = lane < len ? seg[lane] : INT32_MAX;
@@ -166,7 +164,7 @@ __global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __res
             }
         }
         const int32_t prev = __shfl_up(v, 1);
-        const bool keep = lane < len && (lane == 0 || prev != v);
+        const bool keep = v != INT32_MAX && (lane == 0 || prev != v);
         const uint64_t mask = __ballot(keep);
         if (keep) seg[__popcll(mask & ((1ull << lane) - 1ull))] = v;
         if (lane == 0) uniq[row] = __popcll(mask);
@@ -208,7 +206,7 @@ __global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __res
         const int32_t k = base + lane;
         const int32_t v = (k < len) ? buf[k] : INT32_MAX;
         const int32_t pv = (k > 0 && k < len) ? buf[k - 1] : INT32_MIN;
-        const bool keep = k < len && (k == 0 || pv != v);
+        const bool keep = v != INT32_MAX && (k == 0 || pv != v);
         const uint64_t mask = __ballot(keep);
         if (keep) seg[count + __popcll(mask & ((1ull << lane) - 1ull))] = v;
         count += __popcll(mask);
@@ -225,7 +223,7 @@ __global__ __launch_bounds__(256) void csr_row_fill_kernel(CsrRowArgs a) {
     if (row >= a.n) return;
     const int64_t rp = a.row_ptr[row];
     const int64_t cnt = a.row_ptr[row + 1] - rp;
-    const int32_t* seg = a.ent + a.off[row];
+    const int32_t* seg = a.ent + (int64_t)a.L * row + a.in_off[row];
     const float* xi = a.X + row * a.d;
     const bool vec = (a.d & 3) == 0 && (((uintptr_t)a.X) & 15) == 0;
     for (int64_t k = lane; k < cnt; k += 64) {
@@ -276,7 +274,7 @@ hipError_t launch_csr_rows(const CsrRowArgs& a, const int32_t* nbr, int32_t L, u
     csr_scatter_kernel<<<(unsigned)((ns + 255) / 256 + 1), 256, 0, st>>>(nbr, n, L, off, fillc, a.ent);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const unsigned row_blocks = (unsigned)((n + 1 + 3) / 4);
-    csr_row_sort_kernel<<<row_blocks, 256, 0, st>>>(off, a.ent, uniq, n, n_long);
+    csr_row_sort_kernel<<<row_blocks, 256, 0, st>>>(off, L, a.ent, uniq, n, n_long);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_exclusive_scan_i64(uniq, a.row_ptr, n, a.row_ptr + n, uniq_partials, st)) != hipSuccess) return e;
     csr_row_fill_kernel<<<row_blocks, 256, 0, st>>>(a);
