@@ -67,11 +67,13 @@ def cpu_baseline(X, w, target_s: float):
     import oracle
     import workloads
     n, L = w.n, w.L
-    rows = workloads.subsample(n, 8, 4242)
+    # calibrate on two rows per thread, so that every core is busy
+    c = max(8, 2 * oracle.num_threads())
+    rows = workloads.subsample(n, min(n, c), 4242)
     t0 = time.perf_counter()
     oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=False)
     t1 = time.perf_counter() - t0
-    m = int(min(n, max(8, round(8 * target_s / max(t1, 1e-6)))))
+    m = int(min(n, max(8, round(len(rows) * target_s / max(t1, 1e-6)))))
     rows = workloads.subsample(n, m, 4243)
     t0 = time.perf_counter()
     oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=False)
