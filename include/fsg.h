@@ -166,6 +166,75 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
                          const double* deg_dev, int64_t* row_ptr_dev, int32_t* col_dev, float* w_dev,
                          int64_t cap, int64_t* nnz);
 
+/* ------------------------------------------------------------------------
+ * Batching: many independent graph builds (Algorithm 2's sampling loop, as in
+ * fsg_sample_edges, per point set) advanced together.  A job runs its stages
+ * in order: the root pass (binned KDE over all its points, then the descent),
+ * later binned passes, the leaf stage.  fsg_batch_step advances every
+ * unfinished job in `jobs` by one stage; the root passes of all jobs that
+ * share a feature-step class and precision run as ONE launch of the KDE
+ * kernels (every (point set, query tile, bin run) work item of those jobs in
+ * one persistent grid).  Results equal fsg_sample_edges on the same inputs,
+ * bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct fsg_job fsg_job;
+
+/* A build of X with kernel scale gamma, L samples per point and Philox seed
+ * `seed`.  X must outlive the job.  The job owns device buffers for its
+ * samples, degrees and root-pass masses (from the context's pool; about
+ * n*2^D*8 bytes with 2^D ~ n/48 for the root bins).  FSG_E_INVALID on bad
+ * arguments, FSG_E_NOMEM if the buffers cannot be allocated. */
+fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, uint64_t seed, fsg_job** out);
+
+/* Advance every unfinished job by one stage (jobs must belong to ctx; a job
+ * may appear once).  *n_done (host) receives the number of jobs in `jobs`
+ * that have finished.  Enqueues work only: no synchronisation, so a sequence
+ * of calls can be captured with fsg_graph_begin/fsg_graph_end. */
+fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, int32_t* n_done);
+
+/* Rewind a job to its first stage (its buffers are kept). */
+fsg_status fsg_job_reset(fsg_job* job);
+
+/* Enqueue copies of a finished job's result: nbr_dev int32 [n*L] as in
+ * fsg_sample_edges, deg_dev FP64 [n] (either may be NULL).  FSG_E_INVALID if
+ * the job has not finished. */
+fsg_status fsg_job_result(fsg_job* job, int32_t* nbr_dev, double* deg_dev);
+
+/* Device pointers of a job's own result arrays (valid until destroy). */
+fsg_status fsg_job_outputs(fsg_job* job, const int32_t** nbr_dev, const double** deg_dev);
+
+/* Release a job (its buffers return to the context's pool). */
+void fsg_job_destroy(fsg_job* job);
+
+/* Launch shapes of batched root passes are autotuned when enabled (default
+ * on): the first batch of a new shape class times a few candidates with HIP
+ * events and keeps the fastest for the context — in the plain path the grid
+ * size and the data columns per work item, in the precision mode the data
+ * columns per keep-mask work item.  Results do not depend on the shape (the
+ * precision mode's exact pass keeps the single-set item shape, which decides
+ * its rounding order).  Tuning is skipped while the stream is being captured. */
+fsg_status fsg_ctx_set_autotune(fsg_ctx* ctx, int32_t enabled);
+
+/* The shape tuned for a class (feature steps D4 in {1,2,4,8,16,32},
+ * precision): waves per compute unit and data columns per work item (per
+ * keep-mask work item in the precision mode).  FSG_E_INVALID if that class
+ * has not been tuned. */
+fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int32_t* waves_per_cu,
+                               int32_t* cols_per_item);
+
+/* ------------------------------------------------------------------------
+ * HIP graphs of the context's stream: everything enqueued between
+ * fsg_graph_begin and fsg_graph_end (which must not synchronise; e.g.
+ * fsg_batch_step, fsg_sample_edges) is recorded into a graph that
+ * fsg_graph_launch replays on the stream.  The recorded calls must have run
+ * once before (so that no workspace grows while recording).
+ * ------------------------------------------------------------------------ */
+typedef struct fsg_graph fsg_graph;
+fsg_status fsg_graph_begin(fsg_ctx* ctx);
+fsg_status fsg_graph_end(fsg_ctx* ctx, fsg_graph** out);
+fsg_status fsg_graph_launch(fsg_ctx* ctx, fsg_graph* g);
+void fsg_graph_destroy(fsg_graph* g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,19 @@ _lib_fns = dict(
     fsg_sample_edges=_sig("fsg_sample_edges", ctypes.c_int, _vp, _vp, _dbl, _i32, _u64, _vp, _vp, _vp),
     fsg_build_csr=_sig("fsg_build_csr", ctypes.c_int, _vp, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
                        ctypes.POINTER(_i64)),
+    fsg_job_create=_sig("fsg_job_create", ctypes.c_int, _vp, _vp, _dbl, _i32, _u64, ctypes.POINTER(_vp)),
+    fsg_batch_step=_sig("fsg_batch_step", ctypes.c_int, _vp, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i32)),
+    fsg_job_reset=_sig("fsg_job_reset", ctypes.c_int, _vp),
+    fsg_job_result=_sig("fsg_job_result", ctypes.c_int, _vp, _vp, _vp),
+    fsg_job_outputs=_sig("fsg_job_outputs", ctypes.c_int, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)),
+    fsg_job_destroy=_sig("fsg_job_destroy", None, _vp),
+    fsg_ctx_set_autotune=_sig("fsg_ctx_set_autotune", ctypes.c_int, _vp, _i32),
+    fsg_ctx_tuned_shape=_sig("fsg_ctx_tuned_shape", ctypes.c_int, _vp, _i32, ctypes.c_int, ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i32)),
+    fsg_graph_begin=_sig("fsg_graph_begin", ctypes.c_int, _vp),
+    fsg_graph_end=_sig("fsg_graph_end", ctypes.c_int, _vp, ctypes.POINTER(_vp)),
+    fsg_graph_launch=_sig("fsg_graph_launch", ctypes.c_int, _vp, _vp),
+    fsg_graph_destroy=_sig("fsg_graph_destroy", None, _vp),
 )
 EXPORTED = sorted(_lib_fns)
 
@@ -129,6 +142,17 @@ class Context:
     @property
     def workspace_bytes(self) -> int:
         return int(_lib.fsg_ctx_workspace_bytes(self._h))
+
+    def set_autotune(self, enabled: bool):
+        self.check(_lib.fsg_ctx_set_autotune(self._h, 1 if enabled else 0))
+
+    def tuned_shape(self, D4: int, precision=FSG_FP32):
+        """(waves per CU, data columns per work item) tuned for a class, or None."""
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        w, c = _i32(0), _i32(0)
+        st = _lib.fsg_ctx_tuned_shape(self._h, D4, precision, ctypes.byref(w), ctypes.byref(c))
+        return (w.value, c.value) if st == FSG_OK else None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -232,3 +256,84 @@ def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int, 
     nbr, deg, _ = sample_edges(ctx, pts, gamma, L, seed)
     row_ptr, col, w = build_csr(ctx, pts, gamma, L, nbr, deg)
     return row_ptr, col, w, nbr, deg
+
+
+class Job:
+    """fsg_job: one graph build advanced by batch_step together with others."""
+
+    def __init__(self, ctx: Context, pts: Points, gamma: float, L: int, seed: int):
+        self.ctx, self.pts, self.gamma, self.L, self.seed = ctx, pts, gamma, L, seed
+        h = _vp()
+        ctx.check(_lib.fsg_job_create(ctx._h, pts._h, gamma, L, seed, ctypes.byref(h)))
+        self._h = h
+
+    def reset(self):
+        self.ctx.check(_lib.fsg_job_reset(self._h))
+
+    def result(self, nbr: torch.Tensor = None, deg: torch.Tensor = None):
+        dev = self.pts.X.device
+        if nbr is None:
+            nbr = torch.empty((self.pts.n, self.L), dtype=torch.int32, device=dev)
+        if deg is None:
+            deg = torch.empty(self.pts.n, dtype=torch.float64, device=dev)
+        self.ctx.check(_lib.fsg_job_result(self._h, _ptr(nbr), _ptr(deg)))
+        return nbr, deg
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsg_job_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_step(ctx: Context, jobs) -> int:
+    """Advance every unfinished job by one stage; returns how many have finished."""
+    arr = (_vp * max(len(jobs), 1))(*[j._h for j in jobs])
+    done = _i32(0)
+    ctx.check(_lib.fsg_batch_step(ctx._h, arr, len(jobs), ctypes.byref(done)))
+    return done.value
+
+
+def batch_run(ctx: Context, jobs) -> int:
+    """batch_step until every job has finished; returns the number of steps."""
+    steps = 0
+    while True:
+        steps += 1
+        if batch_step(ctx, jobs) == len(jobs):
+            return steps
+
+
+class Graph:
+    """fsg_graph: the work enqueued between begin() and end() on the context's
+    stream, replayed by launch()."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self._h = None
+
+    def begin(self):
+        self.ctx.check(_lib.fsg_graph_begin(self.ctx._h))
+
+    def end(self):
+        h = _vp()
+        self.ctx.check(_lib.fsg_graph_end(self.ctx._h, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        self.ctx.check(_lib.fsg_graph_launch(self.ctx._h, self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsg_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <new>
 
+#include <algorithm>
+#include <cmath>
 #include "common.h"
 
 namespace fsg {
@@ -263,6 +265,18 @@ static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma) 
 // e^-kMarginExtra (1.4e-11) of the row's degree.
 constexpr double kMarginExtra = 25.0;
 
+// Bins per work item of a root pass: about 32 items per wave of the grid.
+// In the precision mode the item boundaries decide how kept columns are
+// grouped, hence the rounding order of the bin sums, so every root pass of a
+// point set uses this one rule.
+static int32_t root_bins_per_item(const fsg_ctx* ctx, int64_t tiles, int32_t nbins) {
+    const int64_t waves = (int64_t)ctx->num_cus * 8;
+    int64_t chunks = (32 * waves + tiles - 1) / tiles;
+    if (chunks > nbins) chunks = nbins;
+    if (chunks < 1) chunks = 1;
+    return (int32_t)((nbins + chunks - 1) / chunks);
+}
+
 // Binned KDE of all n points against the nodes of tree level D (one segment).
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
@@ -270,12 +284,9 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if (!bnd) return st;
     const int64_t n = X->n;
     const int32_t nbins = 1 << D;
-    const int64_t tiles = (n + kTileQ - 1) / kTileQ;
-    const int64_t waves = (int64_t)ctx->num_cus * 8;
-    int64_t chunks = (32 * waves + tiles - 1) / tiles;
-    if (chunks > nbins) chunks = nbins;
-    if (chunks < 1) chunks = 1;
-    const int32_t bpc = (int32_t)((nbins + chunks - 1) / chunks);
+    const int32_t tile = kde_tile(X->D4);
+    const int64_t tiles = (n + tile - 1) / tile;
+    const int32_t bpc = root_bins_per_item(ctx, tiles, nbins);
     const int64_t n_items = tiles * ((nbins + bpc - 1) / bpc);
     WorkItem* items;
     SegDesc* segs;
@@ -284,7 +295,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if ((st = ws(ctx, "root_segs", 1, &segs)) != FSG_OK) return st;
     if ((st = ws(ctx, "root_nitems", 1, &n_items_dev)) != FSG_OK) return st;
     FSG_HIP(ctx, launch_uniform_segs(segs, 1, 0, nbins, ctx->stream));
-    FSG_HIP(ctx, launch_regular_items(n, nbins, bpc, kTileQ, items, n_items_dev, ctx->stream));
+    FSG_HIP(ctx, launch_regular_items(n, nbins, bpc, tile, items, n_items_dev, ctx->stream));
     KdeArgs a = kde_args(X, X, gamma);
     a.q_idx = nullptr;
     a.self_mode = SELF_POINT;
@@ -338,8 +349,9 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         if ((st = ws(ctx, "exact_next_item", 1, &next_item)) != FSG_OK) return st;
         FSG_HIP(ctx, launch_fill_i64(next_item, 1, 0, ctx->stream));
         StageTimer t(ctx, "kde_root");
-        FSG_HIP(ctx, launch_exact_kept(a, m.mask, m.n_blocks, n_items, (unsigned long long*)next_item, ctx->num_cus,
-                                       ctx->stream));
+        a.mask = m.mask;
+        a.n_blocks = m.n_blocks;
+        FSG_HIP(ctx, launch_exact_kept(a, n_items, (unsigned long long*)next_item, ctx->num_cus, ctx->stream));
         return FSG_OK;
     }
     {
@@ -422,6 +434,500 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     return FSG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// One build's sampling state, advanced stage by stage: the root pass (binned
+// KDE over all points, then the descent over its bins), later binned passes,
+// and the leaf stage.  fsg_sample_edges runs the stages back to back; a batch
+// job runs one stage per fsg_batch_step (the root passes of many jobs share
+// launches).
+// ---------------------------------------------------------------------------
+struct Sampler {
+    fsg_points* X = nullptr;
+    double gamma = 0.0;
+    int32_t L = 0;
+    uint64_t seed = 0;
+    Plan plan;
+    int64_t ns = 0;
+    int32_t n_uleaf = 0;
+    int32_t* node = nullptr;   // [ns] current node of every sample
+    double* uleaf = nullptr;   // [ns][n_uleaf] uniforms of the leaf levels (or NULL)
+    double* deg = nullptr;     // [n] degrees (NULL: not wanted)
+    int32_t* nbr = nullptr;    // [ns] result
+    float* margin = nullptr;   // [ns] optional decision margins
+};
+
+static fsg_status sampler_plan(fsg_ctx* ctx, Sampler& S) {
+    S.ns = S.X->n * (int64_t)S.L;
+    if (S.ns > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "n*L must be < 2^31");
+    S.plan = make_plan(S.X->n, S.L, ctx->budget, ctx->max_levels_per_pass);
+    S.n_uleaf = (!S.plan.passes.empty()) ? tree_depth(S.X->n) - S.plan.leaf_level : 0;
+    return FSG_OK;
+}
+
+static DescArgs desc_args(const Sampler& S, size_t p) {
+    DescArgs da;
+    std::memset(&da, 0, sizeof(da));
+    da.D = S.plan.passes[p].second;
+    da.start_level = S.plan.passes[p].first;
+    da.L = S.L;
+    da.seed = S.seed;
+    da.node = S.node;
+    da.margin = S.margin;
+    if (p + 1 == S.plan.passes.size() && S.uleaf != nullptr && S.n_uleaf > 0) {
+        da.uleaf = S.uleaf;
+        da.n_uleaf = S.n_uleaf;
+    }
+    return da;
+}
+
+// descent over the root pass's bins M [n][2^D]
+static fsg_status stage_root_descend(fsg_ctx* ctx, const Sampler& S, const double* M) {
+    DescArgs da = desc_args(S, 0);
+    da.M = M;
+    da.n_entries = S.X->n;
+    da.entry_sample = nullptr;
+    da.deg = S.deg;
+    StageTimer t(ctx, "descend");
+    FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
+    return FSG_OK;
+}
+
+// later binned pass p >= 1: samples grouped by node, binned KDE of every
+// sample's point over its node, descent
+static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
+    fsg_points* X = S.X;
+    const int start = S.plan.passes[p].first, D = S.plan.passes[p].second;
+    const int32_t nbins = 1 << D;
+    const int64_t ns = S.ns;
+    fsg_status st;
+    int32_t *sorted, *starts;
+    if ((st = group_by_node(ctx, S.node, ns, start, &sorted, &starts)) != FSG_OK) return st;
+    const int64_t n_nodes = (int64_t)1 << start;
+    const int32_t* bnd = level_bounds(X, start + D, &st);
+    if (!bnd) return st;
+    int64_t* q_ptr;
+    int32_t* q_idx;
+    SegDesc* segs;
+    WorkItem* items;
+    int32_t* n_items;
+    int64_t* scratch;
+    double* M;
+    const int32_t tile = kde_tile(X->D4);
+    const int64_t max_items = ns / tile + n_nodes + 1;
+    if ((st = ws(ctx, "pass_qptr", (size_t)n_nodes + 1, &q_ptr)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pass_qidx", (size_t)ns, &q_idx)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pass_segs", (size_t)n_nodes, &segs)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pass_items", (size_t)max_items, &items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pass_nitems", 1, &n_items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pass_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) != FSG_OK)
+        return st;
+    if ((st = ws(ctx, "pass_masses", (size_t)ns << D, &M)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_node_qptr(starts, n_nodes, q_ptr, ctx->stream));
+    FSG_HIP(ctx, launch_entry_points(sorted, ns, S.L, q_idx, ctx->stream));
+    FSG_HIP(ctx, launch_uniform_segs(segs, n_nodes, nbins, nbins, ctx->stream));
+    FSG_HIP(ctx, launch_build_items(q_ptr, n_nodes, nbins, nbins, tile, scratch, items, n_items, max_items,
+                                    ctx->stream));
+    KdeArgs a = kde_args(X, X, S.gamma);
+    a.q_idx = q_idx;
+    a.self_idx = q_idx;
+    a.self_mode = SELF_ARRAY;
+    a.bounds = bnd;
+    a.segs = segs;
+    a.items = items;
+    a.n_items = n_items;
+    a.out = M;
+    a.out_stride = nbins;
+    {
+        StageTimer t(ctx, "kde_pass");
+        FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
+    }
+    DescArgs da = desc_args(S, p);
+    da.M = M;
+    da.n_entries = ns;
+    da.entry_sample = sorted;
+    da.deg = nullptr;
+    StageTimer t(ctx, "descend");
+    FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
+    return FSG_OK;
+}
+
+// leaf stage: nodes of at most kLeafMax points resolved with exact kernel
+// values; the degrees come from here too when there was no binned pass
+static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
+    fsg_points* X = S.X;
+    const int64_t ns = S.ns;
+    fsg_status st;
+    int32_t *sorted, *starts;
+    if ((st = group_by_node(ctx, S.node, ns, S.plan.leaf_level, &sorted, &starts)) != FSG_OK) return st;
+    const int64_t n_nodes = (int64_t)1 << S.plan.leaf_level;
+    const int32_t* bnd = level_bounds(X, S.plan.leaf_level, &st);
+    if (!bnd) return st;
+    int32_t* items;
+    int32_t* n_items;
+    int64_t* scratch;
+    const int64_t max_items = ns / 64 + n_nodes + 1;
+    if ((st = ws(ctx, "leaf_items", (size_t)(2 * max_items), &items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "leaf_nitems", 1, &n_items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) != FSG_OK)
+        return st;
+    {
+        StageTimer t(ctx, "leaf");
+        FSG_HIP(ctx, launch_leaf_items(starts, n_nodes, scratch, items, n_items, ctx->stream));
+        LeafArgs la;
+        std::memset(&la, 0, sizeof(la));
+        la.X = X->X;
+        la.n = X->n;
+        la.d = X->d;
+        la.bounds = bnd;
+        la.level = S.plan.leaf_level;
+        la.s = S.gamma * 1.442695040888963407359924681001892137;
+        la.L = S.L;
+        la.seed = S.seed;
+        la.sorted_samples = sorted;
+        la.node_start = starts;
+        la.items = items;
+        la.n_items = n_items;
+        la.nbr = S.nbr;
+        la.margin = S.margin;
+        la.uleaf = S.plan.passes.empty() ? nullptr : S.uleaf;
+        la.n_uleaf = S.plan.passes.empty() ? 0 : S.n_uleaf;
+        FSG_HIP(ctx, launch_leaf(la, max_items, ctx->num_cus, ctx->stream));
+        FSG_HIP(ctx, launch_finish_inactive(S.node, ns, S.nbr, ctx->stream));
+    }
+    return FSG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batching: jobs, and the root pass of many jobs in one launch.
+// ---------------------------------------------------------------------------
+static fsg_status ensure_filter_counts(fsg_ctx* ctx) {
+    if (ctx->filter_counts != nullptr) return FSG_OK;
+    if (hipMalloc(&ctx->filter_counts, 2 * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, FSG_E_NOMEM, "hipMalloc of filter statistics failed");
+    }
+    FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
+    return FSG_OK;
+}
+
+// Device tables of one group of jobs (same feature-step class and precision)
+// for one launch shape; built once per (jobs, shape) and reused, so that
+// repeated batches (and graph replays) upload nothing.
+struct BatchTables {
+    std::vector<fsg_job*> jobs;
+    int waves_per_cu = 8;
+    int cols = 2048;
+    void* dev = nullptr;        // one block: KdeArgs[G] SegDesc[G] BatchItemDesc[G+1] MaskArgs[G] int64[G+1] counter
+    void* host = nullptr;       // pinned staging of the same layout
+    size_t bytes = 0;
+    WorkItem* items = nullptr;  // [total_items]
+    int32_t* n_items = nullptr;
+    int64_t total_items = 0;
+    int64_t mask_items = 0;
+    int64_t scanned = 0;        // (column, tile) pairs the filter examines
+    KdeArgs a0;                 // launch arguments (job tables bound)
+    MaskArgs m0;
+    unsigned long long* counter = nullptr;
+};
+
+static void free_tables(BatchTables* T) {
+    if (T->dev) (void)hipFree(T->dev);
+    if (T->items) (void)hipFree(T->items);
+    if (T->host) (void)hipHostFree(T->host);
+    delete T;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace fsg
+
+struct fsg_job {
+    fsg_ctx* ctx = nullptr;
+    fsg::Sampler S;
+    int stage = 0;
+    int n_stages = 0;
+    int root_D = 0;
+    double* M = nullptr;       // root-pass bins [n][2^root_D]
+    uint16_t* mask = nullptr;  // precision mode: keep masks of the root pass
+    std::vector<void*> owned;  // device blocks from the context's pool
+};
+
+struct fsg_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace fsg {
+
+static void* job_alloc(fsg_job* j, size_t bytes, fsg_status* st) {
+    void* p = nullptr;
+    if (pool_alloc(j->ctx, bytes, &p) != hipSuccess) {
+        (void)hipGetLastError();
+        *st = set_error(j->ctx, FSG_E_NOMEM, "hipMalloc of job buffers failed");
+        return nullptr;
+    }
+    j->owned.push_back(p);
+    return p;
+}
+
+static void batch_cache_drop(fsg_ctx* ctx, const fsg_job* j) {
+    auto& c = ctx->batch_cache;
+    for (size_t i = 0; i < c.size();) {
+        if (std::find(c[i]->jobs.begin(), c[i]->jobs.end(), j) != c[i]->jobs.end()) {
+            (void)hipStreamSynchronize(ctx->stream);
+            free_tables(c[i]);
+            c.erase(c.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+// the arguments of job j's root pass as a plain single-set launch would use them
+static fsg_status job_root_args(fsg_ctx* ctx, fsg_job* j, KdeArgs* a, MaskArgs* m) {
+    fsg_points* X = j->S.X;
+    fsg_status st;
+    const int32_t* bnd = level_bounds(X, j->root_D, &st);
+    if (!bnd) return st;
+    const int64_t n = X->n;
+    *a = kde_args(X, X, j->S.gamma);
+    a->self_mode = SELF_POINT;
+    a->bounds = bnd;
+    a->out = j->M;
+    a->out_stride = (int64_t)1 << j->root_D;
+    std::memset(m, 0, sizeof(*m));
+    if (X->prec == FSG_BF16_SPLIT) {
+        a->q_idx = X->order;
+        a->out_rows = X->order;
+        a->mask = j->mask;
+        a->n_blocks = X->n_pad / 16;
+        m->Xb = X->Xb;
+        m->Qb = X->Qb;
+        m->xa = X->xa;
+        m->KB = X->KB;
+        m->q_idx = X->order;
+        m->n_entries = n;
+        m->n_query = n;
+        m->n_data = n;
+        m->qnorm = X->norm;
+        m->dmin = X->dmin;
+        m->xmax = X->xmax;
+        m->margin_z = std::log((double)n) + kMarginExtra;
+        m->eps = 1.0 / 1024.0;
+        m->gamma = j->S.gamma;
+        m->n_tiles = (n + kTileQ - 1) / kTileQ;
+        m->n_blocks = X->n_pad / 16;
+        m->blocks_per_chunk = 512;
+        m->n_chunks = (m->n_blocks + m->blocks_per_chunk - 1) / m->blocks_per_chunk;
+        m->mask = j->mask;
+    }
+    return FSG_OK;
+}
+
+static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int waves_per_cu, int cols,
+                               BatchTables** out) {
+    for (BatchTables* T : ctx->batch_cache)
+        if (T->jobs == g && T->waves_per_cu == waves_per_cu && T->cols == cols) {
+            *out = T;
+            return FSG_OK;
+        }
+    const int32_t G = (int32_t)g.size();
+    const bool bf16 = g[0]->S.X->prec == FSG_BF16_SPLIT;
+    const size_t o_args = 0;
+    const size_t o_segs = align256(o_args + G * sizeof(KdeArgs));
+    const size_t o_desc = align256(o_segs + G * sizeof(SegDesc));
+    const size_t o_margs = align256(o_desc + (G + 1) * sizeof(BatchItemDesc));
+    const size_t o_moff = align256(o_margs + G * sizeof(MaskArgs));
+    const size_t o_cnt = align256(o_moff + (G + 1) * sizeof(int64_t));
+    const size_t bytes = align256(o_cnt + sizeof(unsigned long long));
+    BatchTables* T = new BatchTables();
+    T->jobs = g;
+    T->waves_per_cu = waves_per_cu;
+    T->cols = cols;
+    T->bytes = bytes;
+    auto fail = [&](fsg_status s) {
+        free_tables(T);
+        return s;
+    };
+    if (hipMalloc(&T->dev, bytes) != hipSuccess || hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(ctx, FSG_E_NOMEM, "allocation of batch tables failed"));
+    }
+    char* h = (char*)T->host;
+    char* d = (char*)T->dev;
+    std::memset(h, 0, bytes);
+    KdeArgs* hargs = (KdeArgs*)(h + o_args);
+    SegDesc* hsegs = (SegDesc*)(h + o_segs);
+    BatchItemDesc* hdesc = (BatchItemDesc*)(h + o_desc);
+    MaskArgs* hmargs = (MaskArgs*)(h + o_margs);
+    int64_t* hmoff = (int64_t*)(h + o_moff);
+    int64_t total = 0, mtotal = 0;
+    fsg_status st;
+    for (int32_t i = 0; i < G; ++i) {
+        fsg_job* j = g[i];
+        if ((st = job_root_args(ctx, j, &hargs[i], &hmargs[i])) != FSG_OK) return fail(st);
+        const int64_t n = j->S.X->n;
+        const int32_t nbins = 1 << j->root_D;
+        const int32_t tile = kde_tile(j->S.X->D4);
+        const int64_t n_tiles = (n + tile - 1) / tile;
+        int64_t bpc;
+        if (bf16) {
+            // item shape as in the single-set pass (see root_bins_per_item);
+            // `cols` sets the keep-mask kernel's data columns per work item
+            bpc = root_bins_per_item(ctx, n_tiles, nbins);
+            MaskArgs& m = hmargs[i];
+            m.blocks_per_chunk = cols / 16;
+            m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+        } else {
+            bpc = (int64_t)std::llround((double)cols * nbins / (double)n);
+            if (bpc < 1) bpc = 1;
+            if (bpc > nbins) bpc = nbins;
+        }
+        const int64_t n_chunks = (nbins + bpc - 1) / bpc;
+        hsegs[i].bound_off = 0;
+        hsegs[i].nbins = nbins;
+        hsegs[i].job = i;
+        hdesc[i].item_off = total;
+        hdesc[i].n_entries = n;
+        hdesc[i].nbins = nbins;
+        hdesc[i].bpc = (int32_t)bpc;
+        hdesc[i].tile = tile;
+        hdesc[i].n_tiles = (int32_t)n_tiles;
+        total += n_tiles * n_chunks;
+        hmoff[i] = mtotal;
+        if (bf16) {
+            mtotal += hmargs[i].n_tiles * hmargs[i].n_chunks;
+            T->scanned += hmargs[i].n_tiles * n;
+        }
+    }
+    hdesc[G].item_off = total;
+    hmoff[G] = mtotal;
+    T->total_items = total;
+    T->mask_items = mtotal;
+    if (total > 2147483647LL) return fail(set_error(ctx, FSG_E_UNSUPPORTED, "more than 2^31-1 work items in a batch"));
+    if (hipMalloc(&T->items, total * sizeof(WorkItem) + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(ctx, FSG_E_NOMEM, "allocation of batch work items failed"));
+    }
+    T->n_items = (int32_t*)((char*)T->items + total * sizeof(WorkItem));
+    T->counter = (unsigned long long*)(d + o_cnt);
+    hipError_t e = hipMemcpyAsync(T->dev, T->host, bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_batch_items((const BatchItemDesc*)(d + o_desc), G, total, T->items, T->n_items, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(ctx, FSG_E_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
+    }
+    T->a0 = hargs[0];
+    T->a0.jobs = (const KdeArgs*)(d + o_args);
+    T->a0.segs = (const SegDesc*)(d + o_segs);
+    T->a0.items = T->items;
+    T->a0.n_items = T->n_items;
+    T->m0 = hmargs[0];
+    T->m0.jobs = (const MaskArgs*)(d + o_margs);
+    T->m0.job_item_off = (const int64_t*)(d + o_moff);
+    T->m0.n_jobs = G;
+    T->m0.n_items_total = mtotal;
+    ctx->batch_cache.push_back(T);
+    *out = T;
+    return FSG_OK;
+}
+
+// the KDE launches of a batched root pass
+static fsg_status batch_root_launch(fsg_ctx* ctx, BatchTables* T, bool stats) {
+    if (T->jobs[0]->S.X->prec == FSG_BF16_SPLIT) {
+        MaskArgs m = T->m0;
+        m.kept = nullptr;
+        if (stats) {
+            fsg_status st;
+            if ((st = ensure_filter_counts(ctx)) != FSG_OK) return st;
+            m.kept = ctx->filter_counts;
+            FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, T->scanned, ctx->stream));
+        }
+        {
+            StageTimer t(ctx, "kde_mask");
+            FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));
+        }
+        FSG_HIP(ctx, launch_fill_i64((int64_t*)T->counter, 1, 0, ctx->stream));
+        StageTimer t(ctx, "kde_root");
+        FSG_HIP(ctx, launch_exact_kept(T->a0, T->total_items, T->counter, ctx->num_cus, ctx->stream));
+        return FSG_OK;
+    }
+    StageTimer t(ctx, "kde_root");
+    FSG_HIP(ctx, launch_kde(T->a0, T->total_items, ctx->num_cus, ctx->stream, T->waves_per_cu));
+    return FSG_OK;
+}
+
+static bool stream_capturing(fsg_ctx* ctx) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Root passes of a group of jobs in one launch (per KDE stage), with the
+// launch shape tuned on the group's first use when autotuning is on.
+static fsg_status batch_root(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
+    const fsg_points* X0 = g[0]->S.X;
+    const std::pair<int, int> key(X0->D4, (int)X0->prec);
+    auto it = ctx->tuned.find(key);
+    const bool bf16 = X0->prec == FSG_BF16_SPLIT;
+    int waves = 8, cols = bf16 ? 8192 : 2048;
+    fsg_status st;
+    if (it != ctx->tuned.end()) {
+        waves = it->second.first;
+        cols = it->second.second;
+    } else if (ctx->autotune && !stream_capturing(ctx)) {
+        hipEvent_t e0, e1;
+        FSG_HIP(ctx, hipEventCreate(&e0));
+        FSG_HIP(ctx, hipEventCreate(&e1));
+        float best = 3.0e38f;
+        // plain: grid size and data columns per item; precision mode: data
+        // columns per keep-mask item (the filter kernels fix their occupancy,
+        // and the exact pass keeps the single-set item shape)
+        const int wave_opts[3] = {4, 8, 12};
+        const int col_opts[3] = {1024, 2048, 4096};
+        const int mask_col_opts[3] = {4096, 8192, 16384};
+        for (int wi = 0; wi < 3; ++wi) {
+            if (bf16 && wave_opts[wi] != 8) continue;
+            for (int ci = 0; ci < 3; ++ci) {
+                const int cand = bf16 ? mask_col_opts[ci] : col_opts[ci];
+                BatchTables* T;
+                if ((st = batch_tables(ctx, g, wave_opts[wi], cand, &T)) != FSG_OK) return st;
+                FSG_HIP(ctx, hipEventRecord(e0, ctx->stream));
+                if ((st = batch_root_launch(ctx, T, false)) != FSG_OK) return st;
+                FSG_HIP(ctx, hipEventRecord(e1, ctx->stream));
+                FSG_HIP(ctx, hipEventSynchronize(e1));
+                float ms = 0.0f;
+                FSG_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    waves = wave_opts[wi];
+                    cols = cand;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        // keep only the tables of the chosen shape
+        auto& c = ctx->batch_cache;
+        for (size_t i = 0; i < c.size();) {
+            if (c[i]->jobs == g && !(c[i]->waves_per_cu == waves && c[i]->cols == cols)) {
+                free_tables(c[i]);
+                c.erase(c.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+        ctx->tuned[key] = {waves, cols};
+    }
+    BatchTables* T;
+    if ((st = batch_tables(ctx, g, waves, cols, &T)) != FSG_OK) return st;
+    return batch_root_launch(ctx, T, true);
+}
+
 }  // namespace fsg
 
 using namespace fsg;
@@ -478,6 +984,17 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
             if (v) ctx->pool_size.erase(v);
         for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
         p->ctx = nullptr;
+    }
+    for (BatchTables* T : ctx->batch_cache) free_tables(T);
+    ctx->batch_cache.clear();
+    // live jobs are detached; their buffers are freed here
+    for (fsg_job* j : ctx->jobs) {
+        for (void* v : j->owned) {
+            ctx->pool_size.erase(v);
+            (void)hipFree(v);
+        }
+        j->owned.clear();
+        j->ctx = nullptr;
     }
     pool_clear(ctx);
     for (auto& kv : ctx->bufs) (void)hipFree(kv.second.first);
@@ -673,7 +1190,8 @@ fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points
     int32_t* n_items;
     int64_t* scratch;
     double* pairs;
-    const int64_t max_items = n_entries / kTileQ + n_seg + 1;
+    const int32_t tile = kde_tile(X->D4);
+    const int64_t max_items = n_entries / tile + n_seg + 1;
     if ((st = ws(ctx, "seg_bounds", (size_t)(3 * n_seg), &bounds)) != FSG_OK) return st;
     if ((st = ws(ctx, "seg_descs", (size_t)n_seg, &segs)) != FSG_OK) return st;
     if ((st = ws(ctx, "seg_items", (size_t)max_items, &items)) != FSG_OK) return st;
@@ -682,7 +1200,7 @@ fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points
         return st;
     if ((st = ws(ctx, "seg_pairs", (size_t)(2 * n_entries), &pairs)) != FSG_OK) return st;
     FSG_HIP(ctx, launch_api_segments(lo, mid, hi, n_seg, bounds, segs, ctx->stream));
-    FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, kTileQ, scratch, items, n_items, max_items, ctx->stream));
+    FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, tile, scratch, items, n_items, max_items, ctx->stream));
     KdeArgs a = kde_args(Q, X, gamma);
     a.q_idx = q_idx;
     a.self_idx = self_idx;
@@ -705,140 +1223,30 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
     if (Xc->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
     if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
     if (L < 1) return set_error(ctx, FSG_E_INVALID, "L must be >= 1");
-    fsg_points* X = const_cast<fsg_points*>(Xc);
-    const int64_t n = X->n;
-    const int64_t ns = n * (int64_t)L;
-    if (ns > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "n*L must be < 2^31");
-    const double s = gamma * 1.442695040888963407359924681001892137;
+    Sampler S;
+    S.X = const_cast<fsg_points*>(Xc);
+    S.gamma = gamma;
+    S.L = L;
+    S.seed = seed;
+    S.deg = deg_dev;
+    S.nbr = nbr_dev;
+    S.margin = margin_dev;
     fsg_status st;
-    const Plan plan = make_plan(n, L, ctx->budget, ctx->max_levels_per_pass);
-    // uniforms of the leaf levels, produced by the last binned pass
-    const int32_t n_uleaf = tree_depth(n) - plan.leaf_level;
-    double* uleaf = nullptr;
-    if (!plan.passes.empty() && n_uleaf > 0) {
-        if ((st = ws(ctx, "smp_uleaf", (size_t)ns * n_uleaf, &uleaf)) != FSG_OK) return st;
+    if ((st = sampler_plan(ctx, S)) != FSG_OK) return st;
+    if (S.n_uleaf > 0 && (st = ws(ctx, "smp_uleaf", (size_t)S.ns * S.n_uleaf, &S.uleaf)) != FSG_OK) return st;
+    if ((st = ws(ctx, "smp_node", (size_t)S.ns, &S.node)) != FSG_OK) return st;
+    FSG_HIP(ctx, launch_init_samples(S.ns, S.node, margin_dev, ctx->stream));
+    if (!S.plan.passes.empty()) {
+        const int D = S.plan.passes[0].second;
+        double* M;
+        if ((st = ws(ctx, "pass_masses", (size_t)S.X->n << D, &M)) != FSG_OK) return st;
+        if ((st = root_bins(ctx, S.X, gamma, D, M)) != FSG_OK) return st;
+        if ((st = stage_root_descend(ctx, S, M)) != FSG_OK) return st;
     }
-
-    int32_t* node;
-    if ((st = ws(ctx, "smp_node", (size_t)ns, &node)) != FSG_OK) return st;
-    FSG_HIP(ctx, launch_init_samples(ns, node, margin_dev, ctx->stream));
-
-    for (size_t p = 0; p < plan.passes.size(); ++p) {
-        const int start = plan.passes[p].first, D = plan.passes[p].second;
-        const int32_t nbins = 1 << D;
-        DescArgs da;
-        std::memset(&da, 0, sizeof(da));
-        da.D = D;
-        da.start_level = start;
-        da.L = L;
-        da.seed = seed;
-        da.node = node;
-        da.margin = margin_dev;
-        if (p + 1 == plan.passes.size() && uleaf != nullptr) {
-            da.uleaf = uleaf;
-            da.n_uleaf = n_uleaf;
-        }
-        if (p == 0) {
-            double* M;
-            if ((st = ws(ctx, "pass_masses", (size_t)n << D, &M)) != FSG_OK) return st;
-            if ((st = root_bins(ctx, X, gamma, D, M)) != FSG_OK) return st;
-            da.M = M;
-            da.n_entries = n;
-            da.entry_sample = nullptr;
-            da.deg = deg_dev;
-            StageTimer t(ctx, "descend");
-            FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
-        } else {
-            int32_t *sorted, *starts;
-            if ((st = group_by_node(ctx, node, ns, start, &sorted, &starts)) != FSG_OK) return st;
-            const int64_t n_nodes = (int64_t)1 << start;
-            const int32_t* bnd = level_bounds(X, start + D, &st);
-            if (!bnd) return st;
-            int64_t* q_ptr;
-            int32_t* q_idx;
-            SegDesc* segs;
-            WorkItem* items;
-            int32_t* n_items;
-            int64_t* scratch;
-            double* M;
-            const int64_t max_items = ns / kTileQ + n_nodes + 1;
-            if ((st = ws(ctx, "pass_qptr", (size_t)n_nodes + 1, &q_ptr)) != FSG_OK) return st;
-            if ((st = ws(ctx, "pass_qidx", (size_t)ns, &q_idx)) != FSG_OK) return st;
-            if ((st = ws(ctx, "pass_segs", (size_t)n_nodes, &segs)) != FSG_OK) return st;
-            if ((st = ws(ctx, "pass_items", (size_t)max_items, &items)) != FSG_OK) return st;
-            if ((st = ws(ctx, "pass_nitems", 1, &n_items)) != FSG_OK) return st;
-            if ((st = ws(ctx, "pass_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
-                FSG_OK)
-                return st;
-            if ((st = ws(ctx, "pass_masses", (size_t)ns << D, &M)) != FSG_OK) return st;
-            FSG_HIP(ctx, launch_node_qptr(starts, n_nodes, q_ptr, ctx->stream));
-            FSG_HIP(ctx, launch_entry_points(sorted, ns, L, q_idx, ctx->stream));
-            FSG_HIP(ctx, launch_uniform_segs(segs, n_nodes, nbins, nbins, ctx->stream));
-            FSG_HIP(ctx, launch_build_items(q_ptr, n_nodes, nbins, nbins, kTileQ, scratch, items, n_items, max_items,
-                                            ctx->stream));
-            KdeArgs a = kde_args(X, X, gamma);
-            a.q_idx = q_idx;
-            a.self_idx = q_idx;
-            a.self_mode = SELF_ARRAY;
-            a.bounds = bnd;
-            a.segs = segs;
-            a.items = items;
-            a.n_items = n_items;
-            a.out = M;
-            a.out_stride = nbins;
-            {
-                StageTimer t(ctx, "kde_pass");
-                FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
-            }
-            da.M = M;
-            da.n_entries = ns;
-            da.entry_sample = sorted;
-            da.deg = nullptr;
-            StageTimer t(ctx, "descend");
-            FSG_HIP(ctx, launch_descend_bins(da, ctx->stream));
-        }
-    }
-
-    // leaf stage
-    {
-        int32_t *sorted, *starts;
-        if ((st = group_by_node(ctx, node, ns, plan.leaf_level, &sorted, &starts)) != FSG_OK) return st;
-        const int64_t n_nodes = (int64_t)1 << plan.leaf_level;
-        const int32_t* bnd = level_bounds(X, plan.leaf_level, &st);
-        if (!bnd) return st;
-        int32_t* items;
-        int32_t* n_items;
-        int64_t* scratch;
-        const int64_t max_items = ns / 64 + n_nodes + 1;
-        if ((st = ws(ctx, "leaf_items", (size_t)(2 * max_items), &items)) != FSG_OK) return st;
-        if ((st = ws(ctx, "leaf_nitems", 1, &n_items)) != FSG_OK) return st;
-        if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
-            FSG_OK)
-            return st;
-        StageTimer t(ctx, "leaf");
-        FSG_HIP(ctx, launch_leaf_items(starts, n_nodes, scratch, items, n_items, ctx->stream));
-        LeafArgs la;
-        std::memset(&la, 0, sizeof(la));
-        la.X = X->X;
-        la.n = n;
-        la.d = X->d;
-        la.bounds = bnd;
-        la.level = plan.leaf_level;
-        la.s = s;
-        la.L = L;
-        la.seed = seed;
-        la.sorted_samples = sorted;
-        la.node_start = starts;
-        la.items = items;
-        la.n_items = n_items;
-        la.nbr = nbr_dev;
-        la.margin = margin_dev;
-        la.uleaf = uleaf;
-        la.n_uleaf = n_uleaf;
-        FSG_HIP(ctx, launch_leaf(la, max_items, ctx->num_cus, ctx->stream));
-        FSG_HIP(ctx, launch_finish_inactive(node, ns, nbr_dev, ctx->stream));
-    }
-    if (plan.passes.empty() && deg_dev) return fsg_degrees(ctx, X, gamma, deg_dev);
+    for (size_t p = 1; p < S.plan.passes.size(); ++p)
+        if ((st = stage_pass(ctx, S, p)) != FSG_OK) return st;
+    if ((st = stage_leaf(ctx, S)) != FSG_OK) return st;
+    if (S.plan.passes.empty() && deg_dev) return fsg_degrees(ctx, S.X, gamma, deg_dev);
     return FSG_OK;
 }
 
@@ -943,6 +1351,177 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
     *nnz = ctx->host_scratch[0];
     if (*nnz > cap) return set_error(ctx, FSG_E_INVALID, "cap is smaller than 2|E|");
     return FSG_OK;
+}
+
+
+fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int32_t L, uint64_t seed,
+                          fsg_job** out) {
+    if (!ctx || !out) return FSG_E_INVALID;
+    *out = nullptr;
+    if (!Xc) return set_error(ctx, FSG_E_INVALID, "NULL points");
+    if (Xc->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    if (L < 1) return set_error(ctx, FSG_E_INVALID, "L must be >= 1");
+    fsg_job* j = new (std::nothrow) fsg_job();
+    if (!j) return set_error(ctx, FSG_E_NOMEM, "host allocation failed");
+    j->ctx = ctx;
+    j->S.X = const_cast<fsg_points*>(Xc);
+    j->S.gamma = gamma;
+    j->S.L = L;
+    j->S.seed = seed;
+    fsg_status st;
+    auto fail = [&](fsg_status s) {
+        for (void* p : j->owned) pool_release(ctx, p);
+        delete j;
+        return s;
+    };
+    if ((st = sampler_plan(ctx, j->S)) != FSG_OK) return fail(st);
+    const int64_t n = Xc->n, ns = j->S.ns;
+    j->n_stages = (int)j->S.plan.passes.size() + 1;
+    if (!(j->S.node = (int32_t*)job_alloc(j, ns * sizeof(int32_t), &st))) return fail(st);
+    if (!(j->S.nbr = (int32_t*)job_alloc(j, ns * sizeof(int32_t), &st))) return fail(st);
+    if (!(j->S.deg = (double*)job_alloc(j, n * sizeof(double), &st))) return fail(st);
+    if (j->S.n_uleaf > 0 && !(j->S.uleaf = (double*)job_alloc(j, ns * j->S.n_uleaf * sizeof(double), &st)))
+        return fail(st);
+    if (!j->S.plan.passes.empty()) {
+        j->root_D = j->S.plan.passes[0].second;
+        if (!(j->M = (double*)job_alloc(j, (size_t)(n << j->root_D) * sizeof(double), &st))) return fail(st);
+        if (Xc->prec == FSG_BF16_SPLIT) {
+            const size_t tiles = (size_t)((n + kTileQ - 1) / kTileQ);
+            if (!(j->mask = (uint16_t*)job_alloc(j, tiles * (size_t)(Xc->n_pad / 16) * sizeof(uint16_t), &st)))
+                return fail(st);
+        }
+    }
+    ctx->jobs.insert(j);
+    *out = j;
+    return FSG_OK;
+}
+
+fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, int32_t* n_done) {
+    if (!ctx || !n_done) return FSG_E_INVALID;
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return set_error(ctx, FSG_E_INVALID, "bad job list");
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        if (!jobs[i] || jobs[i]->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "job is NULL or of another context");
+        for (int32_t k = 0; k < i; ++k)
+            if (jobs[k] == jobs[i]) return set_error(ctx, FSG_E_INVALID, "a job appears twice");
+    }
+    fsg_status st;
+    // root passes: grouped by feature-step class and precision, in list order
+    std::map<std::pair<int, int>, std::vector<fsg_job*>> groups;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        fsg_job* j = jobs[i];
+        if (j->stage != 0) continue;
+        FSG_HIP(ctx, launch_init_samples(j->S.ns, j->S.node, nullptr, ctx->stream));
+        if (!j->S.plan.passes.empty()) groups[{j->S.X->D4, (int)j->S.X->prec}].push_back(j);
+    }
+    for (auto& kv : groups)
+        if ((st = batch_root(ctx, kv.second)) != FSG_OK) return st;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        fsg_job* j = jobs[i];
+        if (j->stage >= j->n_stages) continue;
+        const int P = (int)j->S.plan.passes.size();
+        if (j->stage == 0 && P > 0) {
+            if ((st = stage_root_descend(ctx, j->S, j->M)) != FSG_OK) return st;
+        } else if (j->stage < P) {
+            if ((st = stage_pass(ctx, j->S, (size_t)j->stage)) != FSG_OK) return st;
+        } else {
+            if ((st = stage_leaf(ctx, j->S)) != FSG_OK) return st;
+            if (P == 0 && (st = fsg_degrees(ctx, j->S.X, j->S.gamma, j->S.deg)) != FSG_OK) return st;
+        }
+        ++j->stage;
+    }
+    int32_t done = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) done += (jobs[i]->stage >= jobs[i]->n_stages) ? 1 : 0;
+    *n_done = done;
+    return FSG_OK;
+}
+
+fsg_status fsg_job_reset(fsg_job* j) {
+    if (!j || !j->ctx) return FSG_E_INVALID;
+    j->stage = 0;
+    return FSG_OK;
+}
+
+fsg_status fsg_job_result(fsg_job* j, int32_t* nbr_dev, double* deg_dev) {
+    if (!j || !j->ctx) return FSG_E_INVALID;
+    fsg_ctx* ctx = j->ctx;
+    if (j->stage < j->n_stages) return set_error(ctx, FSG_E_INVALID, "the job has not finished");
+    if (nbr_dev)
+        FSG_HIP(ctx, hipMemcpyAsync(nbr_dev, j->S.nbr, j->S.ns * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    if (deg_dev)
+        FSG_HIP(ctx, hipMemcpyAsync(deg_dev, j->S.deg, j->S.X->n * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    return FSG_OK;
+}
+
+fsg_status fsg_job_outputs(fsg_job* j, const int32_t** nbr_dev, const double** deg_dev) {
+    if (!j || !j->ctx) return FSG_E_INVALID;
+    if (nbr_dev) *nbr_dev = j->S.nbr;
+    if (deg_dev) *deg_dev = j->S.deg;
+    return FSG_OK;
+}
+
+void fsg_job_destroy(fsg_job* j) {
+    if (!j) return;
+    if (j->ctx) {
+        batch_cache_drop(j->ctx, j);
+        for (void* p : j->owned) pool_release(j->ctx, p);
+        j->ctx->jobs.erase(j);
+    }
+    delete j;
+}
+
+fsg_status fsg_ctx_set_autotune(fsg_ctx* ctx, int32_t enabled) {
+    if (!ctx) return FSG_E_INVALID;
+    ctx->autotune = enabled != 0;
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int32_t* waves_per_cu,
+                               int32_t* cols_per_item) {
+    if (!ctx || !waves_per_cu || !cols_per_item) return FSG_E_INVALID;
+    auto it = ctx->tuned.find({(int)D4, (int)prec});
+    if (it == ctx->tuned.end()) return set_error(ctx, FSG_E_INVALID, "no tuned shape for this class");
+    *waves_per_cu = it->second.first;
+    *cols_per_item = it->second.second;
+    return FSG_OK;
+}
+
+fsg_status fsg_graph_begin(fsg_ctx* ctx) {
+    if (!ctx) return FSG_E_INVALID;
+    if (ctx->stream == nullptr) return set_error(ctx, FSG_E_UNSUPPORTED, "recording needs a non-default stream");
+    FSG_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    return FSG_OK;
+}
+
+fsg_status fsg_graph_end(fsg_ctx* ctx, fsg_graph** out) {
+    if (!ctx || !out) return FSG_E_INVALID;
+    *out = nullptr;
+    fsg_graph* g = new (std::nothrow) fsg_graph();
+    if (!g) return set_error(ctx, FSG_E_NOMEM, "host allocation failed");
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return set_error(ctx, FSG_E_DEVICE, std::string("graph: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return FSG_OK;
+}
+
+fsg_status fsg_graph_launch(fsg_ctx* ctx, fsg_graph* g) {
+    if (!ctx || !g) return FSG_E_INVALID;
+    FSG_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
+    return FSG_OK;
+}
+
+void fsg_graph_destroy(fsg_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

@@ -37,10 +37,20 @@ struct WorkItem {
     int32_t b0, b1;  // bin range (indices into the segment's boundary list)
 };
 
+// Work items of one point set in a multi-set launch.
+struct BatchItemDesc {
+    int64_t item_off;   // first item of the set (entry n_jobs: the total)
+    int64_t n_entries;  // query entries (the set's points)
+    int32_t nbins;
+    int32_t bpc;        // bins per item
+    int32_t tile;       // query entries per item
+    int32_t n_tiles;
+};
+
 struct SegDesc {
     int64_t bound_off;  // offset of the segment's boundary list in the bounds array
     int32_t nbins;      // bins in the segment (boundaries: nbins + 1)
-    int32_t pad;
+    int32_t job;        // point set of the segment in a multi-set launch (index into KdeArgs::jobs)
 };
 
 enum SelfMode : int32_t { SELF_NONE = 0, SELF_POINT = 1, SELF_ARRAY = 2 };
@@ -64,6 +74,9 @@ struct KdeArgs {
     double* out;             // out[row * out_stride + bin]
     int64_t out_stride;
     const int32_t* out_rows; // entry -> output row (NULL: the entry index)
+    const KdeArgs* jobs;     // multi-set launch: per point set arguments (NULL: this one)
+    const uint16_t* mask;    // precision mode: keep masks of this point set [tiles][n_blocks]
+    int64_t n_blocks;        // precision mode: 16-column blocks per mask row
 };
 
 // Filtered KDE (precision mode): BF16 split operands decide which pairs are
@@ -89,6 +102,12 @@ struct MaskArgs {
     int64_t n_chunks;
     uint16_t* mask;            // [n_tiles][n_blocks]: bit c = column c of the block kept for the tile
     int64_t* kept;             // optional: number of (column, tile) pairs kept
+    // multi-set launch: items of point set j are [job_item_off[j], job_item_off[j+1]),
+    // each set's arguments in jobs[j] (NULL: this one; kept is this launch's)
+    const MaskArgs* jobs;
+    const int64_t* job_item_off;
+    int32_t n_jobs;
+    int64_t n_items_total;
 };
 
 // ---------------------------------------------------------------------------
@@ -97,6 +116,10 @@ struct MaskArgs {
 struct Arena;
 
 }  // namespace fsg
+
+namespace fsg {
+struct BatchTables;  // device tables of a batched root pass (api.hip)
+}
 
 struct fsg_ctx {
     int device = 0;
@@ -124,6 +147,15 @@ struct fsg_ctx {
     std::multimap<size_t, void*> pool_free;
     std::map<void*, size_t> pool_size;
     size_t pool_cached = 0;
+    // batched root passes: launch shapes tuned per (feature steps, precision)
+    // as (waves per CU, data columns per work item), and the device tables of
+    // the job groups seen so far
+    bool autotune = true;
+    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+    std::vector<fsg::BatchTables*> batch_cache;
+    // live batch jobs; their buffers are freed and they are detached when the
+    // context is destroyed
+    std::set<fsg_job*> jobs;
 };
 
 
@@ -192,12 +224,15 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t
 hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t st);
 
 // KDE over a work list; grid = waves / 4 blocks of 256 threads.
-hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
+hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu = 8);
+int kde_tile(int D4);  // query entries per work item of the plain kernel
+hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
+                              int32_t* n_items, hipStream_t st);
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);
 // next_item: a counter that must read 0 when the kernel starts (work items
 // beyond the first wave of the grid are claimed from it)
-hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
-                             unsigned long long* next_item, int num_cus, hipStream_t st);
+hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long long* next_item, int num_cus,
+                             hipStream_t st);
 int split_steps(int d);
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
                              void* Xb, void* Qb, float* xa, hipStream_t st);

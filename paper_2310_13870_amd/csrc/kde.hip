@@ -18,7 +18,9 @@
 
 namespace fsg {
 
-template <int D4, int RQ>
+// MULTI: items of many point sets in one launch; segment sg.job selects the
+// arguments of its point set from a.jobs.
+template <int D4, int RQ, bool MULTI>
 __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
     __shared__ int32_t win_all[4][kBinWindow];
     const int lane = threadIdx.x & 63;
@@ -26,14 +28,15 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
-    const double two_s = 2.0 * a.s;
     const int grp = lane >> 4;  // data row group inside a 16-column block
     const int r = lane & 15;    // query row inside a query block
 
     for (int64_t it = wave; it < n_items; it += n_waves) {
         const WorkItem w = a.items[it];
         const SegDesc sg = a.segs[w.seg];
-        const int32_t* bnd = a.bounds + sg.bound_off;
+        const KdeArgs& J = MULTI ? a.jobs[sg.job] : a;
+        const int32_t* bnd = J.bounds + sg.bound_off;
+        const double two_s = 2.0 * J.s;
 
         double qf[RQ][D4];
         double hq[RQ];
@@ -43,13 +46,13 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             const int32_t t = 16 * qb + r;
             const bool ok = t < w.ne;
             const int64_t e = w.e0 + (ok ? t : 0);
-            int32_t p = a.q_idx ? a.q_idx[e] : (int32_t)e;
-            p = min(max(p, 0), (int32_t)(a.n_query - 1));  // never read outside the query set
+            int32_t p = J.q_idx ? J.q_idx[e] : (int32_t)e;
+            p = min(max(p, 0), (int32_t)(J.n_query - 1));  // never read outside the query set
             int32_t sf = -1;
-            if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
+            if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -a.s * a.qnorm[p];
-            load_row_part<D4>(qf[qb], a.Qp, p, grp);
+            hq[qb] = -J.s * J.qnorm[p];
+            load_row_part<D4>(qf[qb], J.Qp, p, grp);
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -61,21 +64,21 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
         }
 
         // never read outside the data set, whatever the boundaries say
-        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)a.n_data));
+        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)J.n_data));
         const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
         BinAccumulator<RQ> bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
-        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
+        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);
 
         // the operands of the next block are loaded while the current one is
         // computed
         const int32_t cfirst = col_begin & ~15;
         double xf[D4], xn[4];
         if (cfirst < col_end) {
-            load_row_part<D4>(xf, a.Xp, cfirst + perm_row(r), grp);
+            load_row_part<D4>(xf, J.Xp, cfirst + perm_row(r), grp);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) xn[i] = a.xnorm[cfirst + 4 * grp + i];
+            for (int i = 0; i < 4; ++i) xn[i] = J.xnorm[cfirst + 4 * grp + i];
         }
         for (int32_t c0 = cfirst; c0 < col_end; c0 += 16) {
             double xf_next[D4], xn_next[4];
@@ -83,16 +86,16 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
             constexpr bool kPrefetch = D4 <= 16;
             const bool more = c0 + 16 < col_end;
             if (kPrefetch && more) {
-                load_row_part<D4>(xf_next, a.Xp, c0 + 16 + perm_row(r), grp);
+                load_row_part<D4>(xf_next, J.Xp, c0 + 16 + perm_row(r), grp);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) xn_next[i] = a.xnorm[c0 + 16 + 4 * grp + i];
+                for (int i = 0; i < 4; ++i) xn_next[i] = J.xnorm[c0 + 16 + 4 * grp + i];
             }
             int32_t jj[4];
             double hx[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 jj[i] = c0 + 4 * grp + i;
-                hx[i] = -a.s * xn[i];
+                hx[i] = -J.s * xn[i];
             }
             double4_t c[RQ];
 #pragma unroll
@@ -111,9 +114,9 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) xn[i] = xn_next[i];
                 } else {
-                    load_row_part<D4>(xf, a.Xp, c0 + 16 + perm_row(r), grp);
+                    load_row_part<D4>(xf, J.Xp, c0 + 16 + perm_row(r), grp);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xn[i] = a.xnorm[c0 + 16 + 4 * grp + i];
+                    for (int i = 0; i < 4; ++i) xn[i] = J.xnorm[c0 + 16 + 4 * grp + i];
                 }
             }
         }
@@ -122,14 +125,19 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
 }
 
 template <int D4, int RQ>
-static hipError_t launch_kde_t(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
-    int64_t waves = (int64_t)num_cus * 8;
+static hipError_t launch_kde_t(const KdeArgs& a, int64_t max_items, int num_cus, int waves_per_cu, hipStream_t st) {
+    int64_t waves = (int64_t)num_cus * waves_per_cu;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    kde_bins_kernel<D4, RQ><<<blocks, 256, 0, st>>>(a);
+    if (a.jobs)
+        kde_bins_kernel<D4, RQ, true><<<blocks, 256, 0, st>>>(a);
+    else
+        kde_bins_kernel<D4, RQ, false><<<blocks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
+
+int kde_tile(int D4) { return D4 >= 32 ? 32 : 64; }
 
 int feature_steps(int d) {
     const int d4 = (d + 3) / 4;
@@ -142,14 +150,16 @@ int feature_steps(int d) {
     return -1;  // larger d: not built
 }
 
-hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
+// The query tile (16 RQ entries per item) is kde_tile(D4): 64, and 32 for
+// d > 64, where 64 FP64 query rows would not fit the register file.
+hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu) {
     switch (a.D4) {
-        case 1: return launch_kde_t<1, 4>(a, max_items, num_cus, st);
-        case 2: return launch_kde_t<2, 4>(a, max_items, num_cus, st);
-        case 4: return launch_kde_t<4, 4>(a, max_items, num_cus, st);
-        case 8: return launch_kde_t<8, 4>(a, max_items, num_cus, st);
-        case 16: return launch_kde_t<16, 4>(a, max_items, num_cus, st);
-        case 32: return launch_kde_t<32, 4>(a, max_items, num_cus, st);
+        case 1: return launch_kde_t<1, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 2: return launch_kde_t<2, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 4: return launch_kde_t<4, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 8: return launch_kde_t<8, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 16: return launch_kde_t<16, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 32: return launch_kde_t<32, 2>(a, max_items, num_cus, waves_per_cu, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -181,6 +191,38 @@ hipError_t launch_regular_items(int64_t n_entries, int32_t nbins, int32_t bins_p
     const int64_t total = n_tiles * n_chunks;
     regular_items_kernel<<<(unsigned)((total + 255) / 256 + 1), 256, 0, st>>>(n_entries, nbins, bins_per_chunk, tile,
                                                                              n_tiles, total, items, n_items);
+    return hipGetLastError();
+}
+
+// Work items of many point sets (one segment each, whole tree level): set g
+// owns items [jd[g].item_off, jd[g+1].item_off), chunk-major like the
+// single-set list.
+__global__ void batch_items_kernel(const BatchItemDesc* __restrict__ jd, int32_t n_jobs, int64_t total,
+                                   WorkItem* __restrict__ items, int32_t* __restrict__ n_items) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *n_items = (int32_t)total;
+    if (t >= total) return;
+    int32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (jd[mid].item_off <= t) lo = mid; else hi = mid;
+    }
+    const BatchItemDesc d = jd[lo];
+    const int64_t local = t - d.item_off;
+    const int64_t c = local / d.n_tiles, q = local - c * d.n_tiles;
+    WorkItem w;
+    w.seg = lo;
+    w.e0 = q * d.tile;
+    const int64_t rem = d.n_entries - w.e0;
+    w.ne = (int32_t)(rem < d.tile ? rem : d.tile);
+    w.b0 = (int32_t)(c * d.bpc);
+    w.b1 = (int32_t)min((int64_t)d.nbins, (c + 1) * (int64_t)d.bpc);
+    items[t] = w;
+}
+
+hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
+                              int32_t* n_items, hipStream_t st) {
+    batch_items_kernel<<<(unsigned)((total + 255) / 256 + 1), 256, 0, st>>>(jd, n_jobs, total, items, n_items);
     return hipGetLastError();
 }
 
@@ -247,7 +289,7 @@ __global__ void uniform_segs_kernel(SegDesc* segs, int64_t n_seg, int64_t stride
     SegDesc g;
     g.bound_off = s * stride;
     g.nbins = nbins;
-    g.pad = 0;
+    g.job = 0;
     segs[s] = g;
 }
 
@@ -266,7 +308,7 @@ __global__ void api_segments_kernel(const int32_t* lo, const int32_t* mid, const
     SegDesc g;
     g.bound_off = 3 * s;
     g.nbins = 2;
-    g.pad = 0;
+    g.job = 0;
     segs[s] = g;
 }
 

@@ -36,8 +36,8 @@ constexpr int mask_waves() { return KB <= 3 ? 3 : 2; }
 template <int D4>
 constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
 
-template <int KB, bool PREFETCH, int WAVES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m) {
+template <int KB, bool PREFETCH, int WAVES, bool MULTI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m0) {
     // Queries are the A operand and data the B operand, so lane l receives
     // query rows 4(l/16) + i of a query block and data column l % 16: a column
     // is kept when any of the 4 lane groups sees a compare succeed.
@@ -48,12 +48,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int grp = lane >> 4;
     const int r = lane & 15;
-    const double xmax = *m.xmax;
-    const double half_margin = m.margin_z / (2.0 * m.gamma);
-    const int64_t n_items = m.n_tiles * m.n_chunks;
+    const int64_t n_items = MULTI ? m0.n_items_total : m0.n_tiles * m0.n_chunks;
     int64_t kept = 0;
     for (int64_t it = wave; it < n_items; it += n_waves) {
-        const int64_t chunk = it / m.n_tiles, tile = it - chunk * m.n_tiles;
+        int64_t local = it;
+        int32_t job = 0;
+        if (MULTI) {  // the point set owning item it (uniform binary search)
+            int32_t lo = 0, hi = m0.n_jobs;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (m0.job_item_off[mid] <= it) lo = mid; else hi = mid;
+            }
+            job = lo;
+            local = it - m0.job_item_off[job];
+        }
+        const MaskArgs& m = MULTI ? m0.jobs[job] : m0;
+        const double xmax = *m.xmax;
+        const double half_margin = m.margin_z / (2.0 * m.gamma);
+        const int64_t chunk = local / m.n_tiles, tile = local - chunk * m.n_tiles;
         const int64_t e0 = tile * kTileQ;
         const int32_t ne = (int32_t)min((int64_t)kTileQ, m.n_entries - e0);
         bf16x8_t qb16[4][KB];
@@ -146,7 +158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             }
         }
     }
-    if (m.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m.kept, (unsigned long long)kept);
+    if (m0.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m0.kept, (unsigned long long)kept);
 }
 
 // ---------------------------------------------------------------------------
@@ -166,9 +178,9 @@ struct Gathered {
     int32_t first, last;  // smallest and largest column (uniform)
 };
 
-template <int D4, int RQ>
+template <int D4, int RQ, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
-    KdeArgs a, const uint16_t* __restrict__ mask, int64_t n_blocks, unsigned long long* __restrict__ next_item) {
+    KdeArgs a, unsigned long long* __restrict__ next_item) {
     constexpr int QN = 64;  // circular queue length (at most 31 entries are pending)
     __shared__ int32_t queue_all[4][QN];
     __shared__ double qf_all[4][RQ * D4 * 64];
@@ -180,7 +192,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
-    const double two_s = 2.0 * a.s;
     const int grp = lane >> 4;
     const int r = lane & 15;
     const int pr = perm_row(r);
@@ -193,7 +204,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         if (lane == 0) claim = atomicAdd(next_item, 1ull);
         const WorkItem w = a.items[it];
         const SegDesc sg = a.segs[w.seg];
-        const int32_t* bnd = a.bounds + sg.bound_off;
+        const KdeArgs& J = MULTI ? a.jobs[sg.job] : a;
+        const int32_t* bnd = J.bounds + sg.bound_off;
+        const double two_s = 2.0 * J.s;
         double hq[RQ];
         int32_t selfv[RQ], smin[RQ], smax[RQ];
         __builtin_amdgcn_wave_barrier();
@@ -202,14 +215,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             const int32_t t = 16 * qb + r;
             const bool ok = t < w.ne;
             const int64_t e = w.e0 + (ok ? t : 0);
-            int32_t p = a.q_idx ? a.q_idx[e] : (int32_t)e;
-            p = min(max(p, 0), (int32_t)(a.n_query - 1));
+            int32_t p = J.q_idx ? J.q_idx[e] : (int32_t)e;
+            p = min(max(p, 0), (int32_t)(J.n_query - 1));
             int32_t sf = -1;
-            if (ok) sf = (a.self_mode == SELF_POINT) ? p : ((a.self_mode == SELF_ARRAY) ? a.self_idx[e] : -1);
+            if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -a.s * a.qnorm[p];
+            hq[qb] = -J.s * J.qnorm[p];
             double qv[D4];
-            load_row_part<D4>(qv, a.Qp, p, grp);
+            load_row_part<D4>(qv, J.Qp, p, grp);
 #pragma unroll
             for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = qv[kk];
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
@@ -222,13 +235,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             smax[qb] = uniform(mx);
         }
         __builtin_amdgcn_wave_barrier();
-        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)a.n_data));
+        const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)J.n_data));
         const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
         BinAccumulator<RQ> bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
-        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, a.out_stride, a.out, a.out_rows, lane);
-        const uint16_t* mrow = mask + (w.e0 / kTileQ) * n_blocks;
+        bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);
+        const uint16_t* mrow = J.mask + (w.e0 / kTileQ) * J.n_blocks;
         const int64_t blk0 = col_begin >> 4, blk1 = (col_end + 15) >> 4;
 
         // queue state (uniform): entries [head, tail) are pending
@@ -271,14 +284,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         // consecutive entries 4g .. 4g+3
         auto prepare = [&](Gathered<D4>& g, int32_t pos, int32_t cnt) {
             const int32_t gl = queue[(pos + ((pr < cnt) ? pr : 0)) & (QN - 1)];
-            load_row_part<D4>(g.xf, a.Xp, gl, grp);
+            load_row_part<D4>(g.xf, J.Xp, gl, grp);
             g.first = uniform(queue[pos & (QN - 1)]);
             g.last = uniform(queue[(pos + cnt - 1) & (QN - 1)]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int32_t idx = 4 * grp + i;
                 g.jj[i] = (idx < cnt) ? queue[(pos + idx) & (QN - 1)] : INT32_MAX;
-                const double v = a.xnorm[(idx < cnt) ? g.jj[i] : g.first];
+                const double v = J.xnorm[(idx < cnt) ? g.jj[i] : g.first];
                 g.xn[i] = (idx < cnt) ? v : __builtin_inf();
             }
         };
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             // padding columns: |x|^2 = +inf gives exponent -inf and value 0
             double hx[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hx[i] = -a.s * g.xn[i];
+            for (int i = 0; i < 4; ++i) hx[i] = -J.s * g.xn[i];
             double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
@@ -328,11 +341,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
 
 template <int KB, bool PREFETCH, int WAVES>
 static hipError_t launch_mask_v(const MaskArgs& m, int num_cus, hipStream_t st) {
-    const int64_t n_items = m.n_tiles * m.n_chunks;
+    const int64_t n_items = m.jobs ? m.n_items_total : m.n_tiles * m.n_chunks;
     int64_t waves = (int64_t)num_cus * 4 * WAVES;
     if (n_items < waves) waves = n_items;
     if (waves < 1) waves = 1;
-    kde_keep_mask_kernel<KB, PREFETCH, WAVES><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    if (m.jobs)
+        kde_keep_mask_kernel<KB, PREFETCH, WAVES, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    else
+        kde_keep_mask_kernel<KB, PREFETCH, WAVES, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
     return hipGetLastError();
 }
 
@@ -354,23 +370,26 @@ hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
 }
 
 template <int D4>
-static hipError_t launch_exact_t(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
-                                 unsigned long long* next_item, int num_cus, hipStream_t st) {
+static hipError_t launch_exact_t(const KdeArgs& a, int64_t max_items, unsigned long long* next_item, int num_cus,
+                                 hipStream_t st) {
     int64_t waves = (int64_t)num_cus * 8;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
-    kde_exact_kept_kernel<D4, 4><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, mask, n_blocks, next_item);
+    if (a.jobs)
+        kde_exact_kept_kernel<D4, 4, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
+    else
+        kde_exact_kept_kernel<D4, 4, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
     return hipGetLastError();
 }
 
-hipError_t launch_exact_kept(const KdeArgs& a, const uint16_t* mask, int64_t n_blocks, int64_t max_items,
-                             unsigned long long* next_item, int num_cus, hipStream_t st) {
+hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long long* next_item, int num_cus,
+                             hipStream_t st) {
     switch (a.D4) {
-        case 1: return launch_exact_t<1>(a, mask, n_blocks, max_items, next_item, num_cus, st);
-        case 2: return launch_exact_t<2>(a, mask, n_blocks, max_items, next_item, num_cus, st);
-        case 4: return launch_exact_t<4>(a, mask, n_blocks, max_items, next_item, num_cus, st);
-        case 8: return launch_exact_t<8>(a, mask, n_blocks, max_items, next_item, num_cus, st);
-        case 16: return launch_exact_t<16>(a, mask, n_blocks, max_items, next_item, num_cus, st);
+        case 1: return launch_exact_t<1>(a, max_items, next_item, num_cus, st);
+        case 2: return launch_exact_t<2>(a, max_items, next_item, num_cus, st);
+        case 4: return launch_exact_t<4>(a, max_items, next_item, num_cus, st);
+        case 8: return launch_exact_t<8>(a, max_items, next_item, num_cus, st);
+        case 16: return launch_exact_t<16>(a, max_items, next_item, num_cus, st);
         default: return hipErrorInvalidValue;
     }
 }

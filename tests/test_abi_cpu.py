@@ -56,6 +56,34 @@ def test_status_strings_and_host_validation():
     assert lib.fsg_last_error(None) == b""
 
 
+def test_batch_and_graph_calls_validate_on_the_host():
+    """The batching, autotuning and graph calls reject NULL handles without
+    touching a device; destroying NULL is a no-op."""
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.fsg_job_create.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, vp]
+    assert lib.fsg_job_create(None, None, 1.0, 4, 1, None) == -1
+    lib.fsg_batch_step.argtypes = [vp, vp, ctypes.c_int32, vp]
+    assert lib.fsg_batch_step(None, None, 0, None) == -1
+    for name in ("fsg_job_reset", "fsg_graph_begin"):
+        f = getattr(lib, name)
+        f.argtypes = [vp]
+        assert f(None) == -1
+    lib.fsg_job_result.argtypes = [vp, vp, vp]
+    assert lib.fsg_job_result(None, None, None) == -1
+    lib.fsg_graph_end.argtypes = [vp, vp]
+    assert lib.fsg_graph_end(None, None) == -1
+    lib.fsg_graph_launch.argtypes = [vp, vp]
+    assert lib.fsg_graph_launch(None, None) == -1
+    lib.fsg_ctx_set_autotune.argtypes = [vp, ctypes.c_int32]
+    assert lib.fsg_ctx_set_autotune(None, 1) == -1
+    for name in ("fsg_job_destroy", "fsg_graph_destroy"):
+        f = getattr(lib, name)
+        f.argtypes = [vp]
+        f.restype = None
+        f(None)
+
+
 def test_no_gpu_reports_device_error():
     """Without a GPU, creating a context fails with FSG_E_DEVICE (never a crash)."""
     import torch
