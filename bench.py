@@ -90,12 +90,165 @@ def cpu_baseline(X, w, target_s: float):
     }
 
 
+def run_batched(args):
+    """256 independent point sets (n log-uniform in [1e3, 6.4e4], d in {8, 32,
+    128}): one batch of sampling builds per step, recorded once as a HIP graph
+    and replayed; the same builds run one by one and eagerly batched beside it.
+    The precision mode covers d <= 64; the d = 128 sets run the plain path in
+    both variants."""
+    import numpy as np
+    import torch
+
+    import paper_2310_13870_amd as fsg
+    import workloads
+
+    sets = workloads.batched_sets()
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = fsg.Context(0, stream=s)
+        pts, jobs = [], []
+        for w in sets:
+            prec = args.precision if w.d <= 64 else "fp32"
+            Xd = torch.from_numpy(w.points()).to(dev)
+            p = fsg.Points(ctx, Xd, prec)
+            pts.append((p, w, prec))
+            jobs.append(fsg.Job(ctx, p, w.gamma, w.L, w.philox_seed))
+        s.synchronize()
+        total_samples = sum(w.n * w.L for w in sets)
+        total_pairs = sum(w.n * (w.n - 1) for w in sets)
+
+        def run_eager():
+            for j in jobs:
+                j.reset()
+            return fsg.batch_run(ctx, jobs)
+
+        for _ in range(max(args.warmup, 1)):  # includes autotuning
+            n_steps = run_eager()
+        s.synchronize()
+        # eagerly batched, with stage timing
+        ctx.reset_profiling()
+        ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run_eager()
+        s.synchronize()
+        eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        ctx.set_profiling(False)
+        stages = {}
+        for name in ("kde_mask", "kde_root", "kde_pass", "descend", "group", "leaf"):
+            ms, cnt = ctx.stage_time(name)
+            if cnt:
+                stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps}
+        # one graph for the whole batch
+        for j in jobs:
+            j.reset()
+        g = fsg.Graph(ctx)
+        g.begin()
+        fsg.batch_run(ctx, jobs)
+        g.end()
+        g.launch()
+        s.synchronize()
+        times = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            g.launch()
+            s.synchronize()
+            times.append(time.perf_counter() - t1)
+        graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        # the same builds one by one (fsg_sample_edges per set)
+        t0 = time.perf_counter()
+        for p, w, prec in pts:
+            fsg.sample_edges(ctx, p, w.gamma, w.L, w.philox_seed)
+        s.synchronize()
+        seq_ms = 1e3 * (time.perf_counter() - t0)
+        tuned = {}
+        for D4 in (2, 8, 32):
+            for prec in ("fp32", "bf16_split"):
+                t = ctx.tuned_shape(D4, prec)
+                if t:
+                    tuned[f"D4={D4},{prec}"] = {"waves_per_cu": t[0], "cols_per_item": t[1]}
+        g.close()
+        for j in jobs:
+            j.close()
+        for p, _, _ in pts:
+            p.close()
+        ctx.close()
+    times_ms = np.array(times) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": total_samples / (graph_ms * 1e-3),
+        "unit": "sampled edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": graph_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched-256", "sets": len(sets), "n_min": min(w.n for w in sets),
+                   "n_max": max(w.n for w in sets), "total_points": sum(w.n for w in sets),
+                   "d": sorted({w.d for w in sets}), "precision": PRECISION_NOTE[args.precision],
+                   "note": "one step = the sampling of all 256 sets (root passes of a class in one launch), "
+                           "replayed as one HIP graph; d = 128 sets run the plain path"},
+        "kernel_evals_per_s": total_pairs / (graph_ms * 1e-3),
+        "p50_ms": float(np.percentile(times_ms, 50)),
+        "p99_ms": float(np.percentile(times_ms, 99)),
+        "batch_steps": n_steps,
+        "eager_batched_ms": eager_ms,
+        "one_by_one_ms": seq_ms,
+        "stages_eager": stages,
+        "tuned_shapes": tuned,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(sets, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batched(sets, target_s: float):
+    """The oracle on seeded rows of a seeded subset of the sets (bounded time)."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    rng = np.random.default_rng(4244)
+    pick = sorted(rng.choice(len(sets), size=8, replace=False).tolist())
+    data = [(sets[i], sets[i].points()) for i in pick]
+    work = 0.0
+    t_cal = 0.0
+    for w, X in data:  # calibrate: 16 rows per set
+        rows = workloads.subsample(w.n, 16, 4245)
+        t0 = time.perf_counter()
+        oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows, want_margin=False)
+        t_cal += time.perf_counter() - t0
+    scale = max(1.0, target_s / max(t_cal, 1e-6))
+    edges = 0
+    evals = 0
+    t0 = time.perf_counter()
+    for w, X in data:
+        m = int(min(w.n, round(16 * scale)))
+        rows = workloads.subsample(w.n, m, 4246)
+        oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows, want_margin=False)
+        edges += m * w.L
+        evals += m * (w.n - 1)
+    dt = time.perf_counter() - t0
+    return {"value": edges / dt, "unit": "sampled edges/s", "kernel_evals_per_s": evals / dt,
+            "cores": oracle.num_threads(), "kind": "oracle", "seconds": dt,
+            "sample": f"seeded rows of 8 seeded sets of the 256 ({', '.join(w.name for w, _ in data)}): "
+                      f"per row the full FP64 kernel row, the degree and L descents"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mix32-n100k")
+    ap.add_argument("--workload", default="mix32-n100k",
+                    help="mix32-n100k (default), blobs2d-n1000, mix64-n1m, or batched-256")
     ap.add_argument("--precision", default="bf16_split", choices=["fp32", "bf16_split"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +266,10 @@ def main():
 
     import paper_2310_13870_amd as fsg
     import workloads
+
+    if args.workload == "batched-256":
+        run_batched(args)
+        return
 
     w = workloads.WORKLOADS[args.workload]()
     X = w.points()

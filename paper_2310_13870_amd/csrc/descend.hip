@@ -7,6 +7,8 @@
 //    up to 64 samples that sit in the same node, evaluates the kernel of each
 //    sample's point against every point of the node (difference form, FP64),
 //    keeps the row in LDS, and each lane walks its own sample to a leaf.
+#include <type_traits>
+
 #include "common.h"
 #include "device.h"
 
@@ -181,108 +183,19 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
 // Leaf stage.  items[2k] = node, items[2k+1] = first position of the item's
 // samples in sorted_samples; an item holds up to 64 samples of one node.
 // ---------------------------------------------------------------------------
-template <int DMAX>
-__global__ __launch_bounds__(64) void leaf_kernel(LeafArgs a) {
-    __shared__ double row[kLeafMax * 64];  // row[j * 64 + lane]: kernel of sample `lane` to node point j
-    __shared__ double xs[DMAX > 0 ? (kLeafMax + 3) * DMAX : 1];  // the node's points, FP64 (+3 rows of slack)
-    const int lane = threadIdx.x;
-    const int32_t n_items = *a.n_items;
-    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int32_t v = a.items[2 * it], p0 = a.items[2 * it + 1];
-        const int32_t p1 = a.node_start[v + 1];
-        const int32_t lo = a.bounds[v];
-        const int32_t hi = min(a.bounds[v + 1], lo + kLeafMax);  // the planner keeps nodes within kLeafMax
-        const int32_t pos = p0 + lane;
-        const bool active = pos < p1;
-        const int32_t smp = active ? a.sorted_samples[pos] : a.sorted_samples[p0];
-        const int32_t i = smp / a.L, l = smp - i * a.L;
-        const float* xi = a.X + (int64_t)i * a.d;
-        if (DMAX > 0) {
-            // stage the node's points (contiguous rows lo..hi-1) in LDS
-            const int32_t cnt = (hi - lo) * a.d;
-            const float* src = a.X + (int64_t)lo * a.d;
-            for (int32_t k = lane; k < cnt; k += 64) {
-                const int32_t r = k / a.d, t = k - r * a.d;
-                xs[r * DMAX + t] = (double)src[k];
-            }
-            __syncthreads();
-            double q[DMAX > 0 ? DMAX : 1];
-#pragma unroll
-            for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? (double)xi[t] : 0.0;
-            // four node points at a time: four independent FP64 chains
-            for (int32_t j0 = lo; j0 < hi; j0 += 4) {
-                double D[4] = {0.0, 0.0, 0.0, 0.0};
-                const double* xj = xs + (j0 - lo) * DMAX;  // rows past hi read stale LDS, never stored
-#pragma unroll
-                for (int t = 0; t < DMAX; ++t) {
-                    if (t < a.d) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double df = q[t] - xj[u * DMAX + t];
-                            D[u] = __builtin_fma(df, df, D[u]);
-                        }
-                    }
-                }
-                double k[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) k[u] = exp2_fp64(-a.s * D[u]);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int32_t j = j0 + u;
-                    if (j < hi) row[(j - lo) * 64 + lane] = (j == i) ? 0.0 : k[u];
-                }
-            }
-        } else {
-            for (int32_t j = lo; j < hi; ++j) {
-                const float* xj = a.X + (int64_t)j * a.d;
-                double D = 0.0;
-                for (int32_t t = 0; t < a.d; ++t) {
-                    const double df = (double)xi[t] - (double)xj[t];
-                    D = __builtin_fma(df, df, D);
-                }
-                row[(j - lo) * 64 + lane] = (j == i) ? 0.0 : exp2_fp64(-a.s * D);
-            }
-        }
-        __syncthreads();
-        if (active) {
-            double total = 0.0;
-            for (int32_t j = lo; j < hi; ++j) total += row[(j - lo) * 64 + lane];
-            if (!(total > 0.0)) {
-                // only reachable at the root (a sample never enters a node of
-                // zero mass): an isolated point has no neighbour
-                a.nbr[smp] = -1;
-            } else {
-                SampleUniforms uni;
-                uni.init(a.seed, (uint64_t)i, (uint64_t)l);
-                const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
-                float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
-                int32_t na = lo, nbd = hi, level = a.level;
-                while (nbd - na > 1) {
-                    const int32_t mid = tree_split(na, nbd);
-                    double mL = 0.0, mR = 0.0;
-                    for (int32_t j = na; j < mid; ++j) mL += row[(j - lo) * 64 + lane];
-                    for (int32_t j = mid; j < nbd; ++j) mR += row[(j - lo) * 64 + lane];
-                    const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
-                    double margin;
-                    const bool left = choose_left(u, mL, mR, &margin);
-                    mg = fminf(mg, (float)margin);
-                    if (left) nbd = mid; else na = mid;
-                    ++level;
-                }
-                a.nbr[smp] = na;
-                if (a.margin != nullptr) a.margin[smp] = mg;
-            }
-        }
-        __syncthreads();
-    }
-}
 
 // Leaf stage for d <= 32: each lane keeps its sample's (<= 64) kernel values
 // in registers; the child masses of every level are summed with static
 // predicates, so the descent has no dependent memory chains.
 template <int DMAX>
 __global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
-    __shared__ double xs[(kLeafMax + 3) * DMAX];  // the node's points, FP64 (+3 rows of slack)
+    // d <= 32: the query row in registers, node points in LDS row by row, four
+    // points at a time.  d > 32: features outer, the 64 points' distances in
+    // registers, node points staged transposed (feature-major) in FP32 (the
+    // input precision; the difference is formed in FP64, where it is exact).
+    constexpr bool kWide = DMAX > 32;
+    typedef typename std::conditional<kWide, float, double>::type stage_t;
+    __shared__ stage_t xs[kWide ? DMAX * kLeafMax : (kLeafMax + 3) * DMAX];
     const int lane = threadIdx.x;
     const int32_t n_items = *a.n_items;
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -296,43 +209,68 @@ __global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
         const int32_t smp = active ? a.sorted_samples[pos] : a.sorted_samples[p0];
         const int32_t i = smp / a.L, l = smp - i * a.L;
         const float* xi = a.X + (int64_t)i * a.d;
-        {
-            const int32_t total = cnt * a.d;
-            const float* src = a.X + (int64_t)lo * a.d;
-            for (int32_t k = lane; k < total; k += 64) {
-                const int32_t r = k / a.d, t = k - r * a.d;
-                xs[r * DMAX + t] = (double)src[k];
-            }
-        }
-        __syncthreads();
-        double q[DMAX];
-#pragma unroll
-        for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? (double)xi[t] : 0.0;
         const int32_t self = i - lo;  // the sample's own point, if it lies in the node
         double kv[kLeafMax];
+        if constexpr (kWide) {
+            // xs[t * 64 + j] = X[lo + j][t]; points past the node are 0
+            for (int32_t k = lane; k < a.d * kLeafMax; k += 64) {
+                const int32_t t = k / kLeafMax, j = k - t * kLeafMax;
+                xs[k] = (j < cnt) ? a.X[(int64_t)(lo + j) * a.d + t] : 0.0f;
+            }
+            __syncthreads();
 #pragma unroll
-        for (int j0 = 0; j0 < kLeafMax; j0 += 4) {
-            if (j0 < cnt) {
-                double D[4] = {0.0, 0.0, 0.0, 0.0};
-                const double* xj = xs + j0 * DMAX;
+            for (int j = 0; j < kLeafMax; ++j) kv[j] = 0.0;  // the distances first
+            for (int32_t t = 0; t < a.d; ++t) {
+                const double qt = (double)xi[t];
+                const stage_t* xt = xs + t * kLeafMax;
 #pragma unroll
-                for (int t = 0; t < DMAX; ++t) {
-                    if (t < a.d) {
+                for (int j = 0; j < kLeafMax; ++j) {
+                    const double df = qt - (double)xt[j];
+                    kv[j] = __builtin_fma(df, df, kv[j]);
+                }
+            }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double df = q[t] - xj[u * DMAX + t];
-                            D[u] = __builtin_fma(df, df, D[u]);
+            for (int j = 0; j < kLeafMax; ++j) {
+                const double k = exp2_fp64(-a.s * kv[j]);
+                kv[j] = (j < cnt && j != self) ? k : 0.0;
+            }
+        } else {
+            {
+                const int32_t total = cnt * a.d;
+                const float* src = a.X + (int64_t)lo * a.d;
+                for (int32_t k = lane; k < total; k += 64) {
+                    const int32_t r = k / a.d, t = k - r * a.d;
+                    xs[r * DMAX + t] = (stage_t)src[k];
+                }
+            }
+            __syncthreads();
+            stage_t q[DMAX];
+#pragma unroll
+            for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? (stage_t)xi[t] : (stage_t)0;
+#pragma unroll
+            for (int j0 = 0; j0 < kLeafMax; j0 += 4) {
+                if (j0 < cnt) {
+                    double D[4] = {0.0, 0.0, 0.0, 0.0};
+                    const stage_t* xj = xs + j0 * DMAX;
+#pragma unroll
+                    for (int t = 0; t < DMAX; ++t) {
+                        if (t < a.d) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const double df = (double)q[t] - (double)xj[u * DMAX + t];
+                                D[u] = __builtin_fma(df, df, D[u]);
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double k = exp2_fp64(-a.s * D[u]);
-                    kv[j0 + u] = (j0 + u < cnt && j0 + u != self) ? k : 0.0;
-                }
-            } else {
+                    for (int u = 0; u < 4; ++u) {
+                        const double k = exp2_fp64(-a.s * D[u]);
+                        kv[j0 + u] = (j0 + u < cnt && j0 + u != self) ? k : 0.0;
+                    }
+                } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) kv[j0 + u] = 0.0;
+                    for (int u = 0; u < 4; ++u) kv[j0 + u] = 0.0;
+                }
             }
         }
         __syncthreads();  // xs is reused by the next item
@@ -384,8 +322,9 @@ hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStr
     else if (a.d <= 8) leaf_reg_kernel<8><<<(unsigned)blocks, 64, 0, st>>>(a);
     else if (a.d <= 16) leaf_reg_kernel<16><<<(unsigned)blocks, 64, 0, st>>>(a);
     else if (a.d <= 32) leaf_reg_kernel<32><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 64) leaf_kernel<64><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else leaf_kernel<0><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 64) leaf_reg_kernel<64><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.d <= 128) leaf_reg_kernel<128><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
