@@ -235,6 +235,60 @@ fsg_status fsg_graph_end(fsg_ctx* ctx, fsg_graph** out);
 fsg_status fsg_graph_launch(fsg_ctx* ctx, fsg_graph* g);
 void fsg_graph_destroy(fsg_graph* g);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over one context.  Graph-build requests (Algorithm
+ * 2 for a new point set) and KDE requests (eq. (1) for query points against a
+ * resident set) are queued, admitted in arrival order while the HBM budget
+ * and the active-build limit allow (ready sets that no queued or running
+ * request needs are evicted, least recently used first), and advanced by
+ * fsg_server_poll: every admitted build moves one stage per poll, and the
+ * root passes of builds admitted together run in one launch (continuous
+ * batching).  A finished build's point set, sampled neighbours, degrees and
+ * symmetric CSR stay resident until evicted.  Results equal the single-call
+ * path (fsg_sample_edges + fsg_build_csr, fsg_kde_segmented) bit for bit,
+ * whatever else is in flight.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct fsg_server fsg_server;
+
+/* hbm_budget_bytes bounds the server's resident sets plus admitted builds
+ * (the context's workspace is counted separately); max_active bounds the
+ * builds in flight (>= 1). */
+fsg_status fsg_server_create(fsg_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_active, fsg_server** out);
+void fsg_server_destroy(fsg_server* srv);
+
+/* Build request for a new set `set_id` (caller's unique id >= 0): X_dev is
+ * FP32 n x d on the device and must stay valid until the request completes
+ * (the server copies it at admission).  *req_id receives the request id.
+ * FSG_E_INVALID for a reused set_id or bad arguments; FSG_E_BUDGET if the set
+ * alone could never fit the budget. */
+fsg_status fsg_server_submit_build(fsg_server* srv, int64_t set_id, const float* X_dev, int64_t n, int32_t d,
+                                   double gamma, int32_t L, uint64_t seed, fsg_precision prec, int64_t* req_id);
+
+/* KDE request: out_dev[i] = sum_j exp(-gamma |q_i - x_j|^2) over all points
+ * x_j of set `set_id`, for the m query rows of Q_dev (FP32 m x d, valid until
+ * completion; out_dev FP64 [m]).  Waits while the set is still being built;
+ * completes with FSG_E_INVALID if the set is unknown or has been evicted. */
+fsg_status fsg_server_submit_kde(fsg_server* srv, int64_t set_id, const float* Q_dev, int64_t m, double gamma,
+                                 double* out_dev, int64_t* req_id);
+
+/* One turn of the loop: collect requests whose device work has finished,
+ * admit queued requests, advance every active build by one stage and launch
+ * admitted KDE requests.  Up to `cap` finished request ids and their statuses
+ * are written to done_ids / done_status (*n_done of them); the rest are
+ * reported by later polls.  Does not wait for the device. */
+fsg_status fsg_server_poll(fsg_server* srv, int64_t* done_ids, int32_t* done_status, int32_t cap, int32_t* n_done);
+
+/* Device arrays of a resident, finished set (owned by the server, valid until
+ * the set is evicted or the server destroyed): row_ptr int64 [n+1], col int32
+ * [nnz], w FP32 [nnz], nbr int32 [n*L], deg FP64 [n].  Any output may be NULL. */
+fsg_status fsg_server_graph(fsg_server* srv, int64_t set_id, const int64_t** row_ptr, const int32_t** col,
+                            const float** w, int64_t* nnz, const int32_t** nbr, const double** deg);
+
+/* Counters: bytes held by resident sets and admitted builds, builds in flight,
+ * queued requests, evicted sets so far. */
+fsg_status fsg_server_stats(fsg_server* srv, uint64_t* resident_bytes, int32_t* active, int32_t* queued,
+                            int64_t* evictions);
+
 #ifdef __cplusplus
 }
 #endif

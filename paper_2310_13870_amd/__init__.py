@@ -67,6 +67,18 @@ _lib_fns = dict(
     fsg_graph_end=_sig("fsg_graph_end", ctypes.c_int, _vp, ctypes.POINTER(_vp)),
     fsg_graph_launch=_sig("fsg_graph_launch", ctypes.c_int, _vp, _vp),
     fsg_graph_destroy=_sig("fsg_graph_destroy", None, _vp),
+    fsg_server_create=_sig("fsg_server_create", ctypes.c_int, _vp, _u64, _i32, ctypes.POINTER(_vp)),
+    fsg_server_destroy=_sig("fsg_server_destroy", None, _vp),
+    fsg_server_submit_build=_sig("fsg_server_submit_build", ctypes.c_int, _vp, _i64, _vp, _i64, _i32, _dbl, _i32,
+                                 _u64, ctypes.c_int, ctypes.POINTER(_i64)),
+    fsg_server_submit_kde=_sig("fsg_server_submit_kde", ctypes.c_int, _vp, _i64, _vp, _i64, _dbl, _vp,
+                               ctypes.POINTER(_i64)),
+    fsg_server_poll=_sig("fsg_server_poll", ctypes.c_int, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), _i32,
+                         ctypes.POINTER(_i32)),
+    fsg_server_graph=_sig("fsg_server_graph", ctypes.c_int, _vp, _i64, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                          ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)),
+    fsg_server_stats=_sig("fsg_server_stats", ctypes.c_int, _vp, ctypes.POINTER(_u64), ctypes.POINTER(_i32),
+                          ctypes.POINTER(_i32), ctypes.POINTER(_i64)),
 )
 EXPORTED = sorted(_lib_fns)
 
@@ -330,6 +342,98 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None):
             _lib.fsg_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip_rt = None
+
+
+def _view(ptr: int, count: int, dtype, device) -> torch.Tensor:
+    """A copy of `count` elements at a library-owned device address (copied
+    out, so that the result does not alias memory the library may reuse)."""
+    global _hip_rt
+    out = torch.empty(count, dtype=dtype, device=device)
+    if count == 0:
+        return out
+    if _hip_rt is None:
+        _hip_rt = ctypes.CDLL("libamdhip64.so")
+        _hip_rt.hipMemcpy.restype = ctypes.c_int
+        _hip_rt.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+    err = _hip_rt.hipMemcpy(out.data_ptr(), ptr, count * out.element_size(), 3)  # device to device
+    if err != 0:
+        raise RuntimeError(f"hipMemcpy failed ({err})")
+    return out
+
+
+class Server:
+    """fsg_server: request loop with HBM-budget admission, resident sets and
+    continuous batching of graph builds and KDE queries."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_active: int = 16):
+        self.ctx = ctx
+        h = _vp()
+        ctx.check(_lib.fsg_server_create(ctx._h, hbm_budget_bytes, max_active, ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # request id -> tensors that must stay valid until completion
+
+    def submit_build(self, set_id: int, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_FP32) -> int:
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        _dev_tensor(X, torch.float32, "X")
+        rid = _i64(0)
+        self.ctx.check(_lib.fsg_server_submit_build(self._h, set_id, _ptr(X), X.shape[0], X.shape[1], gamma, L, seed,
+                                                    precision, ctypes.byref(rid)))
+        self._keep[rid.value] = (X,)
+        return rid.value
+
+    def submit_kde(self, set_id: int, Q: torch.Tensor, gamma: float, out: torch.Tensor = None):
+        _dev_tensor(Q, torch.float32, "Q")
+        if out is None:
+            out = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+        rid = _i64(0)
+        self.ctx.check(_lib.fsg_server_submit_kde(self._h, set_id, _ptr(Q), Q.shape[0], gamma, _ptr(out),
+                                                  ctypes.byref(rid)))
+        self._keep[rid.value] = (Q, out)
+        return rid.value, out
+
+    def poll(self, cap: int = 256):
+        """[(request id, status)] of requests completed since the last poll."""
+        ids = (_i64 * cap)()
+        sts = (_i32 * cap)()
+        nd = _i32(0)
+        self.ctx.check(_lib.fsg_server_poll(self._h, ids, sts, cap, ctypes.byref(nd)))
+        out = [(ids[k], sts[k]) for k in range(nd.value)]
+        for rid, _ in out:
+            self._keep.pop(rid, None)
+        return out
+
+    def graph(self, set_id: int, n: int, L: int):
+        """Copies of a finished set's (row_ptr, col, w, nbr, deg)."""
+        rp, c, w, nb, dg = _vp(), _vp(), _vp(), _vp(), _vp()
+        nnz = _i64(0)
+        self.ctx.check(_lib.fsg_server_graph(self._h, set_id, ctypes.byref(rp), ctypes.byref(c), ctypes.byref(w),
+                                             ctypes.byref(nnz), ctypes.byref(nb), ctypes.byref(dg)))
+        dev = torch.device("cuda", self.ctx.device)
+        torch.cuda.current_stream().synchronize()
+        return (_view(rp.value, n + 1, torch.int64, dev), _view(c.value, nnz.value, torch.int32, dev),
+                _view(w.value, nnz.value, torch.float32, dev), _view(nb.value, n * L, torch.int32, dev),
+                _view(dg.value, n, torch.float64, dev))
+
+    def stats(self):
+        b, a, q, e = _u64(0), _i32(0), _i32(0), _i64(0)
+        self.ctx.check(_lib.fsg_server_stats(self._h, ctypes.byref(b), ctypes.byref(a), ctypes.byref(q),
+                                             ctypes.byref(e)))
+        return {"bytes": b.value, "active": a.value, "queued": q.value, "evictions": e.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fsg_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -597,6 +597,47 @@ static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
     return FSG_OK;
 }
 
+// Row-sorted CSR (Algorithm 2's reweighting) enqueued without
+// synchronisation: row_ptr[n] receives 2|E| on the device and *n_long_dev the
+// number of rows longer than the row sort handles (their rows are left empty:
+// the caller then rebuilds with fsg_build_csr, which falls back to a global
+// sort).  cap >= 2 n L always suffices.
+fsg_status csr_rows_async(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, const int32_t* nbr_dev,
+                          const double* deg_dev, int64_t* row_ptr_dev, int32_t* col_dev, float* w_dev, int64_t cap,
+                          int32_t* n_long_dev) {
+    const int64_t n = X->n;
+    const int64_t m = 2 * n * (int64_t)L;
+    if (m > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "2*n*L must be < 2^31");
+    fsg_status st;
+    int32_t* ent;
+    uint32_t *cnt, *fillc, *off, *off_part;
+    int64_t *uniq, *uniq_part;
+    if ((st = ws(ctx, "csr_ent", (size_t)m + 1, &ent)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_cnt", (size_t)n + 1, &cnt)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_fillc", (size_t)n + 1, &fillc)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_off", (size_t)n + 1, &off)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_off_part", (size_t)scan_partials(n) + 1, &off_part)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_uniq", (size_t)n + 1, &uniq)) != FSG_OK) return st;
+    if ((st = ws(ctx, "csr_uniq_part", (size_t)scan_partials(n) + 1, &uniq_part)) != FSG_OK) return st;
+    CsrRowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ent = ent;
+    a.in_off = off;
+    a.n = n;
+    a.d = X->d;
+    a.X = X->X;
+    a.deg = deg_dev;
+    a.s = gamma * 1.442695040888963407359924681001892137;
+    a.L = L;
+    a.row_ptr = row_ptr_dev;
+    a.col = col_dev;
+    a.w = w_dev;
+    a.cap = cap;
+    StageTimer t(ctx, "csr");
+    FSG_HIP(ctx, launch_csr_rows(a, nbr_dev, L, cnt, fillc, off, off_part, uniq, uniq_part, n_long_dev, ctx->stream));
+    return FSG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batching: jobs, and the root pass of many jobs in one launch.
 // ---------------------------------------------------------------------------
@@ -985,6 +1026,10 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
         for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
         p->ctx = nullptr;
     }
+    {
+        const std::set<fsg_server*> servers = ctx->servers;
+        for (fsg_server* srv : servers) server_detach(srv);
+    }
     for (BatchTables* T : ctx->batch_cache) free_tables(T);
     ctx->batch_cache.clear();
     // live jobs are detached; their buffers are freed here
@@ -1265,37 +1310,11 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
     fsg_status st;
     // row-sorted construction
     {
-        int32_t* ent;
-        uint32_t *cnt, *fillc, *off, *off_part;
-        int64_t *uniq, *uniq_part;
         int32_t* n_long;
-        if ((st = ws(ctx, "csr_ent", (size_t)m + 1, &ent)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_cnt", (size_t)n + 1, &cnt)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_fillc", (size_t)n + 1, &fillc)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_off", (size_t)n + 1, &off)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_off_part", (size_t)scan_partials(n) + 1, &off_part)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_uniq", (size_t)n + 1, &uniq)) != FSG_OK) return st;
-        if ((st = ws(ctx, "csr_uniq_part", (size_t)scan_partials(n) + 1, &uniq_part)) != FSG_OK) return st;
         if ((st = ws(ctx, "csr_nlong", 1, &n_long)) != FSG_OK) return st;
-        CsrRowArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.ent = ent;
-        a.in_off = off;
-        a.n = n;
-        a.d = X->d;
-        a.X = X->X;
-        a.deg = deg_dev;
-        a.s = gamma * 1.442695040888963407359924681001892137;
-        a.L = L;
-        a.row_ptr = row_ptr_dev;
-        a.col = col_dev;
-        a.w = w_dev;
-        a.cap = cap;
-        {
-            StageTimer t(ctx, "csr");
-            FSG_HIP(ctx, launch_csr_rows(a, nbr_dev, L, cnt, fillc, off, off_part, uniq, uniq_part, n_long,
-                                         ctx->stream));
-        }
+        if ((st = csr_rows_async(ctx, X, gamma, L, nbr_dev, deg_dev, row_ptr_dev, col_dev, w_dev, cap, n_long)) !=
+            FSG_OK)
+            return st;
         FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch, row_ptr_dev + n, sizeof(int64_t), hipMemcpyDeviceToHost,
                                     ctx->stream));
         FSG_HIP(ctx, hipMemcpyAsync(ctx->host_scratch + 1, n_long, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -1353,6 +1372,42 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
     return FSG_OK;
 }
 
+
+}  // extern "C"
+
+namespace fsg {
+
+bool job_finished(const fsg_job* j) { return j && j->stage >= j->n_stages; }
+
+// Bytes a build of n points in R^d needs: the point set's arrays, the
+// result kept with it (sampled neighbours, degrees, CSR) and a server copy
+// of the input (*resident), and the job's buffers while it runs (*transient).
+void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, fsg_precision prec,
+                          uint64_t* resident, uint64_t* transient) {
+    const int D4 = feature_steps(d);
+    const uint64_t n_pad = (uint64_t)((n + 15) & ~(int64_t)15);
+    const uint64_t ns = (uint64_t)n * (uint64_t)L;
+    uint64_t pts = n_pad * 4 * (uint64_t)D4 * 8 + n_pad * 8 + 2 * n_pad * 4;  // rows, norms, level bounds
+    if (prec == FSG_BF16_SPLIT) {
+        const uint64_t KB = (uint64_t)filter_steps(D4);
+        pts += 2 * (n_pad / 16) * KB * 64 * 16 + (uint64_t)n * 12 + n_pad * 4 + 256;
+    }
+    const uint64_t result = ((uint64_t)n + 1) * 8 + 2 * ns * 8 + ns * 4 + (uint64_t)n * 8 + 256;
+    *resident = pts + result + (uint64_t)n * (uint64_t)d * 4;
+    const Plan plan = make_plan(n, L, ctx->budget, ctx->max_levels_per_pass);
+    uint64_t job = ns * 8 + (uint64_t)n * 8;
+    if (!plan.passes.empty()) {
+        const int D = plan.passes[0].second;
+        const uint64_t n_uleaf = (uint64_t)(tree_depth(n) - plan.leaf_level);
+        job += ns * n_uleaf * 8 + ((uint64_t)n << D) * 8;
+        if (prec == FSG_BF16_SPLIT) job += (uint64_t)((n + kTileQ - 1) / kTileQ) * (n_pad / 16) * 2;
+    }
+    *transient = job;
+}
+
+}  // namespace fsg
+
+extern "C" {
 
 fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int32_t L, uint64_t seed,
                           fsg_job** out) {

@@ -120,6 +120,7 @@ struct Arena;
 namespace fsg {
 struct BatchTables;  // device tables of a batched root pass (api.hip)
 }
+struct fsg_server;
 
 struct fsg_ctx {
     int device = 0;
@@ -156,6 +157,9 @@ struct fsg_ctx {
     // live batch jobs; their buffers are freed and they are detached when the
     // context is destroyed
     std::set<fsg_job*> jobs;
+    // live servers: their sets and requests are released when the context is
+    // destroyed (the handles stay valid for fsg_server_destroy)
+    std::set<fsg_server*> servers;
 };
 
 
@@ -362,6 +366,13 @@ struct CsrRowArgs {
     float* w;
     int64_t cap;
 };
+bool job_finished(const fsg_job* j);
+void server_detach(fsg_server* s);  // release everything a server holds on its context
+void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, fsg_precision prec,
+                          uint64_t* resident, uint64_t* transient);
+fsg_status csr_rows_async(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_t L, const int32_t* nbr_dev,
+                          const double* deg_dev, int64_t* row_ptr_dev, int32_t* col_dev, float* w_dev, int64_t cap,
+                          int32_t* n_long_dev);
 hipError_t launch_csr_rows(const CsrRowArgs& a, const int32_t* nbr, int32_t L, uint32_t* cnt, uint32_t* fillc,
                            uint32_t* off, uint32_t* off_partials, int64_t* uniq, int64_t* uniq_partials,
                            int32_t* n_long, hipStream_t st);
