@@ -209,6 +209,134 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def serving_trace(seconds: float, rate: float, seed: int = 1004):
+    """Seeded open-loop trace: Poisson arrivals; 80% builds of a point set from
+    a pool of 64 (n log-uniform in [2e3, 2e5], d 64, 20 components, means
+    U[-10,10], std U[0.5,2], sigma 3, L ceil(log2 n)), 20% KDE queries of
+    10,000 points of the same mixture family; precision 50/50 per request."""
+    import numpy as np
+    import workloads
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(64):
+        n = int(round(math.exp(rng.uniform(math.log(2e3), math.log(2e5)))))
+        pool.append(workloads.Workload(f"pool{k}-n{n}", n, 64, 3.0, workloads.depth_of(n), seed * 1000 + k,
+                                       seed * 1000 + 500 + k, 20, (-10.0, 10.0), (0.5, 2.0)))
+    t, reqs = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        kind = "build" if rng.random() < 0.8 else "kde"
+        prec = "bf16_split" if rng.random() < 0.5 else "fp32"
+        reqs.append({"t": t, "kind": kind, "pool": int(rng.integers(len(pool))), "prec": prec,
+                     "seed": int(rng.integers(1 << 62)), "pick": float(rng.random())})
+    return pool, reqs
+
+
+def run_serving(args):
+    """Open-loop serving run of the request loop (fsg_server_*): completion
+    minus scheduled arrival per request, aggregate sampled edges/s."""
+    import numpy as np
+    import torch
+
+    import paper_2310_13870_amd as fsg
+    import workloads
+
+    pool, reqs = serving_trace(args.serve_seconds, 50.0)
+    dev = torch.device("cuda:0")
+    Xp = [torch.from_numpy(w.points()).to(dev) for w in pool]
+    Qp = [torch.from_numpy(workloads.mixture(10_000, w.d, w.n_comp, w.data_seed + 7, w.mean_range, w.std_range))
+          .to(dev) for w in pool]
+    torch.cuda.synchronize()
+    ctx = fsg.Context(0)
+    srv = fsg.Server(ctx, 200 << 30, 16)
+    # warm the kernels and the workspace on one build of each precision
+    for k, prec in enumerate(("fp32", "bf16_split")):
+        rid = srv.submit_build(1_000_000 + k, Xp[0], pool[0].gamma, pool[0].L, 1, prec)
+        while not any(r == rid for r, _ in srv.poll()):
+            pass
+    info, arrival, done_at = {}, {}, {}
+    ready_sets = []  # finished build sets, in completion order
+    waiting_kde = []
+    next_i, set_id = 0, 0
+    sid_pool = {}
+    t0 = time.perf_counter()
+    while next_i < len(reqs) or len(done_at) < len(info) or waiting_kde:
+        now = time.perf_counter() - t0
+        if now > args.serve_seconds + 300:
+            print("serving run did not drain", file=sys.stderr)
+            break
+        while next_i < len(reqs) and reqs[next_i]["t"] <= now:
+            r = reqs[next_i]
+            next_i += 1
+            if r["kind"] == "build":
+                w = pool[r["pool"]]
+                rid = srv.submit_build(set_id, Xp[r["pool"]], w.gamma, w.L, r["seed"], r["prec"])
+                info[rid] = ("build", set_id, w.n * w.L, r["prec"])
+                arrival[rid] = r["t"]
+                sid_pool[set_id] = r["pool"]
+                set_id += 1
+            else:
+                waiting_kde.append(r)
+        # a KDE query targets a finished set chosen at random; it waits for one
+        while waiting_kde and ready_sets:
+            r = waiting_kde.pop(0)
+            recent = ready_sets[-64:]  # recently finished: resident
+            sid, pk = recent[int(r["pick"] * len(recent))]
+            w = pool[pk]
+            rid, _ = srv.submit_kde(sid, Qp[pk], w.gamma)
+            info[rid] = ("kde", sid, 0, r["prec"])
+            arrival[rid] = r["t"]
+        for rid, st in srv.poll():
+            if rid not in info:
+                continue
+            done_at[rid] = time.perf_counter() - t0
+            kind, sid, _, _ = info[rid]
+            if kind == "build" and st == fsg.FSG_OK:
+                ready_sets.append((sid, sid_pool[sid]))
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    ctx.close()
+    lat = np.array([(done_at[r] - arrival[r]) * 1e3 for r in done_at])
+    lat_b = np.array([(done_at[r] - arrival[r]) * 1e3 for r in done_at if info[r][0] == "build"])
+    lat_k = np.array([(done_at[r] - arrival[r]) * 1e3 for r in done_at if info[r][0] == "kde"])
+    edges = sum(info[r][2] for r in done_at if info[r][0] == "build")
+    n_builds = sum(1 for r in info if info[r][0] == "build")
+    out = {
+        "metric": METRIC,
+        "value": edges / wall,
+        "unit": "sampled edges/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 2,
+        "ms_per_step": 1e3 * wall / max(len(reqs), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving-50rps-{args.serve_seconds:g}s", "requests": len(reqs), "builds": n_builds,
+                   "kde_requests": len(reqs) - n_builds, "hbm_budget_gb": 200, "max_active_builds": 16,
+                   "precision": "50/50 fp32 / bf16_split per request",
+                   "note": "one step = one request; value = sampled edges of completed builds / wall time of the trace"},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "build_p50_ms": float(np.percentile(lat_b, 50)) if lat_b.size else None,
+        "build_p99_ms": float(np.percentile(lat_b, 99)) if lat_b.size else None,
+        "kde_p50_ms": float(np.percentile(lat_k, 50)) if lat_k.size else None,
+        "kde_p99_ms": float(np.percentile(lat_k, 99)) if lat_k.size else None,
+        "wall_s": wall,
+        "completed": len(done_at),
+        "evictions": stats["evictions"],
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(pool, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batched(sets, target_s: float):
     """The oracle on seeded rows of a seeded subset of the sets (bounded time)."""
     import numpy as np
@@ -238,7 +366,7 @@ def cpu_baseline_batched(sets, target_s: float):
     dt = time.perf_counter() - t0
     return {"value": edges / dt, "unit": "sampled edges/s", "kernel_evals_per_s": evals / dt,
             "cores": oracle.num_threads(), "kind": "oracle", "seconds": dt,
-            "sample": f"seeded rows of 8 seeded sets of the 256 ({', '.join(w.name for w, _ in data)}): "
+            "sample": f"seeded rows of 8 seeded sets of the {len(sets)} ({', '.join(w.name for w, _ in data)}): "
                       f"per row the full FP64 kernel row, the degree and L descents"}
 
 
@@ -248,7 +376,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mix32-n100k",
-                    help="mix32-n100k (default), blobs2d-n1000, mix64-n1m, or batched-256")
+                    help="mix32-n100k (default), blobs2d-n1000, mix64-n1m, batched-256, or serving")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
     ap.add_argument("--precision", default="bf16_split", choices=["fp32", "bf16_split"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -269,6 +398,9 @@ def main():
 
     if args.workload == "batched-256":
         run_batched(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
 
     w = workloads.WORKLOADS[args.workload]()

@@ -271,11 +271,14 @@ fsg_status fsg_server_submit_build(fsg_server* srv, int64_t set_id, const float*
 fsg_status fsg_server_submit_kde(fsg_server* srv, int64_t set_id, const float* Q_dev, int64_t m, double gamma,
                                  double* out_dev, int64_t* req_id);
 
-/* One turn of the loop: collect requests whose device work has finished,
- * admit queued requests, advance every active build by one stage and launch
- * admitted KDE requests.  Up to `cap` finished request ids and their statuses
- * are written to done_ids / done_status (*n_done of them); the rest are
- * reported by later polls.  Does not wait for the device. */
+/* One turn of the loop: collect requests whose device work has finished;
+ * then, if the work the previous turn enqueued has finished, admit queued
+ * requests, advance every active build by one stage and launch admitted KDE
+ * requests (iteration-level scheduling: requests arriving while the device
+ * is busy are admitted together, and their root passes share launches).  Up
+ * to `cap` finished request ids and their statuses are written to done_ids /
+ * done_status (*n_done of them); the rest are reported by later polls.  Does
+ * not wait for the device. */
 fsg_status fsg_server_poll(fsg_server* srv, int64_t* done_ids, int32_t* done_status, int32_t cap, int32_t* n_done);
 
 /* Device arrays of a resident, finished set (owned by the server, valid until

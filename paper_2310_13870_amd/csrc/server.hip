@@ -95,6 +95,7 @@ struct fsg_server {
     std::vector<SetRec*> building;
     std::deque<Req*> finished;    // complete, not yet reported
     std::vector<hipEvent_t> events;
+    hipEvent_t step_ev = nullptr; // recorded after the work a poll enqueued
     int64_t* host = nullptr;      // pinned slots: {nnz, n_long} of finished builds
     std::vector<int32_t> free_slots;
 };
@@ -208,6 +209,21 @@ void finish(fsg_server* s, Req* q, int32_t status) {
     s->finished.push_back(q);
 }
 
+// hand up to `cap` finished requests to the caller
+fsg_status report(fsg_server* s, int64_t* done_ids, int32_t* done_status, int32_t cap, int32_t* n_done) {
+    int32_t nd = 0;
+    while (nd < cap && !s->finished.empty()) {
+        Req* q = s->finished.front();
+        s->finished.pop_front();
+        done_ids[nd] = q->id;
+        done_status[nd] = q->status;
+        ++nd;
+        delete q;
+    }
+    *n_done = nd;
+    return FSG_OK;
+}
+
 }  // namespace
 
 namespace fsg {
@@ -235,6 +251,8 @@ void server_detach(fsg_server* s) {
     s->building.clear();
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     s->events.clear();
+    if (s->step_ev) (void)hipEventDestroy(s->step_ev);
+    s->step_ev = nullptr;
     if (s->host) (void)hipHostFree(s->host);
     s->host = nullptr;
     s->ctx->servers.erase(s);
@@ -383,6 +401,14 @@ fsg_status fsg_server_poll(fsg_server* s, int64_t* done_ids, int32_t* done_statu
         s->running.erase(s->running.begin() + k);
         finish(s, q, status);
     }
+    // new work starts once the previous poll's work has finished, so that the
+    // requests arriving meanwhile are admitted (and their root passes
+    // batched) together
+    if (s->step_ev != nullptr) {
+        const hipError_t e = hipEventQuery(s->step_ev);
+        if (e == hipErrorNotReady) return report(s, done_ids, done_status, cap, n_done);
+        if (e != hipSuccess) (void)hipGetLastError();
+    }
     // 2. admission in arrival order; a KDE request whose set is still being
     // built waits without holding up the requests behind it
     for (auto it = s->queue.begin(); it != s->queue.end();) {
@@ -468,17 +494,12 @@ fsg_status fsg_server_poll(fsg_server* s, int64_t* done_ids, int32_t* done_statu
             s->building.erase(s->building.begin() + k);
         }
     }
-    int32_t nd = 0;
-    while (nd < cap && !s->finished.empty()) {
-        Req* q = s->finished.front();
-        s->finished.pop_front();
-        done_ids[nd] = q->id;
-        done_status[nd] = q->status;
-        ++nd;
-        delete q;
+    if (s->step_ev == nullptr) {
+        s->step_ev = take_ev(s);
+        if (!s->step_ev) return set_error(ctx, FSG_E_DEVICE, "server: event creation failed");
     }
-    *n_done = nd;
-    return FSG_OK;
+    FSG_HIP(ctx, hipEventRecord(s->step_ev, ctx->stream));
+    return report(s, done_ids, done_status, cap, n_done);
 }
 
 fsg_status fsg_server_graph(fsg_server* s, int64_t set_id, const int64_t** row_ptr, const int32_t** col,
