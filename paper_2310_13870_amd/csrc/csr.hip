@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __res
                                                            int64_t n, int32_t* __restrict__ n_long) {
     __shared__ int32_t buf_all[4][kRowSortMax];
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = (int64_t)blockIdx.x * 4 + (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     if (row >= n) return;  // uniform per wave
     const int64_t b = (int64_t)L * row + in_off[row];
     const int32_t len = (int32_t)(L + in_off[row + 1] - in_off[row]);
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __res
 // directions of an edge get bit-identical weights.
 __global__ __launch_bounds__(256) void csr_row_fill_kernel(CsrRowArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = (int64_t)blockIdx.x * 4 + (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     if (row >= a.n) return;
     const int64_t rp = a.row_ptr[row];
     const int64_t cnt = a.row_ptr[row + 1] - rp;

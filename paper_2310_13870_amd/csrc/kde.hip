@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
     __shared__ int32_t win_all[4][kBinWindow];
     const int lane = threadIdx.x & 63;
     int32_t* win = win_all[threadIdx.x >> 6];
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
     const int grp = lane >> 4;  // data row group inside a 16-column block

@@ -41,10 +41,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     // Queries are the A operand and data the B operand, so lane l receives
     // query rows 4(l/16) + i of a query block and data column l % 16: a column
     // is kept when any of the 4 lane groups sees a compare succeed.
-    __shared__ float4_t theta_all[4][4][64];  // [wave][query block][lane]: thresholds of rows 4(l/16)+i
     const int lane = threadIdx.x & 63;
-    float4_t* theta_lds = &theta_all[threadIdx.x >> 6][0][0];
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int grp = lane >> 4;
     const int r = lane & 15;
@@ -69,7 +67,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
         const int64_t e0 = tile * kTileQ;
         const int32_t ne = (int32_t)min((int64_t)kTileQ, m.n_entries - e0);
         bf16x8_t qb16[4][KB];
-        __builtin_amdgcn_wave_barrier();
+        float4_t theta[4];  // keep-thresholds of result rows 4(l/16)+i of each query block
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) {
             {
@@ -103,29 +101,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
                 }
                 thq[i] = ok ? thf : __builtin_inff();
             }
-            theta_lds[qb * 64 + lane] = thq;
+            theta[qb] = thq;
         }
         __builtin_amdgcn_wave_barrier();
         const int64_t bb = chunk * m.blocks_per_chunk;
         const int64_t be = min(m.n_blocks, bb + m.blocks_per_chunk);
         uint16_t* mrow = m.mask + tile * m.n_blocks;
-        bf16x8_t xb[KB], xn[KB];
-        float xa = m.xa[bb * 16 + r], xan = 0.0f;  // -|x|^2/2 of this lane's data column
         const bf16x8_t* X16 = (const bf16x8_t*)m.Xb;
+        // the operands of block b: split data rows and -|x|^2/2 of this lane's column
+        auto load = [&](bf16x8_t (&x)[KB], float& xa, int64_t blk) {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(bb * KB + kb) * 64 + lane];
+            for (int kb = 0; kb < KB; ++kb) x[kb] = X16[(blk * KB + kb) * 64 + lane];
+            xa = m.xa[blk * 16 + r];
+        };
         uint32_t pending = 0;  // lane (b mod 64) keeps the mask of block b until 64 are ready
-        for (int64_t b = bb; b < be; ++b) {
-            if (PREFETCH && b + 1 < be) {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) xn[kb] = X16[((b + 1) * KB + kb) * 64 + lane];
-                xan = m.xa[(b + 1) * 16 + r];
-            }
-            if (!PREFETCH && b > bb) {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) xb[kb] = X16[(b * KB + kb) * 64 + lane];
-                xa = m.xa[b * 16 + r];
-            }
+        auto step = [&](const bf16x8_t (&x)[KB], float xa, int64_t blk) {
             // four independent accumulators, K step outer, so that no matrix
             // op waits for the previous one's result
             float4_t cc[4];
@@ -135,26 +125,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
                 for (int qb = 0; qb < 4; ++qb)
-                    cc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], xb[kb], cc[qb], 0, 0, 0);
+                    cc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], x[kb], cc[qb], 0, 0, 0);
             uint64_t any = 0;
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb) {
-                const float4_t th = theta_lds[qb * 64 + lane];
+            for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) any |= __ballot(cc[qb][i] >= th[i]);
-            }
+                for (int i = 0; i < 4; ++i) any |= __ballot(cc[qb][i] >= theta[qb][i]);
             uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & 0xFFFFull);
-            if (16 * (b + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * b)) - 1u;
+            if (16 * (blk + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * blk)) - 1u;
             kept += __popc(keep);
-            if ((b & 63) == lane) pending = keep;
-            if ((b & 63) == 63 || b + 1 == be) {
-                const int64_t base = b & ~(int64_t)63;
-                if (base + lane >= bb && base + lane <= b) mrow[base + lane] = (uint16_t)pending;
+            if ((blk & 63) == lane) pending = keep;
+            if ((blk & 63) == 63 || blk + 1 == be) {
+                const int64_t base = blk & ~(int64_t)63;
+                if (base + lane >= bb && base + lane <= blk) mrow[base + lane] = (uint16_t)pending;
             }
-            if (PREFETCH) {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) xb[kb] = xn[kb];
-                xa = xan;
+        };
+        bf16x8_t x0[KB], x1[KB];
+        float a0, a1;
+        load(x0, a0, bb);
+        if (PREFETCH) {
+            // two operand buffers in turn: the next block loads while this one computes
+            for (int64_t blk = bb; blk < be; blk += 2) {
+                if (blk + 1 < be) load(x1, a1, blk + 1);
+                step(x0, a0, blk);
+                if (blk + 1 >= be) break;
+                if (blk + 2 < be) load(x0, a0, blk + 2);
+                step(x1, a1, blk + 1);
+            }
+        } else {
+            for (int64_t blk = bb; blk < be; ++blk) {
+                if (blk > bb) load(x0, a0, blk);
+                step(x0, a0, blk);
             }
         }
     }
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     int32_t* win = win_all[threadIdx.x >> 6];
     int32_t* queue = queue_all[threadIdx.x >> 6];
     double* qf = qf_all[threadIdx.x >> 6];  // [qb][kk][lane]
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
     const int grp = lane >> 4;
