@@ -217,8 +217,9 @@ fsg_status fsg_ctx_set_autotune(fsg_ctx* ctx, int32_t enabled);
 
 /* The shape tuned for a class (feature steps D4 in {1,2,4,8,16,32},
  * precision): waves per compute unit and data columns per work item (per
- * keep-mask work item in the precision mode).  FSG_E_INVALID if that class
- * has not been tuned. */
+ * keep-mask work item in the precision mode, where 0 means each set's own
+ * chunk, the one its single-set pass uses).  FSG_E_INVALID if that class has
+ * not been tuned. */
 fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int32_t* waves_per_cu,
                                int32_t* cols_per_item);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include "common.h"
 
+
 namespace fsg {
 
 fsg_status set_error(fsg_ctx* ctx, fsg_status s, const std::string& msg) {
@@ -278,6 +279,62 @@ static int32_t root_bins_per_item(const fsg_ctx* ctx, int64_t tiles, int32_t nbi
 }
 
 // Binned KDE of all n points against the nodes of tree level D (one segment).
+// 16-column blocks per keep-mask chunk.  Work items (chunk, group of tiles)
+// go round-robin to the waves, so the slowest wave does rounds x chunk
+// blocks plus a start-up per item (loading its query operands, worth about
+// kItemStart blocks): the chunk is chosen to make that smallest, which mostly
+// means a chunk count that just fills whole rounds.  The waves work on about
+// two chunks at a time, so a chunk's operands (16 x 64 x KB bytes per block)
+// are kept within about a third of an XCD's 4 MB L2.
+static int64_t mask_chunk_blocks(int64_t n_blocks, int64_t n_groups, int64_t n_waves, int KB) {
+    constexpr int64_t kItemStart = 16, kChunkBytes = 1536 * 1024;
+    const int64_t max_bpc = std::max<int64_t>(32, std::min<int64_t>(1024, kChunkBytes / (16 * 64 * KB)));
+    int64_t best_bpc = n_blocks, best = INT64_MAX;
+    for (int64_t c = (n_blocks + max_bpc - 1) / max_bpc; c <= (n_blocks + 31) / 32; ++c) {
+        const int64_t bpc = (n_blocks + c - 1) / c;
+        const int64_t chunks = (n_blocks + bpc - 1) / bpc;
+        const int64_t rounds = (chunks * n_groups + n_waves - 1) / n_waves;
+        const int64_t load = rounds * (bpc + kItemStart);
+        if (load < best || (load == best && bpc > best_bpc)) {
+            best = load;
+            best_bpc = bpc;
+        }
+    }
+    return best_bpc;
+}
+
+// Keep-mask arguments of a root pass over point set X (precision mode):
+// entries are the points in pivot order, so that each 64-query tile holds
+// points close together and keeps few columns.
+static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus) {
+    MaskArgs m;
+    std::memset(&m, 0, sizeof(m));
+    const int64_t n = X->n;
+    m.Xb = X->Xb;
+    m.Qb = X->Qb;
+    m.xa = X->xa;
+    m.KB = X->KB;
+    m.q_idx = X->order;
+    m.n_entries = n;
+    m.n_query = n;
+    m.n_data = n;
+    m.qnorm = X->norm;
+    m.dmin = X->dmin;
+    m.xmax = X->xmax;
+    m.margin_z = std::log((double)n) + kMarginExtra;
+    m.eps = 1.0 / 1024.0;
+    m.gamma = gamma;
+    m.n_tiles = (n + kTileQ - 1) / kTileQ;
+    m.n_blocks = X->n_pad / 16;
+    const int tp = mask_tiles_per_item(m.KB);
+    m.blocks_per_chunk = mask_chunk_blocks(m.n_blocks, (m.n_tiles + tp - 1) / tp, keep_mask_waves(m.KB, num_cus), m.KB);
+    m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+    return m;
+}
+
+// entries of a keep-threshold array for n entries
+static int64_t theta_entries(int64_t n) { return (n + kThetaPad - 1) / kThetaPad * kThetaPad; }
+
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
     const int32_t* bnd = level_bounds(X, D, &st);
@@ -310,26 +367,11 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         // together and keep few columns; rows are written by point
         a.q_idx = X->order;
         a.out_rows = X->order;
-        MaskArgs m;
-        std::memset(&m, 0, sizeof(m));
-        m.Xb = X->Xb;
-        m.Qb = X->Qb;
-        m.xa = X->xa;
-        m.KB = X->KB;
-        m.q_idx = X->order;
-        m.n_entries = n;
-        m.n_query = n;
-        m.n_data = n;
-        m.qnorm = X->norm;
-        m.dmin = X->dmin;
-        m.xmax = X->xmax;
-        m.margin_z = std::log((double)n) + kMarginExtra;
-        m.eps = 1.0 / 1024.0;
-        m.gamma = gamma;
-        m.n_tiles = tiles;
-        m.n_blocks = X->n_pad / 16;
-        m.blocks_per_chunk = 512;
-        m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+        MaskArgs m = root_mask_args(X, gamma, ctx->num_cus);
+        float* ntheta;
+        if ((st = ws(ctx, "mask_theta", (size_t)theta_entries(n), &ntheta)) != FSG_OK) return st;
+        FSG_HIP(ctx, launch_mask_theta(m, ntheta, theta_entries(n), ctx->stream));
+        m.ntheta = ntheta;
         if ((st = ws(ctx, "keep_mask", (size_t)(m.n_tiles * m.n_blocks), &m.mask)) != FSG_OK) return st;
         if (ctx->filter_counts == nullptr) {
             if (hipMalloc(&ctx->filter_counts, 2 * sizeof(int64_t)) != hipSuccess) {
@@ -403,6 +445,8 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     p->KB = KB;
     const size_t split_bytes = (size_t)(p->n_pad / 16) * KB * 64 * 16;
     const int64_t n = p->n;
+    const int64_t q_rows = (n + kThetaPad - 1) / kThetaPad * kThetaPad;
+    const size_t q_split_bytes = (size_t)(q_rows / 16) * KB * 64 * 16;
     uint32_t* label = nullptr;
     auto fail = [&](const char* what) {
         (void)hipGetLastError();
@@ -412,13 +456,14 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     char* qb = nullptr;
     if (pts_alloc(p, split_bytes, &xb) != hipSuccess) return fail("split operands");
     p->Xb = xb;
-    if (pts_alloc(p, split_bytes, &qb) != hipSuccess) return fail("split operands");
+    if (pts_alloc(p, q_split_bytes, &qb) != hipSuccess) return fail("split operands");
     p->Qb = qb;
     if (pts_alloc(p, (size_t)n, &p->dmin) != hipSuccess) return fail("distance bounds");
     if (pts_alloc(p, (size_t)n, &p->order) != hipSuccess) return fail("pivot order");
     if (pts_alloc(p, 1, &p->xmax) != hipSuccess) return fail("norm bound");
     if (pts_alloc(p, (size_t)p->n_pad, &p->xa) != hipSuccess) return fail("norm terms");
-    p->bytes += 2 * split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) + p->n_pad * sizeof(float);
+    p->bytes += split_bytes + q_split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) +
+                p->n_pad * sizeof(float);
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
@@ -426,10 +471,11 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     double* part;
     if ((st = ws(ctx, "max_norm_parts", (size_t)max_norm_parts(n), &part)) != FSG_OK) return st;
     StageTimer t(ctx, "prep");
-    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->Qb, p->xa, ctx->stream));
+    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->xa, ctx->stream));
     const int32_t P = (int32_t)(n < 256 ? n : 256);
     FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
     FSG_HIP(ctx, radix_sort_u32(label, p->order, n, 8, b, ctx->stream));
+    FSG_HIP(ctx, launch_prep_query_split(p->X, p->order, n, p->d, KB, q_rows, p->Qb, ctx->stream));
     FSG_HIP(ctx, launch_max_norm(p->norm, n, part, p->xmax, ctx->stream));
     return FSG_OK;
 }
@@ -690,6 +736,7 @@ struct fsg_job {
     int root_D = 0;
     double* M = nullptr;       // root-pass bins [n][2^root_D]
     uint16_t* mask = nullptr;  // precision mode: keep masks of the root pass
+    float* ntheta = nullptr;   // precision mode: keep-thresholds of the root pass
     std::vector<void*> owned;  // device blocks from the context's pool
 };
 
@@ -742,24 +789,8 @@ static fsg_status job_root_args(fsg_ctx* ctx, fsg_job* j, KdeArgs* a, MaskArgs* 
         a->out_rows = X->order;
         a->mask = j->mask;
         a->n_blocks = X->n_pad / 16;
-        m->Xb = X->Xb;
-        m->Qb = X->Qb;
-        m->xa = X->xa;
-        m->KB = X->KB;
-        m->q_idx = X->order;
-        m->n_entries = n;
-        m->n_query = n;
-        m->n_data = n;
-        m->qnorm = X->norm;
-        m->dmin = X->dmin;
-        m->xmax = X->xmax;
-        m->margin_z = std::log((double)n) + kMarginExtra;
-        m->eps = 1.0 / 1024.0;
-        m->gamma = j->S.gamma;
-        m->n_tiles = (n + kTileQ - 1) / kTileQ;
-        m->n_blocks = X->n_pad / 16;
-        m->blocks_per_chunk = 512;
-        m->n_chunks = (m->n_blocks + m->blocks_per_chunk - 1) / m->blocks_per_chunk;
+        *m = root_mask_args(X, j->S.gamma, ctx->num_cus);
+        m->ntheta = j->ntheta;
         m->mask = j->mask;
     }
     return FSG_OK;
@@ -817,8 +848,10 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
             // `cols` sets the keep-mask kernel's data columns per work item
             bpc = root_bins_per_item(ctx, n_tiles, nbins);
             MaskArgs& m = hmargs[i];
-            m.blocks_per_chunk = cols / 16;
-            m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+            if (cols > 0) {  // 0: the set's own balanced chunk
+                m.blocks_per_chunk = cols / 16;
+                m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
+            }
         } else {
             bpc = (int64_t)std::llround((double)cols * nbins / (double)n);
             if (bpc < 1) bpc = 1;
@@ -837,7 +870,7 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
         total += n_tiles * n_chunks;
         hmoff[i] = mtotal;
         if (bf16) {
-            mtotal += hmargs[i].n_tiles * hmargs[i].n_chunks;
+            mtotal += mask_items(hmargs[i]);
             T->scanned += hmargs[i].n_tiles * n;
         }
     }
@@ -915,7 +948,7 @@ static fsg_status batch_root(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
     const std::pair<int, int> key(X0->D4, (int)X0->prec);
     auto it = ctx->tuned.find(key);
     const bool bf16 = X0->prec == FSG_BF16_SPLIT;
-    int waves = 8, cols = bf16 ? 8192 : 2048;
+    int waves = 8, cols = bf16 ? 0 : 2048;
     fsg_status st;
     if (it != ctx->tuned.end()) {
         waves = it->second.first;
@@ -930,7 +963,7 @@ static fsg_status batch_root(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
         // and the exact pass keeps the single-set item shape)
         const int wave_opts[3] = {4, 8, 12};
         const int col_opts[3] = {1024, 2048, 4096};
-        const int mask_col_opts[3] = {4096, 8192, 16384};
+        const int mask_col_opts[3] = {0, 4096, 8192};
         for (int wi = 0; wi < 3; ++wi) {
             if (bf16 && wave_opts[wi] != 8) continue;
             for (int ci = 0; ci < 3; ++ci) {
@@ -1390,7 +1423,8 @@ void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, f
     uint64_t pts = n_pad * 4 * (uint64_t)D4 * 8 + n_pad * 8 + 2 * n_pad * 4;  // rows, norms, level bounds
     if (prec == FSG_BF16_SPLIT) {
         const uint64_t KB = (uint64_t)filter_steps(D4);
-        pts += 2 * (n_pad / 16) * KB * 64 * 16 + (uint64_t)n * 12 + n_pad * 4 + 256;
+        const uint64_t q_rows = ((uint64_t)n + kThetaPad - 1) / kThetaPad * kThetaPad;
+        pts += (n_pad / 16 + q_rows / 16) * KB * 64 * 16 + (uint64_t)n * 12 + n_pad * 4 + 256;
     }
     const uint64_t result = ((uint64_t)n + 1) * 8 + 2 * ns * 8 + ns * 4 + (uint64_t)n * 8 + 256;
     *resident = pts + result + (uint64_t)n * (uint64_t)d * 4;
@@ -1400,7 +1434,9 @@ void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, f
         const int D = plan.passes[0].second;
         const uint64_t n_uleaf = (uint64_t)(tree_depth(n) - plan.leaf_level);
         job += ns * n_uleaf * 8 + ((uint64_t)n << D) * 8;
-        if (prec == FSG_BF16_SPLIT) job += (uint64_t)((n + kTileQ - 1) / kTileQ) * (n_pad / 16) * 2;
+        if (prec == FSG_BF16_SPLIT)  // keep masks and thresholds
+            job += (uint64_t)((n + kTileQ - 1) / kTileQ) * (n_pad / 16) * 2 +
+                   ((uint64_t)n + kThetaPad - 1) / kThetaPad * kThetaPad * 4;
     }
     *transient = job;
 }
@@ -1445,6 +1481,12 @@ fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int3
             const size_t tiles = (size_t)((n + kTileQ - 1) / kTileQ);
             if (!(j->mask = (uint16_t*)job_alloc(j, tiles * (size_t)(Xc->n_pad / 16) * sizeof(uint16_t), &st)))
                 return fail(st);
+            if (!(j->ntheta = (float*)job_alloc(j, (size_t)theta_entries(n) * sizeof(float), &st))) return fail(st);
+            const hipError_t e = launch_mask_theta(root_mask_args(Xc, j->S.gamma, ctx->num_cus), j->ntheta, theta_entries(n), ctx->stream);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(set_error(ctx, FSG_E_DEVICE, std::string("keep-thresholds: ") + hipGetErrorString(e)));
+            }
         }
     }
     ctx->jobs.insert(j);

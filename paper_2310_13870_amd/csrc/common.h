@@ -83,7 +83,8 @@ struct KdeArgs {
 // recomputed exactly; the rest add 0 (provably below e^-Delta of the row).
 struct MaskArgs {
     const void* Xb;            // data-side split fragments [n_pad/16][KB][64] x 8 bf16
-    const void* Qb;            // query-side split fragments
+    const void* Qb;            // query-side split fragments of the entries, in entry order
+                               // (rows up to a multiple of kThetaPad, zero past the last)
     const float* xa;           // -|x|^2/2 of the data points [n_pad]
     int32_t KB;                // 32-wide K steps of the split operands
     const int32_t* q_idx;      // entry -> query point (NULL: the entry itself)
@@ -101,6 +102,8 @@ struct MaskArgs {
     int64_t blocks_per_chunk;
     int64_t n_chunks;
     uint16_t* mask;            // [n_tiles][n_blocks]: bit c = column c of the block kept for the tile
+    const float* ntheta;       // per entry: minus its keep-threshold (FP32, rounded so that the test
+                               // only keeps more); -inf up to a multiple of kThetaPad entries
     int64_t* kept;             // optional: number of (column, tile) pairs kept
     // multi-set launch: items of point set j are [job_item_off[j], job_item_off[j+1]),
     // each set's arguments in jobs[j] (NULL: this one; kept is this launch's)
@@ -109,6 +112,17 @@ struct MaskArgs {
     int32_t n_jobs;
     int64_t n_items_total;
 };
+
+constexpr int kThetaPad = 128;  // padding of MaskArgs::ntheta: a whole number of tile groups
+// 64-entry query tiles per keep-mask work item: two tiles reuse each loaded
+// data operand twice as often; with d > 32 their operands do not fit in registers
+__host__ __device__ constexpr int mask_tiles_per_item(int KB) { return KB <= 3 ? 2 : 1; }
+
+// work items of one point set's keep-mask pass: (group of tiles, chunk of blocks)
+__host__ __device__ inline int64_t mask_items(const MaskArgs& m) {
+    const int tp = mask_tiles_per_item(m.KB);
+    return (m.n_tiles + tp - 1) / tp * m.n_chunks;
+}
 
 // ---------------------------------------------------------------------------
 // Internal handles.
@@ -176,7 +190,7 @@ struct fsg_points {
     // precision mode (FSG_BF16_SPLIT)
     int32_t KB = 0;            // 32-wide K steps of the split operands
     void* Xb = nullptr;        // data-side split fragments
-    void* Qb = nullptr;        // query-side split fragments
+    void* Qb = nullptr;        // query-side split fragments in pivot order (rows: n rounded up to kThetaPad)
     float* xa = nullptr;       // -|x|^2/2 in FP32 [n_pad]
     double* dmin = nullptr;    // upper bound on each point's smallest squared distance
     int32_t* order = nullptr;  // points ordered by nearest pivot
@@ -233,13 +247,21 @@ int kde_tile(int D4);  // query entries per work item of the plain kernel
 hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
                               int32_t* n_items, hipStream_t st);
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);
+// waves of one keep-mask launch (before clamping to the item count)
+int64_t keep_mask_waves(int KB, int num_cus);
+// MaskArgs::ntheta of every entry of m (n_out = n_entries rounded up to kThetaPad)
+hipError_t launch_mask_theta(const MaskArgs& m, float* out, int64_t n_out, hipStream_t st);
 // next_item: a counter that must read 0 when the kernel starts (work items
 // beyond the first wave of the grid are claimed from it)
 hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long long* next_item, int num_cus,
                              hipStream_t st);
 int split_steps(int d);
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
-                             void* Xb, void* Qb, float* xa, hipStream_t st);
+                             void* Xb, float* xa, hipStream_t st);
+// query-side split fragments of points order[0..n) in that order, rows
+// (a multiple of 16, at least n) rows with zeros past n
+hipError_t launch_prep_query_split(const float* X, const int32_t* order, int64_t n, int32_t d, int32_t KB,
+                                   int64_t rows, void* Qb, hipStream_t st);
 hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double* dmin, uint32_t* label, int32_t* ids,
                          hipStream_t st);
 int max_norm_parts(int64_t n);  // partial maxima launch_max_norm needs in `part`

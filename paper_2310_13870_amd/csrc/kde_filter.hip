@@ -3,21 +3,27 @@
 // Every pair first gets an approximate cross term from BF16 hi/lo split
 // operands (hi = bf16(x), lo = bf16(x - hi); one contraction over K = 3d
 // gives hi.hi + hi.lo + lo.hi), accumulated in FP32 by
-// v_mfma_f32_16x16x32_bf16 onto an accumulator that starts at -|x|^2/2.  A pair can change a row's masses only if
-// its exponent z = gamma |q-x|^2 is within Delta of the row's smallest one
-// (a term e^-Delta times the largest term of the row is negligible); with a
-// guaranteed bound E on the error of the approximate cross term, the test
-//     c~ - |x|^2/2 >= |q|^2/2 - (T_q/(2 gamma)) - E,   T_q = gamma dmin_q + Delta
+// v_mfma_f32_16x16x32_bf16.  A pair can change a row's masses only if its
+// exponent z = gamma |q-x|^2 is within Delta of the row's smallest one (a
+// term e^-Delta times the largest term of the row is negligible); with a
+// guaranteed bound E on the error of the approximate cross term (it also
+// covers the FP32 rounding of the accumulation and of |x|^2/2), the test
+//     c~ - theta_q >= |x|^2/2,   theta_q = |q|^2/2 - T_q/(2 gamma) - E,
+//     T_q = gamma dmin_q + Delta
 // keeps every such pair (dmin_q is an upper bound on the row's smallest
-// squared distance).  Stage 1 writes, per 64-query tile and 16-column block,
-// the mask of columns kept for any query of the tile; stage 2 queues the kept
-// columns, gathers every 16 of them into one block whose cross terms are
-// recomputed on the FP64 matrix cores, and sends them through the same FP64
-// epilogue and bin accumulation as the plain kernel.  Pairs not kept add 0:
-// their total is below (n-1) e^-Delta of the row's mass.
+// squared distance).  The accumulator starts at -theta_q (theta_q rounded
+// down to FP32), so that the 16 results a lane holds, which share one data
+// column, are tested with one max and one compare.  Stage 1 writes, per
+// 64-query tile and 16-column block, the mask of columns kept for any query
+// of the tile; stage 2 queues the kept columns, gathers every 16 of them into
+// one block whose cross terms are recomputed on the FP64 matrix cores, and
+// sends them through the same FP64 epilogue and bin accumulation as the plain
+// kernel.  Pairs not kept add 0: their total is below (n-1) e^-Delta of the
+// row's mass.
 #include "common.h"
 #include "device.h"
 #include "kde_epilogue.h"
+
 
 namespace fsg {
 
@@ -32,21 +38,34 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // occupancy targets that fit without spilling
 template <int KB>
-constexpr int mask_waves() { return KB <= 3 ? 3 : 2; }
+constexpr int mask_waves() { return (KB <= 3 && mask_tiles_per_item(KB) == 1) ? 3 : 2; }
+
+int64_t keep_mask_waves(int KB, int num_cus) {
+    switch (KB) {
+        case 1: return (int64_t)num_cus * 4 * mask_waves<1>();
+        case 2: return (int64_t)num_cus * 4 * mask_waves<2>();
+        case 3: return (int64_t)num_cus * 4 * mask_waves<3>();
+        default: return (int64_t)num_cus * 4 * mask_waves<6>();
+    }
+}
 template <int D4>
 constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
 
-template <int KB, bool PREFETCH, int WAVES, bool MULTI>
+template <int KB, int TP, int WAVES, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m0) {
     // Queries are the A operand and data the B operand, so lane l receives
     // query rows 4(l/16) + i of a query block and data column l % 16: a column
-    // is kept when any of the 4 lane groups sees a compare succeed.
+    // is kept for a tile when any of the 4 lane groups sees a compare succeed
+    // in one of the tile's four query blocks.  A work item covers TP
+    // consecutive tiles, so that every data operand loaded feeds 4 TP matrix
+    // ops per K step.
+    constexpr int QB = 4 * TP;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int grp = lane >> 4;
     const int r = lane & 15;
-    const int64_t n_items = MULTI ? m0.n_items_total : m0.n_tiles * m0.n_chunks;
+    const int64_t n_items = MULTI ? m0.n_items_total : mask_items(m0);
     int64_t kept = 0;
     for (int64_t it = wave; it < n_items; it += n_waves) {
         int64_t local = it;
@@ -61,102 +80,107 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             local = it - m0.job_item_off[job];
         }
         const MaskArgs& m = MULTI ? m0.jobs[job] : m0;
-        const double xmax = *m.xmax;
-        const double half_margin = m.margin_z / (2.0 * m.gamma);
-        const int64_t chunk = local / m.n_tiles, tile = local - chunk * m.n_tiles;
-        const int64_t e0 = tile * kTileQ;
-        const int32_t ne = (int32_t)min((int64_t)kTileQ, m.n_entries - e0);
-        bf16x8_t qb16[4][KB];
-        float4_t theta[4];  // keep-thresholds of result rows 4(l/16)+i of each query block
+        const int64_t n_groups = (m.n_tiles + TP - 1) / TP;
+        const int64_t chunk = local / n_groups, tile0 = (local - chunk * n_groups) * TP;
+        const int64_t e0 = tile0 * kTileQ;
+        const int32_t ne = (int32_t)min((int64_t)(TP * kTileQ), m.n_entries - e0);
+        bf16x8_t qb16[QB][KB];
+        // minus the keep-thresholds of result rows 4(l/16)+i of each query
+        // block (consecutive entries; -inf past the last): the accumulators
+        // start there
+        float4_t ntheta[QB];
 #pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
-            {
-                // operand rows: query 16 qb + r
-                const int32_t t = 16 * qb + r;
-                const int64_t e = e0 + ((t < ne) ? t : 0);
-                int32_t p = m.q_idx ? m.q_idx[e] : (int32_t)e;
-                p = min(max(p, 0), (int32_t)(m.n_query - 1));
-                const bf16x8_t* bsrc = (const bf16x8_t*)m.Qb + (int64_t)(p >> 4) * KB * 64 + grp * 16 + (p & 15);
+        for (int qb = 0; qb < QB; ++qb) {
+            // operand rows: entries e0 + 16 qb .. (fragments in entry order)
+            const bf16x8_t* bsrc = (const bf16x8_t*)m.Qb + ((e0 >> 4) + qb) * KB * 64 + lane;
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb) qb16[qb][kb] = bsrc[kb * 64];
-            }
-            float4_t thq;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                // result rows: query 16 qb + 4 grp + i; keep-threshold on
-                // -|x|^2/2 + c~, rounded down to FP32
-                const int32_t t = 16 * qb + 4 * grp + i;
-                const bool ok = t < ne;
-                const int64_t e = e0 + (ok ? t : 0);
-                int32_t p = m.q_idx ? m.q_idx[e] : (int32_t)e;
-                p = min(max(p, 0), (int32_t)(m.n_query - 1));
-                const double nq = m.qnorm[p];
-                const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
-                const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - half_margin - err;
-                float thf = (float)th;
-                if ((double)thf > th) {  // step one FP32 ulp down
-                    int32_t bits = __float_as_int(thf);
-                    bits = (thf > 0.0f) ? bits - 1 : ((thf < 0.0f) ? bits + 1 : (int32_t)0x80000001);
-                    thf = __int_as_float(bits);
-                }
-                thq[i] = ok ? thf : __builtin_inff();
-            }
-            theta[qb] = thq;
+            for (int kb = 0; kb < KB; ++kb) qb16[qb][kb] = bsrc[kb * 64];
+            ntheta[qb] = *(const float4_t*)(m.ntheta + e0 + 16 * qb + 4 * grp);
         }
         __builtin_amdgcn_wave_barrier();
-        const int64_t bb = chunk * m.blocks_per_chunk;
-        const int64_t be = min(m.n_blocks, bb + m.blocks_per_chunk);
-        uint16_t* mrow = m.mask + tile * m.n_blocks;
+        // block indices fit in 32 bits (n < 2^31 columns), so that the loop
+        // control stays on the scalar unit
+        const int32_t bb = (int32_t)(chunk * m.blocks_per_chunk);
+        const int32_t be = (int32_t)min(m.n_blocks, (int64_t)bb + m.blocks_per_chunk);
+        const int32_t n_data = (int32_t)m.n_data;
+        const int32_t n_live = (int32_t)min((int64_t)TP, m.n_tiles - tile0);  // tiles of this item that exist
+        uint16_t* mrow = m.mask + tile0 * m.n_blocks;
+        const int64_t mstride = m.n_blocks;
         const bf16x8_t* X16 = (const bf16x8_t*)m.Xb;
         // the operands of block b: split data rows and -|x|^2/2 of this lane's column
-        auto load = [&](bf16x8_t (&x)[KB], float& xa, int64_t blk) {
+        auto load = [&](bf16x8_t (&x)[KB], float& xa, int32_t blk) {
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) x[kb] = X16[(blk * KB + kb) * 64 + lane];
-            xa = m.xa[blk * 16 + r];
+            for (int kb = 0; kb < KB; ++kb) x[kb] = X16[((int64_t)blk * KB + kb) * 64 + lane];
+            xa = m.xa[(int64_t)blk * 16 + r];
         };
-        uint32_t pending = 0;  // lane (b mod 64) keeps the mask of block b until 64 are ready
-        auto step = [&](const bf16x8_t (&x)[KB], float xa, int64_t blk) {
-            // four independent accumulators, K step outer, so that no matrix
-            // op waits for the previous one's result
-            float4_t cc[4];
+        // lane (b mod 64) keeps the masks of block b until 64 blocks are ready
+        uint32_t pending[TP];
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb) cc[qb] = float4_t{xa, xa, xa, xa};
+        for (int h = 0; h < TP; ++h) pending[h] = 0;
+        // cross terms of one block: independent accumulators, K step outer,
+        // so that no matrix op waits for the previous one's result
+        auto mma = [&](float4_t (&cc)[QB], const bf16x8_t (&x)[KB]) {
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
+            for (int qb = 0; qb < QB; ++qb)
+                cc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][0], x[0], ntheta[qb], 0, 0, 0);
 #pragma unroll
-                for (int qb = 0; qb < 4; ++qb)
+            for (int kb = 1; kb < KB; ++kb)
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb)
                     cc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qb16[qb][kb], x[kb], cc[qb], 0, 0, 0);
-            uint64_t any = 0;
+        };
+        // keep bits of one block from its cross terms
+        auto finish = [&](const float4_t (&cc)[QB], float xa, int32_t blk) {
+            const uint32_t tail = (16 * (blk + 1) > n_data) ? (1u << (n_data - 16 * blk)) - 1u : 0xFFFFu;
 #pragma unroll
-            for (int qb = 0; qb < 4; ++qb)
+            for (int h = 0; h < TP; ++h) {
+                // the lane's 16 results all belong to its one data column:
+                // a column is kept when the largest of them reaches |x|^2/2
+                float dm = cc[4 * h][0];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) any |= __ballot(cc[qb][i] >= theta[qb][i]);
-            uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & 0xFFFFull);
-            if (16 * (blk + 1) > m.n_data) keep &= (1u << (m.n_data - 16 * blk)) - 1u;
-            kept += __popc(keep);
-            if ((blk & 63) == lane) pending = keep;
+                for (int qb = 4 * h; qb < 4 * h + 4; ++qb)
+#pragma unroll
+                    for (int i = (qb == 4 * h) ? 1 : 0; i < 4; ++i) dm = __builtin_fmaxf(dm, cc[qb][i]);
+                const uint64_t any = __ballot(dm >= -xa);
+                const uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & tail);
+                kept += __popc(keep);
+                if ((blk & 63) == lane) pending[h] = keep;
+            }
             if ((blk & 63) == 63 || blk + 1 == be) {
-                const int64_t base = blk & ~(int64_t)63;
-                if (base + lane >= bb && base + lane <= blk) mrow[base + lane] = (uint16_t)pending;
+                const int32_t b = (blk & ~63) + lane;
+                if (b >= bb && b <= blk) {
+#pragma unroll
+                    for (int h = 0; h < TP; ++h)
+                        if (h < n_live) mrow[h * mstride + b] = (uint16_t)pending[h];
+                }
             }
         };
+        // Software pipeline over the blocks: the matrix ops of block b + 1
+        // are issued before the keep bits of block b are taken, and the
+        // operands of block b + 2 load meanwhile (two operand buffers, two
+        // accumulator sets).  Past the end the last block is loaded and
+        // multiplied again (in bounds, results unused), so that every
+        // iteration issues the same instructions.
+        auto clampb = [&](int32_t b) { return b < be ? b : be - 1; };
         bf16x8_t x0[KB], x1[KB];
         float a0, a1;
+        float4_t c0[QB], c1[QB];
+        float f0, f1;  // -|x|^2/2 of the blocks whose keep bits are taken next
         load(x0, a0, bb);
-        if (PREFETCH) {
-            // two operand buffers in turn: the next block loads while this one computes
-            for (int64_t blk = bb; blk < be; blk += 2) {
-                if (blk + 1 < be) load(x1, a1, blk + 1);
-                step(x0, a0, blk);
-                if (blk + 1 >= be) break;
-                if (blk + 2 < be) load(x0, a0, blk + 2);
-                step(x1, a1, blk + 1);
-            }
-        } else {
-            for (int64_t blk = bb; blk < be; ++blk) {
-                if (blk > bb) load(x0, a0, blk);
-                step(x0, a0, blk);
-            }
+        load(x1, a1, clampb(bb + 1));
+        mma(c0, x0);
+        f0 = a0;
+        for (int32_t blk = bb;;) {
+            load(x0, a0, clampb(blk + 2));
+            mma(c1, x1);
+            f1 = a1;
+            finish(c0, f0, blk);
+            if (++blk >= be) break;
+            load(x1, a1, clampb(blk + 2));
+            mma(c0, x0);
+            f0 = a0;
+            finish(c1, f1, blk);
+            if (++blk >= be) break;
         }
     }
     if (m0.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m0.kept, (unsigned long long)kept);
@@ -340,24 +364,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     }
 }
 
-template <int KB, bool PREFETCH, int WAVES>
-static hipError_t launch_mask_v(const MaskArgs& m, int num_cus, hipStream_t st) {
-    const int64_t n_items = m.jobs ? m.n_items_total : m.n_tiles * m.n_chunks;
+// Minus the keep-threshold of every entry:
+//     theta_q = |q|^2/2 - dmin_q (1 + 1e-6)/2 - Delta/(2 gamma) - E,
+//     E = eps (|q| xmax + xmax^2/2),
+// in FP64, then rounded down to FP32 (the test c~ - theta_q >= |x|^2/2 only
+// keeps more); entries past the last get -inf (never kept).
+__global__ void mask_theta_kernel(MaskArgs m, float* __restrict__ out, int64_t n_out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_out) return;
+    if (e >= m.n_entries) {
+        out[e] = -__builtin_inff();
+        return;
+    }
+    int32_t p = m.q_idx ? m.q_idx[e] : (int32_t)e;
+    p = min(max(p, 0), (int32_t)(m.n_query - 1));
+    const double xmax = *m.xmax;
+    const double nq = m.qnorm[p];
+    const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
+    const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - m.margin_z / (2.0 * m.gamma) - err;
+    float thf = (float)th;
+    if ((double)thf > th) {  // step one FP32 ulp down
+        int32_t bits = __float_as_int(thf);
+        bits = (thf > 0.0f) ? bits - 1 : ((thf < 0.0f) ? bits + 1 : (int32_t)0x80000001);
+        thf = __int_as_float(bits);
+    }
+    out[e] = -thf;
+}
+
+hipError_t launch_mask_theta(const MaskArgs& m, float* out, int64_t n_out, hipStream_t st) {
+    if (n_out < m.n_entries || n_out % kThetaPad != 0) return hipErrorInvalidValue;
+    if (n_out == 0) return hipSuccess;
+    mask_theta_kernel<<<(unsigned)((n_out + 255) / 256), 256, 0, st>>>(m, out, n_out);
+    return hipGetLastError();
+}
+
+template <int KB>
+static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) {
+    constexpr int TP = mask_tiles_per_item(KB), WAVES = mask_waves<KB>();
+    static_assert(kThetaPad % (TP * kTileQ) == 0, "threshold padding must hold whole tile groups");
+    const int64_t n_items = m.jobs ? m.n_items_total : mask_items(m);
     int64_t waves = (int64_t)num_cus * 4 * WAVES;
     if (n_items < waves) waves = n_items;
     if (waves < 1) waves = 1;
     if (m.jobs)
-        kde_keep_mask_kernel<KB, PREFETCH, WAVES, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+        kde_keep_mask_kernel<KB, TP, WAVES, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
     else
-        kde_keep_mask_kernel<KB, PREFETCH, WAVES, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+        kde_keep_mask_kernel<KB, TP, WAVES, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
     return hipGetLastError();
-}
-
-// Measured on the MI355X (n = 100k, d = 32): next-block prefetch at 3 waves per
-// SIMD beats no prefetch at 3 or 4 waves and prefetch at 2 waves.
-template <int KB>
-static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) {
-    return launch_mask_v<KB, true, mask_waves<KB>()>(m, num_cus, st);
 }
 
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
@@ -435,11 +488,30 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t st) {
 // Split fragments in the operand layout of v_mfma_f32_16x16x32_bf16: lane l
 // holds 8 consecutive K entries 8(l/16).. of row 16b + l%16.  Data rows are
 // [hi(x), lo(x), hi(x), 0...], query rows [hi(q), hi(q), lo(q), 0...]; their
-// contraction is hi.hi + hi.lo + lo.hi.  xa = -|x|^2/2 in FP32 seeds the
-// accumulator of each data column.
+// contraction is hi.hi + hi.lo + lo.hi.  xa = -|x|^2/2 in FP32.
+__device__ __forceinline__ bf16x8_t split_fragment(const float* __restrict__ X, int64_t row, int32_t d, int32_t kb,
+                                                   int32_t lane, bool query) {
+    bf16x8_t v;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int32_t k = kb * 32 + (lane >> 4) * 8 + t;
+        __bf16 b = (__bf16)0.0f;
+        if (row >= 0 && k < 3 * d) {
+            const int32_t part = k / d;  // 0, 1, 2
+            const float x = X[row * d + (k - part * d)];
+            const __bf16 hi = (__bf16)x;
+            const __bf16 lo = (__bf16)(x - (float)hi);
+            b = (part == (query ? 2 : 1)) ? lo : hi;
+        }
+        v[t] = b;
+    }
+    return v;
+}
+
+// data-side fragments of the points in index order, and xa
 __global__ void prep_split_kernel(const float* __restrict__ X, const double* __restrict__ norm, int64_t n, int32_t d,
-                                  int32_t KB, int64_t total, bf16x8_t* __restrict__ Xb, bf16x8_t* __restrict__ Qb,
-                                  float* __restrict__ xa, int64_t n_pad) {
+                                  int32_t KB, int64_t total, bf16x8_t* __restrict__ Xb, float* __restrict__ xa,
+                                  int64_t n_pad) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n_pad) xa[idx] = (idx < n) ? (float)(-0.5 * norm[idx]) : 0.0f;
     if (idx >= total) return;
@@ -448,30 +520,21 @@ __global__ void prep_split_kernel(const float* __restrict__ X, const double* __r
     const int32_t rem = (int32_t)(idx - blk * per_blk);
     const int32_t kb = rem >> 6, lane = rem & 63;
     const int64_t row = blk * 16 + (lane & 15);
-    bf16x8_t dv, qv;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int32_t k = kb * 32 + (lane >> 4) * 8 + t;
-        float xd = 0.0f, xq = 0.0f;
-        __bf16 bd = (__bf16)0.0f, bq = (__bf16)0.0f;
-        if (row < n) {
-            if (k < 3 * d) {
-                const int32_t f = k % d;
-                const float x = X[row * d + f];
-                const __bf16 hi = (__bf16)x;
-                const __bf16 lo = (__bf16)(x - (float)hi);
-                const int32_t part = k / d;  // 0, 1, 2
-                bd = (part == 1) ? lo : hi;
-                bq = (part == 2) ? lo : hi;
-            }
-        }
-        (void)xd;
-        (void)xq;
-        dv[t] = bd;
-        qv[t] = bq;
-    }
-    Xb[idx] = dv;
-    Qb[idx] = qv;
+    Xb[idx] = split_fragment(X, row < n ? row : -1, d, kb, lane, false);
+}
+
+// query-side fragments in entry order: row e holds point order[e] (zero rows
+// past the last entry), so that a tile's operands are contiguous
+__global__ void prep_query_split_kernel(const float* __restrict__ X, const int32_t* __restrict__ order, int64_t n,
+                                        int32_t d, int32_t KB, int64_t total, bf16x8_t* __restrict__ Qb) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t per_blk = (int64_t)KB * 64;
+    const int64_t blk = idx / per_blk;
+    const int32_t rem = (int32_t)(idx - blk * per_blk);
+    const int32_t kb = rem >> 6, lane = rem & 63;
+    const int64_t e = blk * 16 + (lane & 15);
+    Qb[idx] = split_fragment(X, e < n ? (int64_t)order[e] : -1, d, kb, lane, true);
 }
 
 // dmin[i] = an upper bound on min_{j != i} |x_i - x_j|^2 over P pivot points
@@ -556,11 +619,21 @@ __global__ __launch_bounds__(256) void max_norm_final_kernel(const double* __res
 }
 
 hipError_t launch_prep_split(const float* X, const double* norm, int64_t n, int32_t d, int32_t KB, int64_t n_pad,
-                             void* Xb, void* Qb, float* xa, hipStream_t st) {
+                             void* Xb, float* xa, hipStream_t st) {
     const int64_t total = (n_pad / 16) * KB * 64;
     const int64_t threads = total > n_pad ? total : n_pad;
-    prep_split_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(X, norm, n, d, KB, total, (bf16x8_t*)Xb,
-                                                                         (bf16x8_t*)Qb, xa, n_pad);
+    prep_split_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(X, norm, n, d, KB, total, (bf16x8_t*)Xb, xa,
+                                                                         n_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_query_split(const float* X, const int32_t* order, int64_t n, int32_t d, int32_t KB,
+                                   int64_t rows, void* Qb, hipStream_t st) {
+    if (rows % 16 != 0 || rows < n) return hipErrorInvalidValue;
+    const int64_t total = (rows / 16) * KB * 64;
+    if (total == 0) return hipSuccess;
+    prep_query_split_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, order, n, d, KB, total,
+                                                                             (bf16x8_t*)Qb);
     return hipGetLastError();
 }
 
