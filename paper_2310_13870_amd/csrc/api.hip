@@ -278,7 +278,6 @@ static int32_t root_bins_per_item(const fsg_ctx* ctx, int64_t tiles, int32_t nbi
     return (int32_t)((nbins + chunks - 1) / chunks);
 }
 
-// Binned KDE of all n points against the nodes of tree level D (one segment).
 // 16-column blocks per keep-mask chunk.  Work items (chunk, group of tiles)
 // go round-robin to the waves, so the slowest wave does rounds x chunk
 // blocks plus a start-up per item (loading its query operands, worth about
@@ -335,6 +334,7 @@ static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus) {
 // entries of a keep-threshold array for n entries
 static int64_t theta_entries(int64_t n) { return (n + kThetaPad - 1) / kThetaPad * kThetaPad; }
 
+// Binned KDE of all n points against the nodes of tree level D (one segment).
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
     const int32_t* bnd = level_bounds(X, D, &st);

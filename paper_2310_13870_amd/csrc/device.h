@@ -39,6 +39,35 @@ __device__ __forceinline__ double exp2_fp64(double a) {
 }
 
 // ---------------------------------------------------------------------------
+// 2^(a/256) in FP64 with a table (the KDE kernels, where the exponential is
+// most of the vector work).  a = 256 e + j + r with m = rint(a), j = m mod 256,
+// e = floor(m / 256) and |r| <= 1/2: 2^(a/256) = 2^e 2^(j/256) e^(r ln2/256).
+// tab[j] = 2^(j/256) rounded to FP64 (kExp2Table, copied to LDS by the
+// caller); e^x - 1 for |x| = |r ln2/256| <= 1.36e-3 is its Taylor series to
+// degree 4, whose remainder is below 4e-17 relative; the result is
+// tab[j] + tab[j] q scaled by 2^e with ldexp (exact, gradual underflow).
+// Arguments below -2000 * 256 give 0, as does -inf.
+// ---------------------------------------------------------------------------
+constexpr double tab_coef(int k) {
+    double v = 1.0;
+    for (int i = 1; i <= k; ++i) v = v * (kLn2 / 256.0) / (double)i;
+    return v;
+}
+
+__device__ __forceinline__ double exp2_256_tab(double a, const double* tab) {
+    a = __builtin_fmax(a, -512000.0);
+    const double m = __builtin_rint(a);
+    const double r = a - m;  // exact: |r| <= 1/2
+    const int32_t mi = (int32_t)m;
+    const double t = tab[mi & 255];
+    double q = __builtin_fma(tab_coef(4), r, tab_coef(3));
+    q = __builtin_fma(q, r, tab_coef(2));
+    q = __builtin_fma(q, r, tab_coef(1));
+    q *= r;
+    return __builtin_ldexp(__builtin_fma(t, q, t), mi >> 8);
+}
+
+// ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
 // 64x64->128 multiplies; the key advances by the Weyl increments between
 // rounds.  u(seed, i, l, level) = (word[level % 4] >> 11) * 2^-53 of the block

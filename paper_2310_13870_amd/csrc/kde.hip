@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, kv);
+            exact_values<RQ, false>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, nullptr, kv);
             bins.add(kv, jj, c0 + 15);
             if (more) {
                 if (kPrefetch) {

@@ -210,6 +210,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     __shared__ int32_t queue_all[4][QN];
     __shared__ double qf_all[4][RQ * D4 * 64];
     __shared__ int32_t win_all[4][kBinWindow];
+    __shared__ double exp_tab[256];
+    load_exp2_table(exp_tab);
     const int lane = threadIdx.x & 63;
     int32_t* win = win_all[threadIdx.x >> 6];
     int32_t* queue = queue_all[threadIdx.x >> 6];
@@ -231,7 +233,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         const SegDesc sg = a.segs[w.seg];
         const KdeArgs& J = MULTI ? a.jobs[sg.job] : a;
         const int32_t* bnd = J.bounds + sg.bound_off;
-        const double two_s = 2.0 * J.s;
+        const double s256 = 256.0 * J.s;  // exponent terms scaled by 256 for exp2_256_tab
+        const double two_s = 2.0 * s256;
         double hq[RQ];
         int32_t selfv[RQ], smin[RQ], smax[RQ];
         __builtin_amdgcn_wave_barrier();
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             int32_t sf = -1;
             if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -J.s * J.qnorm[p];
+            hq[qb] = -s256 * J.qnorm[p];
             double qv[D4];
             load_row_part<D4>(qv, J.Qp, p, grp);
 #pragma unroll
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             // padding columns: |x|^2 = +inf gives exponent -inf and value 0
             double hx[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hx[i] = -J.s * g.xn[i];
+            for (int i = 0; i < 4; ++i) hx[i] = -s256 * g.xn[i];
             double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
@@ -337,26 +340,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ>(c, hq, hx, two_s, g.jj, selfv, smin, smax, g.first, g.last, kv);
+            exact_values<RQ, true>(c, hq, hx, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
             bins.add(kv, g.jj, g.last);
         };
 
         fill();
         if (tail > head) {
-            Gathered<D4> cur, nxt;
+            // two operand buffers in turn: the next block gathers while this
+            // one computes
+            Gathered<D4> g0, g1;
             int32_t n0 = min(16, tail - head);
-            prepare(cur, head, n0);
+            prepare(g0, head, n0);
             head += n0;
             while (true) {
                 fill();
                 const int32_t n1 = min(16, tail - head);
                 if (n1 > 0) {
-                    prepare(nxt, head, n1);
+                    prepare(g1, head, n1);
                     head += n1;
                 }
-                compute(cur);
+                compute(g0);
                 if (n1 == 0) break;
-                cur = nxt;
+                fill();
+                const int32_t n2 = min(16, tail - head);
+                if (n2 > 0) {
+                    prepare(g0, head, n2);
+                    head += n2;
+                }
+                compute(g1);
+                if (n2 == 0) break;
             }
         }
         bins.finish();
