@@ -206,7 +206,8 @@ struct Gathered {
 template <int D4, int RQ, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
     KdeArgs a, unsigned long long* __restrict__ next_item) {
-    constexpr int QN = 64;  // circular queue length (at most 31 entries are pending)
+    // queue length: fewer than 16 entries left over plus one batch of 256 columns
+    constexpr int QN = 288;
     __shared__ int32_t queue_all[4][QN];
     __shared__ double qf_all[4][RQ * D4 * 64];
     __shared__ int32_t win_all[4][kBinWindow];
@@ -275,34 +276,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         // queue state (uniform): entries [head, tail) are pending
         int32_t head = 0, tail = 0;
         int64_t blk = blk0;  // next block whose mask is to be read
-        // masks of blocks [base, base + 64) and of the 64 after them, one per
-        // lane; the second batch is loaded one batch ahead
-        int64_t base = blk0 & ~(int64_t)63;
-        auto load_batch = [&](int64_t b) -> uint32_t {
-            const int64_t myb = b + lane;
-            return (myb >= blk0 && myb < blk1) ? (uint32_t)mrow[myb] : 0u;
+        // masks of the next batch of 16 blocks: lane l holds block blk + l/4,
+        // loaded one batch ahead
+        auto load_masks = [&](int64_t b) -> uint32_t {
+            const int64_t mb = b + (lane >> 2);
+            return (mb < blk1) ? (uint32_t)mrow[mb] : 0u;
         };
-        uint32_t batch = load_batch(base);
-        uint32_t batch_next = load_batch(base + 64);
+        uint32_t masks = load_masks(blk);
 
-        // append the kept columns of further blocks until 16 are pending or the range ends
+        // append the kept columns of further batches of 16 blocks (in index
+        // order) until 16 are pending or the range ends.  Lane l takes columns
+        // 4(l%4) .. 4(l%4)+3 of block l/4; its entries go after those of the
+        // lanes below it, counted with one ballot per column position.
         auto fill = [&]() {
             while (tail - head < 16 && blk < blk1) {
-                if (blk >= base + 64) {
-                    base += 64;
-                    batch = batch_next;
-                    batch_next = load_batch(base + 64);
+                if (head > 0) {  // move the fewer than 16 pending entries to the front
+                    const int32_t left = tail - head;
+                    const int32_t v = queue[head + (lane < left ? lane : 0)];
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < left) queue[lane] = v;
+                    head = 0;
+                    tail = left;
                 }
-                uint32_t keep = (uint32_t)__builtin_amdgcn_readlane((int)batch, (int)(blk - base));
-                const int32_t c0 = (int32_t)(blk << 4);
-                if (c0 < col_begin) keep &= ~((1u << (col_begin - c0)) - 1u);
-                if (c0 + 16 > col_end) keep &= (1u << (col_end - c0)) - 1u;
-                if (keep != 0) {
-                    if (lane < 16 && ((keep >> lane) & 1u))
-                        queue[(tail + (int32_t)__builtin_amdgcn_mbcnt_lo(keep, 0u)) & (QN - 1)] = c0 + lane;
-                    tail += __popc(keep);
+                const int32_t c0 = (int32_t)((blk + (lane >> 2)) << 4) + 4 * (lane & 3);
+                uint32_t bits = (masks >> (4 * (lane & 3))) & 15u;
+                const int32_t lo = min(max(col_begin - c0, 0), 4), hi = min(max(col_end - c0, 0), 4);
+                bits &= ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                blk += 16;
+                masks = load_masks(blk);
+                int32_t pos = tail, total = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint64_t bk = __ballot((bits >> k) & 1u);
+                    pos += (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
+                    total += __popcll(bk);
                 }
-                ++blk;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if ((bits >> k) & 1u) queue[pos] = c0 + k;
+                    pos += (bits >> k) & 1u;
+                }
+                tail += uniform(total);
             }
             __builtin_amdgcn_wave_barrier();
         };
@@ -311,14 +325,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         // A row r holds entry perm_row(r), so that lane group g receives the
         // consecutive entries 4g .. 4g+3
         auto prepare = [&](Gathered<D4>& g, int32_t pos, int32_t cnt) {
-            const int32_t gl = queue[(pos + ((pr < cnt) ? pr : 0)) & (QN - 1)];
+            const int32_t gl = queue[pos + ((pr < cnt) ? pr : 0)];
             load_row_part<D4>(g.xf, J.Xp, gl, grp);
-            g.first = uniform(queue[pos & (QN - 1)]);
-            g.last = uniform(queue[(pos + cnt - 1) & (QN - 1)]);
+            g.first = uniform(queue[pos]);
+            g.last = uniform(queue[pos + cnt - 1]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int32_t idx = 4 * grp + i;
-                g.jj[i] = (idx < cnt) ? queue[(pos + idx) & (QN - 1)] : INT32_MAX;
+                g.jj[i] = (idx < cnt) ? queue[pos + idx] : INT32_MAX;
                 const double v = J.xnorm[(idx < cnt) ? g.jj[i] : g.first];
                 g.xn[i] = (idx < cnt) ? v : __builtin_inf();
             }
