@@ -114,9 +114,10 @@ struct MaskArgs {
 };
 
 constexpr int kThetaPad = 128;  // padding of MaskArgs::ntheta: a whole number of tile groups
-// 64-entry query tiles per keep-mask work item: two tiles reuse each loaded
-// data operand twice as often; with d > 32 their operands do not fit in registers
-__host__ __device__ constexpr int mask_tiles_per_item(int KB) { return KB <= 3 ? 2 : 1; }
+// 64-entry query tiles per keep-mask work item: two tiles use each loaded
+// data operand twice as often as one (the kernel is bound by operand traffic
+// more than by occupancy); for d > 32 their operands need one wave per SIMD
+__host__ __device__ constexpr int mask_tiles_per_item(int KB) { return KB <= 6 ? 2 : 1; }
 
 // work items of one point set's keep-mask pass: (group of tiles, chunk of blocks)
 __host__ __device__ inline int64_t mask_items(const MaskArgs& m) {

@@ -36,9 +36,10 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // for at least one query of the tile.  Work item = (tile, run of blocks); the
 // next block's operands are loaded while the current one is processed.
 // ---------------------------------------------------------------------------
-// occupancy targets that fit without spilling
+// occupancy targets that fit without spilling (measured on the MI355X: two
+// tiles per item at these occupancies beat one tile at three or two waves)
 template <int KB>
-constexpr int mask_waves() { return (KB <= 3 && mask_tiles_per_item(KB) == 1) ? 3 : 2; }
+constexpr int mask_waves() { return KB <= 3 ? 2 : 1; }
 
 int64_t keep_mask_waves(int KB, int num_cus) {
     switch (KB) {
