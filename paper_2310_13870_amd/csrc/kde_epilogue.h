@@ -234,6 +234,144 @@ struct BinAccumulator {
     }
 };
 
+// The same accumulation with one open bin per lane, for the gathered columns
+// of the precision mode, where a block of 16 kept columns spans several bins
+// (their columns are sparse): slot[qb] is this lane's partial of bin cur for
+// query block qb (RQ = 4, one per lane group).  Closing a bin combines the
+// four query blocks' partials across the lane groups with the same
+// permlane32 and permlane16 swaps, which leaves query block g's total in lane
+// group g, and shifts it into a 4-bin staging register; every 4 bins each
+// lane writes its row's 32 bytes.  Fixed order, no atomics: bit-reproducible.
+template <int RQ>
+struct BinAccumulator1 {
+    static_assert(RQ == 4, "one query block per lane group");
+    const int32_t* bnd;  // boundaries of the segment's bins
+    const int32_t* win;  // LDS copy of bnd[b0 .. b0 + kBinWindow)
+    int32_t b0, b1;      // bins [b0, b1) of this work item
+    int32_t cur;         // bin being accumulated (b0 - 1: before the first)
+    int32_t start;       // first column of bin cur
+    int32_t nxt;         // first column of bin cur + 1
+    int64_t stride;
+    double* out;
+    int32_t orow;        // output row of query row lane % 16 of query block lane / 16 (-1: none)
+    double slot[RQ];     // partials of bin cur
+    double stage[4];     // stage[3] is the last closed bin, stage[j] the one 3 - j before it
+
+    __device__ __forceinline__ void init(const int32_t* bnd_, const int32_t* win_, int32_t b0_, int32_t b1_,
+                                         int32_t col_begin, int64_t e0_, int32_t ne_, int64_t stride_, double* out_,
+                                         const int32_t* out_rows_, int lane) {
+        bnd = bnd_;
+        win = win_;
+        b0 = uniform(b0_);
+        b1 = uniform(b1_);
+        cur = uniform(b0_ - 1);
+        start = INT32_MIN;
+        nxt = uniform(col_begin);
+        stride = stride_;
+        out = out_;
+#pragma unroll
+        for (int qb = 0; qb < RQ; ++qb) slot[qb] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) stage[j] = 0.0;
+        const int32_t t = 16 * (lane >> 4) + (lane & 15);
+        const int64_t e = e0_ + t;
+        orow = (t < ne_) ? (out_rows_ ? out_rows_[e] : (int32_t)e) : -1;
+    }
+
+    // write the staged window of 4 bins ending at bin c (c % 4 == 3), those in [b0, b1)
+    __device__ __forceinline__ void write_window(int32_t c) {
+        if (orow < 0) return;
+        double* row = out + (int64_t)orow * stride + (c - 3);
+        if (c - 3 >= b0 && c < b1) {
+            typedef double double2_t __attribute__((ext_vector_type(2)));
+            ((double2_t*)row)[0] = double2_t{stage[0], stage[1]};
+            ((double2_t*)row)[1] = double2_t{stage[2], stage[3]};
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c - 3 + j >= b0 && c - 3 + j < b1) row[j] = stage[j];
+        }
+    }
+
+    // bin cur is complete: combine it, stage it, write a full window
+    __device__ __forceinline__ void close() {
+        const double t02 = swap32_add(slot[0], slot[2]);
+        const double t13 = swap32_add(slot[1], slot[3]);
+        stage[0] = stage[1];
+        stage[1] = stage[2];
+        stage[2] = stage[3];
+        stage[3] = swap16_add(t02, t13);
+#pragma unroll
+        for (int qb = 0; qb < RQ; ++qb) slot[qb] = 0.0;
+        if ((cur & 3) == 3) write_window(cur);
+    }
+
+    __device__ __forceinline__ void advance() {
+        ++cur;
+        start = nxt;
+        if (cur < b1) {
+            const int32_t k = cur + 1 - b0;
+            nxt = uniform((k < kBinWindow) ? win[k] : bnd[cur + 1]);
+        } else {
+            nxt = INT32_MAX;
+        }
+    }
+
+    // Add kernel values kv[qb][i] of columns jj[i]; `last` is the largest
+    // column of the block (uniform).  Columns below the first bin or at/after
+    // the end of the last bin are dropped.
+    __device__ __forceinline__ void add(const double (&kv)[RQ][4], const int32_t (&jj)[4], int32_t last) {
+        if (nxt > last) {  // the whole block lies in bin cur (uniform)
+            if (cur >= b0 && cur < b1) {
+#pragma unroll
+                for (int qb = 0; qb < RQ; ++qb) slot[qb] += (kv[qb][0] + kv[qb][1]) + (kv[qb][2] + kv[qb][3]);
+            }
+            return;
+        }
+        while (nxt <= last) {  // a boundary inside this block (uniform)
+            if (cur >= b0) {
+                double wgt[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) wgt[i] = (jj[i] >= start && jj[i] < nxt) ? 1.0 : 0.0;
+#pragma unroll
+                for (int qb = 0; qb < RQ; ++qb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) slot[qb] = __builtin_fma(kv[qb][i], wgt[i], slot[qb]);
+            }
+            // bins before b0 are not written (close() writes only in [b0, b1))
+            close();
+            advance();
+        }
+        if (cur >= b0 && cur < b1) {
+            double wgt[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wgt[i] = (jj[i] >= start) ? 1.0 : 0.0;
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) slot[qb] = __builtin_fma(kv[qb][i], wgt[i], slot[qb]);
+        }
+    }
+
+    // the open bin and the empty bins after it, to the end of the item
+    __device__ __forceinline__ void finish() {
+        if (cur < b0 - 1) cur = b0 - 1;
+        while (cur < b1) {  // close bins until the window of b1 - 1 is written
+            close();
+            if (cur >= b1 - 1 && (cur & 3) != 3) {  // pad the last window with the empty bins after it
+                for (int32_t c = cur + 1; (c & 3) != 0; ++c) {
+                    stage[0] = stage[1];
+                    stage[1] = stage[2];
+                    stage[2] = stage[3];
+                    stage[3] = 0.0;
+                }
+                write_window(cur | 3);
+            }
+            ++cur;
+        }
+    }
+};
+
 // The FP64 epilogue of one query block against 16 columns: kernel values
 // from the cross terms c (result element i of lane group g is block position
 // 4g + i), the self term removed.  With tab (the LDS copy of kExp2Table) the

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         __builtin_amdgcn_wave_barrier();
         const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)J.n_data));
         const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
-        BinAccumulator<RQ> bins;
+        BinAccumulator1<RQ> bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
         bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);
