@@ -34,31 +34,32 @@ FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
-# the dominant kernel of each precision mode, the source files that define it
-# and the committed counter summary that holds its HBM traffic per launch
-DOMINANT = {
-    "fp32": ("kde_bins", ("kde.hip", "kde_epilogue.h", "device.h", "common.h")),
-    "bf16_split": ("kde_exact_kept", ("kde_filter.hip", "kde_epilogue.h", "device.h", "common.h")),
+# the source files that define each kernel whose HBM traffic is looked up in
+# the committed counter summaries (profiles/<kernel>_<workload>_traffic.json)
+KERNEL_SOURCES = {
+    "kde_bins": ("kde.hip", "kde_epilogue.h", "device.h", "common.h"),
+    "kde_exact_kept": ("kde_filter.hip", "kde_epilogue.h", "exp2_table.h", "device.h", "common.h"),
+    "kde_keep_mask": ("kde_filter.hip", "device.h", "common.h"),
 }
 
 
-def kernel_source_hash(precision: str) -> str:
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for name in DOMINANT[precision][1]:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2310_13870_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, precision: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{DOMINANT[precision][0]}_{workload}_traffic.json")
+def traffic_from_profile(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel from the committed counter summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash(precision):
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -466,7 +467,7 @@ def main():
             pairs = kept / args.steps * 64
         flops = 2.0 * d * pairs
         achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
-        traffic = traffic_from_profile(args.workload, args.precision)
+        traffic = traffic_from_profile("kde_bins" if args.precision == "fp32" else "kde_exact_kept", args.workload)
         label = ("binned KDE over all point pairs (FP64 matrix cores)" if args.precision == "fp32"
                  else "exact FP64 recompute of the kept pairs (FP64 matrix cores)")
         roofline = {"bound": "mfma", "kernel": label,
@@ -480,7 +481,9 @@ def main():
         achieved = flops / (mask["ms_per_launch"] * 1e-3) / 1e12
         distance_tiles = {"bound": "mfma", "kernel": "BF16 split keep-mask kernel (distance tiles)",
                           "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "ms_per_launch": mask["ms_per_launch"],
+                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
+                          "traffic": traffic_from_profile("kde_keep_mask", args.workload),
+                          "ms_per_launch": mask["ms_per_launch"],
                           "algorithmic_flops_per_launch": flops}
         if roofline is None or mask["ms_per_launch"] > kde["ms_per_launch"]:
             roofline, distance_tiles = distance_tiles, roofline
