@@ -275,7 +275,11 @@ static int32_t root_bins_per_item(const fsg_ctx* ctx, int64_t tiles, int32_t nbi
     int64_t chunks = (32 * waves + tiles - 1) / tiles;
     if (chunks > nbins) chunks = nbins;
     if (chunks < 1) chunks = 1;
-    return (int32_t)((nbins + chunks - 1) / chunks);
+    int64_t bpc = (nbins + chunks - 1) / chunks;
+    // whole 128-byte lines (16 doubles) of each output row per item, so that
+    // no line is written back in part by two items
+    if (nbins >= 16) bpc = std::min<int64_t>(nbins, (bpc + 15) / 16 * 16);
+    return (int32_t)bpc;
 }
 
 // 16-column blocks per keep-mask chunk.  Work items (chunk, group of tiles)
