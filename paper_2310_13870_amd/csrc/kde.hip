@@ -12,6 +12,8 @@
 // boundary is crossed the 4 partial sums of each query row are combined with
 // two cross-lane steps and written once: no atomics, fixed order, so results
 // are bit-reproducible.
+#include <type_traits>
+
 #include "common.h"
 #include "device.h"
 #include "kde_epilogue.h"
@@ -21,7 +23,7 @@ namespace fsg {
 // MULTI: items of many point sets in one launch; segment sg.job selects the
 // arguments of its point set from a.jobs.
 template <int D4, int RQ, bool MULTI>
-__global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2 : 1))) void kde_bins_kernel(KdeArgs a) {
     __shared__ int32_t win_all[4][kBinWindow];
     const int lane = threadIdx.x & 63;
     int32_t* win = win_all[threadIdx.x >> 6];
@@ -66,7 +68,10 @@ __global__ __launch_bounds__(256) void kde_bins_kernel(KdeArgs a) {
         // never read outside the data set, whatever the boundaries say
         const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)J.n_data));
         const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
-        BinAccumulator<RQ> bins;
+        // one open bin per lane where there are four query blocks (fewer
+        // registers than four parked bins, which lets d <= 32 run two waves
+        // per SIMD); the four-bin shift register otherwise
+        typename std::conditional<RQ == 4, BinAccumulator1<RQ>, BinAccumulator<RQ>>::type bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
         bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);

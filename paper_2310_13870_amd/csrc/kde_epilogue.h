@@ -293,17 +293,27 @@ struct BinAccumulator1 {
         }
     }
 
-    // bin cur is complete: combine it, stage it, write a full window
-    __device__ __forceinline__ void close() {
-        const double t02 = swap32_add(slot[0], slot[2]);
-        const double t13 = swap32_add(slot[1], slot[3]);
+    __device__ __forceinline__ void push(double v) {
         stage[0] = stage[1];
         stage[1] = stage[2];
         stage[2] = stage[3];
-        stage[3] = swap16_add(t02, t13);
+        stage[3] = v;
+    }
+
+    // bin cur is complete: combine it and stage it; a full window, or the
+    // last bin's window padded with the empty bins after it, is written
+    __device__ __forceinline__ void close() {
+        const double t02 = swap32_add(slot[0], slot[2]);
+        const double t13 = swap32_add(slot[1], slot[3]);
+        push(swap16_add(t02, t13));
 #pragma unroll
         for (int qb = 0; qb < RQ; ++qb) slot[qb] = 0.0;
-        if ((cur & 3) == 3) write_window(cur);
+        if ((cur & 3) == 3) {
+            write_window(cur);
+        } else if (cur == b1 - 1) {
+            for (int32_t c = cur + 1; (c & 3) != 0; ++c) push(0.0);
+            write_window(cur | 3);
+        }
     }
 
     __device__ __forceinline__ void advance() {
@@ -353,22 +363,10 @@ struct BinAccumulator1 {
         }
     }
 
-    // the open bin and the empty bins after it, to the end of the item
+    // the open bin and the empty bins after it, to the end of the item (once
+    // bin b1 - 1 has been closed, by add() or here, every bin is written)
     __device__ __forceinline__ void finish() {
-        if (cur < b0 - 1) cur = b0 - 1;
-        while (cur < b1) {  // close bins until the window of b1 - 1 is written
-            close();
-            if (cur >= b1 - 1 && (cur & 3) != 3) {  // pad the last window with the empty bins after it
-                for (int32_t c = cur + 1; (c & 3) != 0; ++c) {
-                    stage[0] = stage[1];
-                    stage[1] = stage[2];
-                    stage[2] = stage[3];
-                    stage[3] = 0.0;
-                }
-                write_window(cur | 3);
-            }
-            ++cur;
-        }
+        for (; cur < b1; ++cur) close();
     }
 };
 
