@@ -24,7 +24,13 @@ namespace fsg {
 // arguments of its point set from a.jobs.
 template <int D4, int RQ, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2 : 1))) void kde_bins_kernel(KdeArgs a) {
+    // the table exponential where two waves share a SIMD (d <= 32), whose LDS
+    // reads the other wave hides; the polynomial one at one wave per SIMD
+    constexpr bool kTab = D4 <= 8;
+    constexpr double kScale = kTab ? 256.0 : 1.0;  // exponent terms scaled for exp2_256_tab
     __shared__ int32_t win_all[4][kBinWindow];
+    __shared__ double exp_tab[kTab ? 256 : 1];
+    if (kTab) load_exp2_table(exp_tab);
     const int lane = threadIdx.x & 63;
     int32_t* win = win_all[threadIdx.x >> 6];
     const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
@@ -38,7 +44,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2
         const SegDesc sg = a.segs[w.seg];
         const KdeArgs& J = MULTI ? a.jobs[sg.job] : a;
         const int32_t* bnd = J.bounds + sg.bound_off;
-        const double two_s = 2.0 * J.s;
+        const double two_s = 2.0 * kScale * J.s;
 
         double qf[RQ][D4];
         double hq[RQ];
@@ -53,7 +59,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2
             int32_t sf = -1;
             if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -J.s * J.qnorm[p];
+            hq[qb] = -kScale * J.s * J.qnorm[p];
             load_row_part<D4>(qf[qb], J.Qp, p, grp);
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 jj[i] = c0 + 4 * grp + i;
-                hx[i] = -J.s * xn[i];
+                hx[i] = -kScale * J.s * xn[i];
             }
             double4_t c[RQ];
 #pragma unroll
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, false>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, nullptr, kv);
+            exact_values<RQ, kTab>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, exp_tab, kv);
             bins.add(kv, jj, c0 + 15);
             if (more) {
                 if (kPrefetch) {
