@@ -67,7 +67,7 @@ typedef enum {
      * and node mass then differs from the exact one by less than
      * (n-1) e^-Delta < e^-25 = 1.4e-11 of the degree.
      * Applies to the pass over all points (fsg_degrees, the first pass of
-     * fsg_sample_edges); d <= 64. */
+     * fsg_sample_edges); d <= 128. */
     FSG_BF16_SPLIT = 1
 } fsg_precision;
 

@@ -1167,7 +1167,7 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
     const int D4 = feature_steps(d);
     if (D4 < 0) return set_error(ctx, FSG_E_UNSUPPORTED, "d > 128 is not built in this version");
     if (prec == FSG_BF16_SPLIT && filter_steps(D4) < 0)
-        return set_error(ctx, FSG_E_UNSUPPORTED, "the precision mode is built for d <= 64");
+        return set_error(ctx, FSG_E_UNSUPPORTED, "the precision mode is built for d <= 128");
     fsg_points* p = new (std::nothrow) fsg_points();
     if (!p) return set_error(ctx, FSG_E_NOMEM, "host allocation failed");
     p->ctx = ctx;

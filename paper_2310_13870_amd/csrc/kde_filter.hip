@@ -20,6 +20,8 @@
 // sends them through the same FP64 epilogue and bin accumulation as the plain
 // kernel.  Pairs not kept add 0: their total is below (n-1) e^-Delta of the
 // row's mass.
+#include <type_traits>
+
 #include "common.h"
 #include "device.h"
 #include "kde_epilogue.h"
@@ -46,7 +48,8 @@ int64_t keep_mask_waves(int KB, int num_cus) {
         case 1: return (int64_t)num_cus * 4 * mask_waves<1>();
         case 2: return (int64_t)num_cus * 4 * mask_waves<2>();
         case 3: return (int64_t)num_cus * 4 * mask_waves<3>();
-        default: return (int64_t)num_cus * 4 * mask_waves<6>();
+        case 6: return (int64_t)num_cus * 4 * mask_waves<6>();
+        default: return (int64_t)num_cus * 4 * mask_waves<12>();
     }
 }
 template <int D4>
@@ -267,7 +270,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         __builtin_amdgcn_wave_barrier();
         const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)J.n_data));
         const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
-        BinAccumulator1<RQ> bins;
+        // one open bin per lane with four query blocks, the four-bin shift
+        // register with two
+        typename std::conditional<RQ == 4, BinAccumulator1<RQ>, BinAccumulator<RQ>>::type bins;
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
         bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);
@@ -446,6 +451,7 @@ hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st) {
         case 2: return launch_mask_t<2>(m, num_cus, st);
         case 3: return launch_mask_t<3>(m, num_cus, st);
         case 6: return launch_mask_t<6>(m, num_cus, st);
+        case 12: return launch_mask_t<12>(m, num_cus, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -456,10 +462,13 @@ static hipError_t launch_exact_t(const KdeArgs& a, int64_t max_items, unsigned l
     int64_t waves = (int64_t)num_cus * 8;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
+    // 32-entry items for d > 64 (kde_tile), whose FP64 query fragments
+    // would not fit the LDS at 64
+    constexpr int RQ = D4 >= 32 ? 2 : 4;
     if (a.jobs)
-        kde_exact_kept_kernel<D4, 4, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
+        kde_exact_kept_kernel<D4, RQ, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
     else
-        kde_exact_kept_kernel<D4, 4, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
+        kde_exact_kept_kernel<D4, RQ, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
     return hipGetLastError();
 }
 
@@ -471,6 +480,7 @@ hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long 
         case 4: return launch_exact_t<4>(a, max_items, next_item, num_cus, st);
         case 8: return launch_exact_t<8>(a, max_items, next_item, num_cus, st);
         case 16: return launch_exact_t<16>(a, max_items, next_item, num_cus, st);
+        case 32: return launch_exact_t<32>(a, max_items, next_item, num_cus, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -486,6 +496,7 @@ int filter_steps(int D4) {
         case 4: return 2;
         case 8: return 3;
         case 16: return 6;
+        case 32: return 12;
         default: return -1;
     }
 }
@@ -672,6 +683,7 @@ hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double
     else if (d <= 16) pivot_kernel<16><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
     else if (d <= 32) pivot_kernel<32><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
     else if (d <= 64) pivot_kernel<64><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
+    else if (d <= 128) pivot_kernel<128><<<blocks, 256, 0, st>>>(X, n, d, P, dmin, label, ids);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

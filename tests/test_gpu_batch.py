@@ -37,7 +37,7 @@ def _reference(ctx, pts):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
 def test_batch_equals_single(prec):
-    sets = [s for s in SETS if prec == "fp32" or s[1] <= 64]
+    sets = SETS
     say(f"batch {prec}: {len(sets)} jobs")
     ctx = fsg.Context(0)
     try:

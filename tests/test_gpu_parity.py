@@ -256,7 +256,8 @@ def test_multi_pass_plans(ctx, cap):
 # Precision mode (BF16 split filter + exact FP64 recompute)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n,d,gamma", [(2, 2, 0.5), (17, 5, 0.3), (1000, 2, 0.5), (2049, 8, 0.1),
-                                       (3001, 32, 1 / 8), (1500, 33, 0.02), (777, 64, 1 / 18), (4000, 16, 0.3)])
+                                       (3001, 32, 1 / 8), (1500, 33, 0.02), (777, 64, 1 / 18), (4000, 16, 0.3),
+                                       (1300, 65, 0.02), (2100, 100, 0.01), (999, 128, 1 / 32)])
 def test_degrees_bf16_split(ctx, n, d, gamma):
     say(f"degrees bf16_split n={n} d={d}")
     X = _mix(n, d, 700 + n + d)
@@ -268,7 +269,7 @@ def test_degrees_bf16_split(ctx, n, d, gamma):
 
 
 @pytest.mark.parametrize("n,d,L", [(2, 2, 4), (65, 2, 7), (1000, 2, 10), (4097, 8, 13), (3000, 32, 12),
-                                   (2000, 64, 8), (1111, 17, 9)])
+                                   (2000, 64, 8), (1111, 17, 9), (1700, 128, 9), (801, 97, 6)])
 def test_sample_edges_bf16_split(ctx, n, d, L):
     X = _mix(n, d, 900 + n + d)
     gamma = 1.0 / (2.0 * (0.5 * math.sqrt(d)) ** 2)
