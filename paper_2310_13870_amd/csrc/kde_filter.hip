@@ -192,10 +192,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
 
 // ---------------------------------------------------------------------------
 // Stage 2: exact recompute of the kept columns.  Work item = (query tile,
-// run of bins).  Kept columns enter a circular queue in index order; every 16
-// of them form one gathered block for the FP64 matrix cores and the binned
-// epilogue.  The operands of the next block are loaded while the current one
-// is computed; the FP64 query fragments live in LDS.
+// run of bins).  Kept columns enter a per-wave queue in LDS in index order, 16
+// mask blocks at a time; every 16 of them form one gathered block for the
+// FP64 matrix cores and the binned epilogue.  The operands of the next block
+// are loaded while the current one is computed; the FP64 query fragments
+// live in LDS.
 // ---------------------------------------------------------------------------
 template <int D4>
 struct Gathered {
