@@ -345,7 +345,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if (!bnd) return st;
     const int64_t n = X->n;
     const int32_t nbins = 1 << D;
-    const int32_t tile = kde_tile(X->D4);
+    const int32_t tile = (X->prec == FSG_BF16_SPLIT) ? exact_tile(X->D4) : kde_tile(X->D4);
     const int64_t tiles = (n + tile - 1) / tile;
     const int32_t bpc = root_bins_per_item(ctx, tiles, nbins);
     const int64_t n_items = tiles * ((nbins + bpc - 1) / bpc);
@@ -844,7 +844,7 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
         if ((st = job_root_args(ctx, j, &hargs[i], &hmargs[i])) != FSG_OK) return fail(st);
         const int64_t n = j->S.X->n;
         const int32_t nbins = 1 << j->root_D;
-        const int32_t tile = kde_tile(j->S.X->D4);
+        const int32_t tile = bf16 ? exact_tile(j->S.X->D4) : kde_tile(j->S.X->D4);
         const int64_t n_tiles = (n + tile - 1) / tile;
         int64_t bpc;
         if (bf16) {

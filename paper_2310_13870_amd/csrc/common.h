@@ -245,6 +245,7 @@ hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t s
 // KDE over a work list; grid = waves / 4 blocks of 256 threads.
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu = 8);
 int kde_tile(int D4);  // query entries per work item of the plain kernel
+int exact_tile(int D4);  // query entries per work item of the exact recompute (precision mode)
 hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
                               int32_t* n_items, hipStream_t st);
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);

@@ -23,10 +23,10 @@ namespace fsg {
 // MULTI: items of many point sets in one launch; segment sg.job selects the
 // arguments of its point set from a.jobs.
 template <int D4, int RQ, bool MULTI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 8 ? 2 : 1))) void kde_bins_kernel(KdeArgs a) {
-    // the table exponential where two waves share a SIMD (d <= 32), whose LDS
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 2 : 1))) void kde_bins_kernel(KdeArgs a) {
+    // the table exponential where two waves share a SIMD (d <= 64), whose LDS
     // reads the other wave hides; the polynomial one at one wave per SIMD
-    constexpr bool kTab = D4 <= 8;
+    constexpr bool kTab = D4 <= 16;
     constexpr double kScale = kTab ? 256.0 : 1.0;  // exponent terms scaled for exp2_256_tab
     __shared__ int32_t win_all[4][kBinWindow];
     __shared__ double exp_tab[kTab ? 256 : 1];
@@ -148,7 +148,7 @@ static hipError_t launch_kde_t(const KdeArgs& a, int64_t max_items, int num_cus,
     return hipGetLastError();
 }
 
-int kde_tile(int D4) { return D4 >= 32 ? 32 : 64; }
+int kde_tile(int D4) { return D4 >= 16 ? 32 : 64; }
 
 int feature_steps(int d) {
     const int d4 = (d + 3) / 4;
@@ -162,14 +162,15 @@ int feature_steps(int d) {
 }
 
 // The query tile (16 RQ entries per item) is kde_tile(D4): 64, and 32 for
-// d > 64, where 64 FP64 query rows would not fit the register file.
+// d > 32, where 32 FP64 query rows let two waves share a SIMD (d <= 64) or
+// 64 would not fit the register file (d > 64).
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu) {
     switch (a.D4) {
         case 1: return launch_kde_t<1, 4>(a, max_items, num_cus, waves_per_cu, st);
         case 2: return launch_kde_t<2, 4>(a, max_items, num_cus, waves_per_cu, st);
         case 4: return launch_kde_t<4, 4>(a, max_items, num_cus, waves_per_cu, st);
         case 8: return launch_kde_t<8, 4>(a, max_items, num_cus, waves_per_cu, st);
-        case 16: return launch_kde_t<16, 4>(a, max_items, num_cus, waves_per_cu, st);
+        case 16: return launch_kde_t<16, 2>(a, max_items, num_cus, waves_per_cu, st);
         case 32: return launch_kde_t<32, 2>(a, max_items, num_cus, waves_per_cu, st);
         default: return hipErrorInvalidValue;
     }

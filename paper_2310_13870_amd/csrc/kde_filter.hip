@@ -463,7 +463,7 @@ static hipError_t launch_exact_t(const KdeArgs& a, int64_t max_items, unsigned l
     int64_t waves = (int64_t)num_cus * 8;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
-    // 32-entry items for d > 64 (kde_tile), whose FP64 query fragments
+    // 32-entry items for d > 64 (exact_tile), whose FP64 query fragments
     // would not fit the LDS at 64
     constexpr int RQ = D4 >= 32 ? 2 : 4;
     if (a.jobs)
@@ -485,6 +485,8 @@ hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long 
         default: return hipErrorInvalidValue;
     }
 }
+
+int exact_tile(int D4) { return D4 >= 32 ? 32 : 64; }
 
 int split_steps(int d) { return (3 * d + 31) / 32; }
 
