@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--precision", default="bf16_split", choices=["fp32", "bf16_split"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--levels-per-pass", type=int, default=0,
+                    help="cap on the tree levels one binned pass resolves (0: the library's choice)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference "
                          "that scales the HBM byte counters of a profiling run")
@@ -409,6 +411,8 @@ def main():
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(X).to(dev)
     ctx = fsg.Context(0)
+    if args.levels_per_pass:
+        ctx.set_levels_per_pass(args.levels_per_pass)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -626,6 +626,7 @@ static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
         LeafArgs la;
         std::memset(&la, 0, sizeof(la));
         la.X = X->X;
+        la.norm = X->norm;
         la.n = X->n;
         la.d = X->d;
         la.bounds = bnd;

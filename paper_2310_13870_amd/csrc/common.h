@@ -305,6 +305,7 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st);
 
 struct LeafArgs {
     const float* X;            // FP32 points
+    const double* norm;        // FP64 ||x||^2
     int64_t n;
     int32_t d;
     const int32_t* bounds;     // boundaries of the nodes at `level`

@@ -5,12 +5,14 @@
 //    levels down it, one Philox uniform per level;
 //  * the leaf stage resolves nodes of at most 64 points directly: a wave takes
 //    up to 64 samples that sit in the same node, evaluates the kernel of each
-//    sample's point against every point of the node (difference form, FP64),
-//    keeps the row in LDS, and each lane walks its own sample to a leaf.
+//    sample's point against every point of the node (FP64, as the binned
+//    passes do: |q|^2 + |x|^2 - 2 q.x and the table exponential), keeps the
+//    row in registers, and each lane walks its own sample to a leaf.
 #include <type_traits>
 
 #include "common.h"
 #include "device.h"
+#include "kde_epilogue.h"
 
 namespace fsg {
 
@@ -184,20 +186,26 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
 // samples in sorted_samples; an item holds up to 64 samples of one node.
 // ---------------------------------------------------------------------------
 
-// Leaf stage for d <= 32: each lane keeps its sample's (<= 64) kernel values
+// Leaf stage: each lane keeps its sample's (<= 64) kernel values
 // in registers; the child masses of every level are summed with static
 // predicates, so the descent has no dependent memory chains.
 template <int DMAX>
-__global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void leaf_reg_kernel(LeafArgs a) {
     // d <= 32: the query row in registers, node points in LDS row by row, four
-    // points at a time.  d > 32: features outer, the 64 points' distances in
+    // points at a time.  d > 32: features outer, the 64 points' cross terms in
     // registers, node points staged transposed (feature-major) in FP32 (the
-    // input precision; the difference is formed in FP64, where it is exact).
+    // input precision; products are formed in FP64, where they are exact).
+    // z = -256 s (|q|^2 + |x|^2) + 512 s q.x, as in the binned passes, and
+    // 2^(z/256) from the table.
     constexpr bool kWide = DMAX > 32;
     typedef typename std::conditional<kWide, float, double>::type stage_t;
     __shared__ stage_t xs[kWide ? DMAX * kLeafMax : (kLeafMax + 3) * DMAX];
+    __shared__ double xns[kLeafMax];  // |x|^2 of the node's points, 0 past the last
+    __shared__ double exp_tab[256];
+    load_exp2_table(exp_tab);
     const int lane = threadIdx.x;
     const int32_t n_items = *a.n_items;
+    const double s256 = 256.0 * a.s, two_s = 2.0 * s256;
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int32_t v = a.items[2 * it], p0 = a.items[2 * it + 1];
         const int32_t p1 = a.node_start[v + 1];
@@ -210,6 +218,8 @@ __global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
         const int32_t i = smp / a.L, l = smp - i * a.L;
         const float* xi = a.X + (int64_t)i * a.d;
         const int32_t self = i - lo;  // the sample's own point, if it lies in the node
+        const double hq = -s256 * a.norm[i];
+        xns[lane] = (lane < cnt) ? a.norm[lo + lane] : 0.0;
         double kv[kLeafMax];
         if constexpr (kWide) {
             // xs[t * 64 + j] = X[lo + j][t]; points past the node are 0
@@ -219,28 +229,28 @@ __global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
             }
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kLeafMax; ++j) kv[j] = 0.0;  // the distances first
+            for (int j = 0; j < kLeafMax; ++j) kv[j] = 0.0;  // the cross terms first
             for (int32_t t = 0; t < a.d; ++t) {
                 const double qt = (double)xi[t];
                 const stage_t* xt = xs + t * kLeafMax;
 #pragma unroll
-                for (int j = 0; j < kLeafMax; ++j) {
-                    const double df = qt - (double)xt[j];
-                    kv[j] = __builtin_fma(df, df, kv[j]);
-                }
+                for (int j = 0; j < kLeafMax; ++j) kv[j] = __builtin_fma(qt, (double)xt[j], kv[j]);
             }
 #pragma unroll
             for (int j = 0; j < kLeafMax; ++j) {
-                const double k = exp2_fp64(-a.s * kv[j]);
-                kv[j] = (j < cnt && j != self) ? k : 0.0;
+                // (a uniform branch per point: evaluated unconditionally, the 64
+                // exponentials get interleaved and spill)
+                const double k = (j < cnt) ? exp2_256_tab(__builtin_fma(two_s, kv[j], hq - s256 * xns[j]), exp_tab)
+                                           : 0.0;
+                kv[j] = (j != self) ? k : 0.0;
             }
         } else {
             {
-                const int32_t total = cnt * a.d;
+                // rows of the node's points, zero-padded to DMAX features
                 const float* src = a.X + (int64_t)lo * a.d;
-                for (int32_t k = lane; k < total; k += 64) {
-                    const int32_t r = k / a.d, t = k - r * a.d;
-                    xs[r * DMAX + t] = (stage_t)src[k];
+                for (int32_t k = lane; k < cnt * DMAX; k += 64) {
+                    const int32_t r = k / DMAX, t = k - r * DMAX;
+                    xs[k] = (t < a.d) ? (stage_t)src[(int64_t)r * a.d + t] : (stage_t)0;
                 }
             }
             __syncthreads();
@@ -250,22 +260,18 @@ __global__ __launch_bounds__(64) void leaf_reg_kernel(LeafArgs a) {
 #pragma unroll
             for (int j0 = 0; j0 < kLeafMax; j0 += 4) {
                 if (j0 < cnt) {
-                    double D[4] = {0.0, 0.0, 0.0, 0.0};
+                    double c[4] = {0.0, 0.0, 0.0, 0.0};
                     const stage_t* xj = xs + j0 * DMAX;
 #pragma unroll
                     for (int t = 0; t < DMAX; ++t) {
-                        if (t < a.d) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const double df = (double)q[t] - (double)xj[u * DMAX + t];
-                                D[u] = __builtin_fma(df, df, D[u]);
-                            }
-                        }
+                        for (int u = 0; u < 4; ++u) c[u] = __builtin_fma((double)q[t], (double)xj[u * DMAX + t], c[u]);
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const double k = exp2_fp64(-a.s * D[u]);
-                        kv[j0 + u] = (j0 + u < cnt && j0 + u != self) ? k : 0.0;
+                        const int j = j0 + u;
+                        const double k = exp2_256_tab(__builtin_fma(two_s, c[u], hq - s256 * xns[j]), exp_tab);
+                        kv[j] = (j < cnt && j != self) ? k : 0.0;
                     }
                 } else {
 #pragma unroll
