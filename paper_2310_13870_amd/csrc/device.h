@@ -143,6 +143,10 @@ __device__ __forceinline__ bool choose_left(double u, double mL, double mR, doub
     return left;
 }
 
+// The compiler's lane-write intrinsic (v_writelane_b32): lane `lane` of the
+// result is `val` (both uniform), the other lanes keep `old`.
+__device__ uint32_t writelane_u32(uint32_t val, uint32_t lane, uint32_t old) __asm("llvm.amdgcn.writelane.i32");
+
 // Split of node [a,b): the left half holds floor((b-a)/2) points.
 __device__ __forceinline__ int32_t tree_split(int32_t a, int32_t b) { return a + ((b - a) >> 1); }
 

@@ -55,6 +55,10 @@ int64_t keep_mask_waves(int KB, int num_cus) {
 template <int D4>
 constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
 
+// Word 3 of a raw buffer resource on gfx9-family parts: 32-bit data format,
+// no swizzle, no index stride.
+constexpr int kBufferFlags = 0x00020000;
+
 template <int KB, int TP, int WAVES, bool MULTI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m0) {
     // Queries are the A operand and data the B operand, so lane l receives
@@ -110,12 +114,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
         const int32_t n_live = (int32_t)min((int64_t)TP, m.n_tiles - tile0);  // tiles of this item that exist
         uint16_t* mrow = m.mask + tile0 * m.n_blocks;
         const int64_t mstride = m.n_blocks;
-        const bf16x8_t* X16 = (const bf16x8_t*)m.Xb;
-        // the operands of block b: split data rows and -|x|^2/2 of this lane's column
+        // the operands of block b: split data rows and -|x|^2/2 of this lane's
+        // column, as buffer loads from the chunk's first block with the
+        // block's offset in a scalar register (the lane offsets stay constant,
+        // so the loop does no vector address arithmetic); a chunk spans at
+        // most a few MB, well inside the 32-bit offsets
+        const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)((const char*)m.Xb + (int64_t)bb * (KB * 1024)), (short)0, 0x7fffffff, kBufferFlags);
+        const __amdgpu_buffer_rsrc_t ars =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(m.xa + (int64_t)bb * 16), (short)0, 0x7fffffff, kBufferFlags);
         auto load = [&](bf16x8_t (&x)[KB], float& xa, int32_t blk) {
+            const int32_t rel = blk - bb;
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) x[kb] = X16[((int64_t)blk * KB + kb) * 64 + lane];
-            xa = m.xa[(int64_t)blk * 16 + r];
+            for (int kb = 0; kb < KB; ++kb) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(xrs, kb * 1024 + lane * 16, rel * (KB * 1024), 0);
+                x[kb] = __builtin_bit_cast(bf16x8_t, v);
+            }
+            xa = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ars, r * 4, rel * 64, 0));
         };
         // lane (b mod 64) keeps the masks of block b until 64 blocks are ready
         uint32_t pending[TP];
@@ -140,15 +155,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             for (int h = 0; h < TP; ++h) {
                 // the lane's 16 results all belong to its one data column:
                 // a column is kept when the largest of them reaches |x|^2/2
+                // (the NaN-propagating maximum needs no canonicalising of its
+                // operands; the operands are finite or -inf)
                 float dm = cc[4 * h][0];
 #pragma unroll
                 for (int qb = 4 * h; qb < 4 * h + 4; ++qb)
 #pragma unroll
-                    for (int i = (qb == 4 * h) ? 1 : 0; i < 4; ++i) dm = __builtin_fmaxf(dm, cc[qb][i]);
+                    for (int i = (qb == 4 * h) ? 1 : 0; i < 4; ++i) dm = __builtin_elementwise_maximum(dm, cc[qb][i]);
                 const uint64_t any = __ballot(dm >= -xa);
                 const uint32_t keep = (uint32_t)((any | (any >> 16) | (any >> 32) | (any >> 48)) & tail);
                 kept += __popc(keep);
-                if ((blk & 63) == lane) pending[h] = keep;
+                // lane blk % 64 takes the (uniform) keep bits
+                pending[h] = writelane_u32(keep, (uint32_t)(blk & 63), pending[h]);
             }
             if ((blk & 63) == 63 || blk + 1 == be) {
                 const int32_t b = (blk & ~63) + lane;
