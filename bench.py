@@ -39,7 +39,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 KERNEL_SOURCES = {
     "kde_bins": ("kde.hip", "kde_epilogue.h", "device.h", "common.h"),
     "kde_exact_kept": ("kde_filter.hip", "kde_epilogue.h", "exp2_table.h", "device.h", "common.h"),
-    "kde_keep_mask": ("kde_filter.hip", "device.h", "common.h"),
+    "kde_keep_mask": ("kde_mask.hip", "device.h", "common.h"),
 }
 
 

@@ -25,9 +25,18 @@ FLAGS = [
 ]
 
 
+# Per-source additions.  kde_mask.hip: the matrix ops in their VGPR form (the
+# keep-mask kernel places its query fragments in the accumulation registers
+# itself; by default the compiler would put the cross terms there, and every
+# keep test would first copy them out).
+EXTRA = {
+    "kde_mask.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

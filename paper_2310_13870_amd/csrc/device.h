@@ -143,6 +143,11 @@ __device__ __forceinline__ bool choose_left(double u, double mL, double mR, doub
     return left;
 }
 
+// A value the whole wave agrees on, kept in a scalar register: loop bounds
+// and bin indices derived from LDS or vector loads would otherwise be
+// treated as per-lane values.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // The compiler's lane-write intrinsic (v_writelane_b32): lane `lane` of the
 // result is `val` (both uniform), the other lanes keep `old`.
 __device__ uint32_t writelane_u32(uint32_t val, uint32_t lane, uint32_t old) __asm("llvm.amdgcn.writelane.i32");

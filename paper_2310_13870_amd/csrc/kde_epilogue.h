@@ -19,11 +19,6 @@
 
 namespace fsg {
 
-// A value the whole wave agrees on, kept in a scalar register: loop bounds
-// and bin indices derived from LDS or vector loads would otherwise be
-// treated as per-lane values.
-__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
 // Row rho of the A operand holds block position perm_row(rho); the result
 // element i of lane group g is then position 4g + i.
 __device__ __forceinline__ int perm_row(int rho) { return 4 * (rho & 3) + (rho >> 2); }
