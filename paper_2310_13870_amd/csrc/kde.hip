@@ -102,12 +102,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 
                 for (int i = 0; i < 4; ++i) xn_next[i] = J.xnorm[c0 + 16 + 4 * grp + i];
             }
             int32_t jj[4];
-            double hx[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                jj[i] = c0 + 4 * grp + i;
-                hx[i] = -kScale * J.s * xn[i];
-            }
+            for (int i = 0; i < 4; ++i) jj[i] = c0 + 4 * grp + i;
             double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
@@ -116,7 +112,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, kTab>(c, hq, hx, two_s, jj, selfv, smin, smax, c0, c0 + 15, exp_tab, kv);
+            exact_values<RQ, kTab>(c, hq, xn, -kScale * J.s, two_s, jj, selfv, smin, smax, c0, c0 + 15, exp_tab, kv);
             bins.add(kv, jj, c0 + 15);
             if (more) {
                 if (kPrefetch) {

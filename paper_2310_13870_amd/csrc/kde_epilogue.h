@@ -367,20 +367,23 @@ struct BinAccumulator1 {
 
 // The FP64 epilogue of one query block against 16 columns: kernel values
 // from the cross terms c (result element i of lane group g is block position
-// 4g + i), the self term removed.  With tab (the LDS copy of kExp2Table) the
-// exponent terms are scaled by 256 (hq = -256 s |q|^2, hx = -256 s |x|^2,
-// two_s = 512 s, s = gamma log2 e), a power of two that leaves every rounding
-// as it is, and exp2_256_tab evaluates them; without it (tab = nullptr, a
-// compile-time choice of the caller) hq = -s |q|^2, hx = -s |x|^2, two_s = 2 s
-// and exp2_fp64 does.  The self compare runs only when a query of the block
-// has its own index in [lo_col, hi_col].
+// 4g + i), the self term removed.  The exponent of each pair is
+// fma(two_s, c, fma(|x|^2, neg_s, hq)): the column's norm term enters through
+// a fused multiply-add, one rounding of the large partial sum.  With tab (the
+// LDS copy of kExp2Table) the exponent terms are scaled by 256 (hq = -256 s
+// |q|^2, neg_s = -256 s, two_s = 512 s, s = gamma log2 e), a power of two that
+// leaves every rounding as it is, and exp2_256_tab evaluates them; without it
+// (tab = nullptr, a compile-time choice of the caller) hq = -s |q|^2, neg_s =
+// -s, two_s = 2 s and exp2_fp64 does.  The self compare runs only when a query
+// of the block has its own index in [lo_col, hi_col].
 template <bool TAB>
-__device__ __forceinline__ void exact_values_block(const double4_t& c, double hq, const double (&hx)[4], double two_s,
-                                                   const int32_t (&jj)[4], int32_t selfv, int32_t smin, int32_t smax,
-                                                   int32_t lo_col, int32_t hi_col, const double* tab, double (&kv)[4]) {
+__device__ __forceinline__ void exact_values_block(const double4_t& c, double hq, const double (&xn)[4], double neg_s,
+                                                   double two_s, const int32_t (&jj)[4], int32_t selfv, int32_t smin,
+                                                   int32_t smax, int32_t lo_col, int32_t hi_col, const double* tab,
+                                                   double (&kv)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const double z = __builtin_fma(two_s, c[i], hq + hx[i]);
+        const double z = __builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq));
         kv[i] = TAB ? exp2_256_tab(z, tab) : exp2_fp64(z);
     }
     if (smax >= lo_col && smin <= hi_col && __ballot(selfv >= lo_col && selfv <= hi_col) != 0) {
@@ -392,14 +395,15 @@ __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq
 
 // The FP64 epilogue of all query blocks against one 16-column block.
 template <int RQ, bool TAB>
-__device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const double (&hq)[RQ], const double (&hx)[4],
-                                             double two_s, const int32_t (&jj)[4], const int32_t (&selfv)[RQ],
-                                             const int32_t (&smin)[RQ], const int32_t (&smax)[RQ], int32_t lo_col,
-                                             int32_t hi_col, const double* tab, double (&kv)[RQ][4]) {
+__device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const double (&hq)[RQ], const double (&xn)[4],
+                                             double neg_s, double two_s, const int32_t (&jj)[4],
+                                             const int32_t (&selfv)[RQ], const int32_t (&smin)[RQ],
+                                             const int32_t (&smax)[RQ], int32_t lo_col, int32_t hi_col,
+                                             const double* tab, double (&kv)[RQ][4]) {
 #pragma unroll
     for (int qb = 0; qb < RQ; ++qb)
-        exact_values_block<TAB>(c[qb], hq[qb], hx, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col, hi_col, tab,
-                                kv[qb]);
+        exact_values_block<TAB>(c[qb], hq[qb], xn, neg_s, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col, hi_col,
+                                tab, kv[qb]);
 }
 
 }  // namespace fsg

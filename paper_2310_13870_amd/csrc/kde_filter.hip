@@ -194,9 +194,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
 
         auto compute = [&](const Gathered<D4>& g) {
             // padding columns: |x|^2 = +inf gives exponent -inf and value 0
-            double hx[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) hx[i] = -s256 * g.xn[i];
             double4_t c[RQ];
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
@@ -208,7 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, true>(c, hq, hx, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
+            exact_values<RQ, true>(c, hq, g.xn, -s256, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
             bins.add(kv, g.jj, g.last);
         };
 
