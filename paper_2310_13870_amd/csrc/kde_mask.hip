@@ -168,31 +168,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             }
         };
         // Software pipeline over the blocks: the matrix ops of block b + 1
-        // are issued before the keep bits of block b are taken, and the
-        // operands of block b + 2 load meanwhile (two operand buffers, two
-        // accumulator sets).  Past the end the last block is loaded and
-        // multiplied again (in bounds, results unused), so that every
-        // iteration issues the same instructions.
+        // are issued before the keep bits of block b are taken, while the
+        // operands of a later block load: block b + 3 with three operand
+        // buffers in turn where one wave runs per SIMD (a load has two
+        // blocks' worth of matrix work to arrive), block b + 2 with two where
+        // two waves share the registers.  Two accumulator sets.  Past the end
+        // the last block is loaded and multiplied again (in bounds, results
+        // unused), so that every step issues the same instructions.
         auto clampb = [&](int32_t b) { return b < be ? b : be - 1; };
-        bf16x8_t x0[KB], x1[KB];
-        float a0, a1;
+        constexpr int AHEAD = (WAVES == 1) ? 3 : 2;
+        bf16x8_t x0[KB], x1[KB], x2[KB];
+        float a0, a1, a2;
         float4_t c0[QB], c1[QB];
         float f0, f1;  // -|x|^2/2 of the blocks whose keep bits are taken next
+        int32_t blk = bb;
+        // one step: load block blk + AHEAD into the free buffer xl, multiply
+        // block blk + 1 (buffer xm) into cm, take the keep bits of block blk (cf)
+        auto step = [&](bf16x8_t (&xl)[KB], float& al, const bf16x8_t (&xm)[KB], float am, float4_t (&cm)[QB],
+                        float& fm, const float4_t (&cf)[QB], float ff) {
+            load(xl, al, clampb(blk + AHEAD));
+            mma(cm, xm);
+            fm = am;
+            finish(cf, ff, blk);
+        };
         load(x0, a0, bb);
         load(x1, a1, clampb(bb + 1));
+        if constexpr (AHEAD == 3) load(x2, a2, clampb(bb + 2));
         mma(c0, x0);
         f0 = a0;
-        for (int32_t blk = bb;;) {
-            load(x0, a0, clampb(blk + 2));
-            mma(c1, x1);
-            f1 = a1;
-            finish(c0, f0, blk);
-            if (++blk >= be) break;
-            load(x1, a1, clampb(blk + 2));
-            mma(c0, x0);
-            f0 = a0;
-            finish(c1, f1, blk);
-            if (++blk >= be) break;
+        for (;;) {
+            if constexpr (AHEAD == 3) {
+                step(x0, a0, x1, a1, c1, f1, c0, f0);
+                if (++blk >= be) break;
+                step(x1, a1, x2, a2, c0, f0, c1, f1);
+                if (++blk >= be) break;
+                step(x2, a2, x0, a0, c1, f1, c0, f0);
+                if (++blk >= be) break;
+                step(x0, a0, x1, a1, c0, f0, c1, f1);
+                if (++blk >= be) break;
+                step(x1, a1, x2, a2, c1, f1, c0, f0);
+                if (++blk >= be) break;
+                step(x2, a2, x0, a0, c0, f0, c1, f1);
+                if (++blk >= be) break;
+            } else {
+                step(x0, a0, x1, a1, c1, f1, c0, f0);
+                if (++blk >= be) break;
+                step(x1, a1, x0, a0, c0, f0, c1, f1);
+                if (++blk >= be) break;
+            }
         }
     }
     if (m0.kept != nullptr && lane == 0 && kept > 0) atomicAdd((unsigned long long*)m0.kept, (unsigned long long)kept);
