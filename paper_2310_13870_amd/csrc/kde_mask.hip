@@ -22,8 +22,9 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // Stage 1: keep masks.  For query tile t (64 entries) and data block b (16
 // columns) mask[t * n_blocks + b] has bit c set when column 16b + c is kept
-// for at least one query of the tile.  Work item = (tile, run of blocks); the
-// next block's operands are loaded while the current one is processed.
+// for at least one query of the tile.  Work item = (group of tiles, run of
+// blocks); the operands of later blocks load while the current one is
+// processed.
 // ---------------------------------------------------------------------------
 // occupancy targets that fit without spilling (measured on the MI355X: two
 // tiles per item at these occupancies beat one tile at three or two waves)
