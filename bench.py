@@ -69,7 +69,16 @@ def traffic_from_profile(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(X, w, target_s: float):
+# a sampled neighbour may differ from the oracle's only where the oracle's
+# uniform lies within this distance of a split boundary
+NEIGHBOUR_BAND = 1e-6
+
+
+def cpu_baseline(X, w, target_s: float, gpu_nbr=None, gpu_deg=None):
+    """The oracle timed on a seeded sample of rows; with the GPU run's
+    neighbours and degrees, also their agreement with the oracle on those rows."""
+    import numpy as np
+
     import oracle
     import workloads
     n, L = w.n, w.L
@@ -82,8 +91,20 @@ def cpu_baseline(X, w, target_s: float):
     m = int(min(n, max(8, round(len(rows) * target_s / max(t1, 1e-6)))))
     rows = workloads.subsample(n, m, 4243)
     t0 = time.perf_counter()
-    oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=False)
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=True)
     dt = time.perf_counter() - t0
+    agreement = None
+    if gpu_nbr is not None and gpu_deg is not None:
+        gdeg = np.asarray(gpu_deg)[rows]
+        rel = np.abs(gdeg - rdeg) / np.maximum(rdeg, 1e-300)
+        rel[rdeg == 0] = np.abs(gdeg[rdeg == 0])
+        gnbr = np.asarray(gpu_nbr).reshape(n, L)[rows]
+        mism = gnbr != rnbr
+        exempt = rmargin < NEIGHBOUR_BAND
+        agreement = {"rows": int(m), "samples": int(m * L),
+                     "degree_max_rel_err": float(rel.max()), "degree_p99_rel_err": float(np.percentile(rel, 99)),
+                     "neighbour_mismatches": int(mism.sum()), "band_exempt": int((mism & exempt).sum()),
+                     "non_exempt": int((mism & ~exempt).sum())}
     return {
         "value": m * L / dt,
         "unit": "sampled edges/s",
@@ -92,7 +113,9 @@ def cpu_baseline(X, w, target_s: float):
         "kind": "oracle",
         "seconds": dt,
         "sample": f"{m} seeded rows of the {n}-point workload: per row the full FP64 kernel row "
-                  f"({n - 1} evaluations), the degree and L={L} descents; reweighting/CSR (O(nL)) not included",
+                  f"({n - 1} evaluations), the degree and L={L} descents (with the split margins); "
+                  f"reweighting/CSR (O(nL)) not included",
+        "oracle_agreement": agreement,
     }
 
 
@@ -425,11 +448,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    last = {}  # the last step's neighbours and degrees (compared with the oracle after timing)
+
     def step():
         pts = fsg.Points(ctx, Xd, args.precision)
         nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, L, w.philox_seed)
         row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, L, nbr, deg)
         pts.close()
+        last["nbr"], last["deg"] = nbr, deg
         return col.numel()
 
     for _ in range(args.warmup):
@@ -522,9 +548,11 @@ def main():
         "second_kernel_roofline": distance_tiles,
         "cpu_baseline": None,
     }
+    gpu_nbr, gpu_deg = last["nbr"].cpu().numpy(), last["deg"].cpu().numpy()
+    last.clear()
     ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(X, w, args.cpu_seconds, gpu_nbr, gpu_deg)
     print(json.dumps(out), flush=True)
 
 
