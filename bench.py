@@ -197,6 +197,12 @@ def run_batched(args):
                 t = ctx.tuned_shape(D4, prec)
                 if t:
                     tuned[f"D4={D4},{prec}"] = {"waves_per_cu": t[0], "cols_per_item": t[1]}
+        # the picked sets' results of the last graph replay, for the oracle comparison
+        picked = {}
+        if not args.no_cpu_baseline:
+            for i in batched_pick(len(sets)):
+                nbr, deg = jobs[i].result()
+                picked[i] = (nbr.cpu().numpy(), deg.cpu().numpy())
         g.close()
         for j in jobs:
             j.close()
@@ -233,7 +239,7 @@ def run_batched(args):
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(sets, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_batched(sets, args.cpu_seconds, picked)
     print(json.dumps(out), flush=True)
 
 
@@ -365,14 +371,22 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_batched(sets, target_s: float):
-    """The oracle on seeded rows of a seeded subset of the sets (bounded time)."""
+def batched_pick(n_sets: int):
+    """The seeded subset of 8 sets the CPU baseline of a multi-set run covers."""
+    import numpy as np
+    rng = np.random.default_rng(4244)
+    return sorted(rng.choice(n_sets, size=8, replace=False).tolist())
+
+
+def cpu_baseline_batched(sets, target_s: float, results=None):
+    """The oracle on seeded rows of a seeded subset of the sets (bounded time);
+    with the GPU results of those sets ({set index: (nbr, deg)}), also their
+    agreement with the oracle on the rows."""
     import numpy as np
 
     import oracle
     import workloads
-    rng = np.random.default_rng(4244)
-    pick = sorted(rng.choice(len(sets), size=8, replace=False).tolist())
+    pick = batched_pick(len(sets))
     data = [(sets[i], sets[i].points()) for i in pick]
     work = 0.0
     t_cal = 0.0
@@ -384,18 +398,37 @@ def cpu_baseline_batched(sets, target_s: float):
     scale = max(1.0, target_s / max(t_cal, 1e-6))
     edges = 0
     evals = 0
+    outs = []
     t0 = time.perf_counter()
     for w, X in data:
         m = int(min(w.n, round(16 * scale)))
         rows = workloads.subsample(w.n, m, 4246)
-        oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows, want_margin=False)
+        outs.append((rows, oracle.sample_rows(X, w.gamma, w.L, w.philox_seed, rows=rows, want_margin=True)))
         edges += m * w.L
         evals += m * (w.n - 1)
     dt = time.perf_counter() - t0
+    agreement = None
+    if results is not None:
+        agreement = {"rows": 0, "samples": 0, "degree_max_rel_err": 0.0, "neighbour_mismatches": 0,
+                     "band_exempt": 0, "non_exempt": 0}
+        for i, (w, _), (rows, (rnbr, rdeg, rmargin)) in zip(pick, data, outs):
+            gnbr, gdeg = results[i]
+            gdeg = np.asarray(gdeg)[rows]
+            rel = np.abs(gdeg - rdeg) / np.maximum(rdeg, 1e-300)
+            rel[rdeg == 0] = np.abs(gdeg[rdeg == 0])
+            mism = np.asarray(gnbr).reshape(w.n, w.L)[rows] != rnbr
+            exempt = rmargin < NEIGHBOUR_BAND
+            agreement["rows"] += int(len(rows))
+            agreement["samples"] += int(len(rows) * w.L)
+            agreement["degree_max_rel_err"] = max(agreement["degree_max_rel_err"], float(rel.max()))
+            agreement["neighbour_mismatches"] += int(mism.sum())
+            agreement["band_exempt"] += int((mism & exempt).sum())
+            agreement["non_exempt"] += int((mism & ~exempt).sum())
     return {"value": edges / dt, "unit": "sampled edges/s", "kernel_evals_per_s": evals / dt,
             "cores": oracle.num_threads(), "kind": "oracle", "seconds": dt,
             "sample": f"seeded rows of 8 seeded sets of the {len(sets)} ({', '.join(w.name for w, _ in data)}): "
-                      f"per row the full FP64 kernel row, the degree and L descents"}
+                      f"per row the full FP64 kernel row, the degree and L descents (with the split margins)",
+            "oracle_agreement": agreement}
 
 
 def main():
