@@ -331,6 +331,18 @@ def run_serving(args):
                 ready_sets.append((sid, sid_pool[sid]))
     wall = time.perf_counter() - t0
     stats = srv.stats()
+    # untimed: the sets the CPU baseline covers, built through the server with
+    # their workload seeds (precision alternating), for the oracle comparison
+    picked = {}
+    if not args.no_cpu_baseline:
+        for k, i in enumerate(batched_pick(len(pool))):
+            w = pool[i]
+            key = 2_000_000 + i
+            rid = srv.submit_build(key, Xp[i], w.gamma, w.L, w.philox_seed, ("bf16_split", "fp32")[k % 2])
+            while not any(r == rid for r, _ in srv.poll()):
+                pass
+            graph = srv.graph(key, w.n, w.L)
+            picked[i] = (graph[3].cpu().numpy(), graph[4].cpu().numpy())
     srv.close()
     ctx.close()
     lat = np.array([(done_at[r] - arrival[r]) * 1e3 for r in done_at])
@@ -367,7 +379,7 @@ def run_serving(args):
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(pool, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_batched(pool, args.cpu_seconds, picked)
     print(json.dumps(out), flush=True)
 
 
