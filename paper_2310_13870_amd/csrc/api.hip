@@ -420,17 +420,18 @@ static SortBufs sort_bufs(fsg_ctx* ctx, int64_t n, size_t key_bytes, fsg_status*
 }
 
 // Orders the samples by their node at `level` (2^level nodes); inactive
-// samples last.  Returns sorted sample ids and node starts.
+// samples last.  Returns sorted sample ids and node starts, in the given
+// buffers ([ns], [2^level + 1]) or else in the workspace.
 static fsg_status group_by_node(fsg_ctx* ctx, const int32_t* node, int64_t ns, int level, int32_t** sorted,
-                                int32_t** starts) {
+                                int32_t** starts, int32_t* vals_out = nullptr, int32_t* starts_out = nullptr) {
     fsg_status st;
     uint32_t* keys;
-    int32_t* vals;
-    int32_t* start;
+    int32_t* vals = vals_out;
+    int32_t* start = starts_out;
     const int64_t n_nodes = (int64_t)1 << level;
     if ((st = ws(ctx, "grp_keys", (size_t)ns, &keys)) != FSG_OK) return st;
-    if ((st = ws(ctx, "grp_vals", (size_t)ns, &vals)) != FSG_OK) return st;
-    if ((st = ws(ctx, "grp_starts", (size_t)n_nodes + 1, &start)) != FSG_OK) return st;
+    if (!vals && (st = ws(ctx, "grp_vals", (size_t)ns, &vals)) != FSG_OK) return st;
+    if (!start && (st = ws(ctx, "grp_starts", (size_t)n_nodes + 1, &start)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, ns, sizeof(uint32_t), &st);
     if (st != FSG_OK) return st;
     StageTimer t(ctx, "group");
@@ -603,6 +604,36 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
 
 // leaf stage: nodes of at most kLeafMax points resolved with exact kernel
 // values; the degrees come from here too when there was no binned pass
+// leaf-stage arguments of sampler S (node boundaries bnd at its leaf level,
+// samples grouped by node, work items)
+static LeafArgs leaf_args(const Sampler& S, const int32_t* bnd, const int32_t* sorted, const int32_t* starts,
+                          const int32_t* items, const int32_t* n_items) {
+    LeafArgs la;
+    std::memset(&la, 0, sizeof(la));
+    const fsg_points* X = S.X;
+    la.X = X->X;
+    la.norm = X->norm;
+    la.n = X->n;
+    la.d = X->d;
+    la.bounds = bnd;
+    la.level = S.plan.leaf_level;
+    la.s = S.gamma * 1.442695040888963407359924681001892137;
+    la.L = S.L;
+    la.seed = S.seed;
+    la.sorted_samples = sorted;
+    la.node_start = starts;
+    la.items = items;
+    la.n_items = n_items;
+    la.nbr = S.nbr;
+    la.margin = S.margin;
+    la.uleaf = S.plan.passes.empty() ? nullptr : S.uleaf;
+    la.n_uleaf = S.plan.passes.empty() ? 0 : S.n_uleaf;
+    return la;
+}
+
+// work items of a leaf stage over 2^level nodes: at most this many
+static int64_t leaf_max_items(int64_t ns, int level) { return ns / 64 + ((int64_t)1 << level) + 1; }
+
 static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
     fsg_points* X = S.X;
     const int64_t ns = S.ns;
@@ -615,7 +646,7 @@ static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
     int32_t* items;
     int32_t* n_items;
     int64_t* scratch;
-    const int64_t max_items = ns / 64 + n_nodes + 1;
+    const int64_t max_items = leaf_max_items(ns, S.plan.leaf_level);
     if ((st = ws(ctx, "leaf_items", (size_t)(2 * max_items), &items)) != FSG_OK) return st;
     if ((st = ws(ctx, "leaf_nitems", 1, &n_items)) != FSG_OK) return st;
     if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) != FSG_OK)
@@ -623,25 +654,7 @@ static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
     {
         StageTimer t(ctx, "leaf");
         FSG_HIP(ctx, launch_leaf_items(starts, n_nodes, scratch, items, n_items, ctx->stream));
-        LeafArgs la;
-        std::memset(&la, 0, sizeof(la));
-        la.X = X->X;
-        la.norm = X->norm;
-        la.n = X->n;
-        la.d = X->d;
-        la.bounds = bnd;
-        la.level = S.plan.leaf_level;
-        la.s = S.gamma * 1.442695040888963407359924681001892137;
-        la.L = S.L;
-        la.seed = S.seed;
-        la.sorted_samples = sorted;
-        la.node_start = starts;
-        la.items = items;
-        la.n_items = n_items;
-        la.nbr = S.nbr;
-        la.margin = S.margin;
-        la.uleaf = S.plan.passes.empty() ? nullptr : S.uleaf;
-        la.n_uleaf = S.plan.passes.empty() ? 0 : S.n_uleaf;
+        const LeafArgs la = leaf_args(S, bnd, sorted, starts, items, n_items);
         FSG_HIP(ctx, launch_leaf(la, max_items, ctx->num_cus, ctx->stream));
         FSG_HIP(ctx, launch_finish_inactive(S.node, ns, S.nbr, ctx->stream));
     }
@@ -731,6 +744,22 @@ static void free_tables(BatchTables* T) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// device tables of a batched leaf stage: the jobs' leaf arguments and their
+// work-slot offsets
+struct LeafTables {
+    std::vector<fsg_job*> jobs;
+    void* dev = nullptr;   // LeafArgs[G], int64[G+1]
+    void* host = nullptr;  // pinned staging of the same layout
+    LeafArgs a0;           // launch arguments (tables bound)
+    int64_t slots = 0;
+};
+
+static void free_leaf_tables(LeafTables* T) {
+    if (T->dev) (void)hipFree(T->dev);
+    if (T->host) (void)hipHostFree(T->host);
+    delete T;
+}
+
 }  // namespace fsg
 
 struct fsg_job {
@@ -742,6 +771,12 @@ struct fsg_job {
     double* M = nullptr;       // root-pass bins [n][2^root_D]
     uint16_t* mask = nullptr;  // precision mode: keep masks of the root pass
     float* ntheta = nullptr;   // precision mode: keep-thresholds of the root pass
+    // leaf stage: samples grouped by node [ns], node starts [2^leaf_level + 1],
+    // work items [2 leaf_max_items] followed by their count
+    int32_t* leaf_sorted = nullptr;
+    int32_t* leaf_starts = nullptr;
+    int32_t* leaf_items = nullptr;
+    int64_t leaf_items_max = 0;
     std::vector<void*> owned;  // device blocks from the context's pool
 };
 
@@ -770,6 +805,16 @@ static void batch_cache_drop(fsg_ctx* ctx, const fsg_job* j) {
             (void)hipStreamSynchronize(ctx->stream);
             free_tables(c[i]);
             c.erase(c.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    auto& lc = ctx->leaf_cache;
+    for (size_t i = 0; i < lc.size();) {
+        if (std::find(lc[i]->jobs.begin(), lc[i]->jobs.end(), j) != lc[i]->jobs.end()) {
+            (void)hipStreamSynchronize(ctx->stream);
+            free_leaf_tables(lc[i]);
+            lc.erase(lc.begin() + i);
         } else {
             ++i;
         }
@@ -1007,6 +1052,87 @@ static fsg_status batch_root(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
     return batch_root_launch(ctx, T, true);
 }
 
+// the device tables of a group's leaf stage (built on its first use, cached)
+static fsg_status leaf_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, LeafTables** out) {
+    for (LeafTables* T : ctx->leaf_cache)
+        if (T->jobs == g) {
+            *out = T;
+            return FSG_OK;
+        }
+    const int32_t G = (int32_t)g.size();
+    const size_t o_off = align256(G * sizeof(LeafArgs));
+    const size_t bytes = align256(o_off + (G + 1) * sizeof(int64_t));
+    LeafTables* T = new LeafTables();
+    T->jobs = g;
+    auto fail = [&](fsg_status s) {
+        free_leaf_tables(T);
+        return s;
+    };
+    if (hipMalloc(&T->dev, bytes) != hipSuccess || hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(ctx, FSG_E_NOMEM, "allocation of leaf tables failed"));
+    }
+    char* h = (char*)T->host;
+    std::memset(h, 0, bytes);
+    LeafArgs* hargs = (LeafArgs*)h;
+    int64_t* hoff = (int64_t*)(h + o_off);
+    int64_t total = 0;
+    fsg_status st;
+    for (int32_t i = 0; i < G; ++i) {
+        const fsg_job* j = g[i];
+        const int32_t* bnd = level_bounds(j->S.X, j->S.plan.leaf_level, &st);
+        if (!bnd) return fail(st);
+        hargs[i] = leaf_args(j->S, bnd, j->leaf_sorted, j->leaf_starts, j->leaf_items,
+                             j->leaf_items + 2 * j->leaf_items_max);
+        hoff[i] = total;
+        total += j->leaf_items_max;
+    }
+    hoff[G] = total;
+    T->slots = total;
+    const hipError_t e = hipMemcpyAsync(T->dev, T->host, bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(ctx, FSG_E_DEVICE, std::string("leaf tables: ") + hipGetErrorString(e)));
+    }
+    T->a0 = hargs[0];
+    T->a0.jobs = (const LeafArgs*)T->dev;
+    T->a0.job_slot_off = (const int64_t*)((char*)T->dev + o_off);
+    T->a0.n_jobs = G;
+    ctx->leaf_cache.push_back(T);
+    *out = T;
+    return FSG_OK;
+}
+
+// Leaf stages of a group of jobs (one class of d) in one launch: each job's
+// samples are grouped by node into its own buffers and its work items listed,
+// then one kernel walks the items of all of them.  Per item the work is that
+// of the single-set leaf stage, so the results are the same bit for bit.
+static fsg_status batch_leaf(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
+    fsg_status st;
+    for (fsg_job* j : g) {
+        const Sampler& S = j->S;
+        const int lv = S.plan.leaf_level;
+        const int64_t n_nodes = (int64_t)1 << lv;
+        int32_t *sorted, *starts;
+        if ((st = group_by_node(ctx, S.node, S.ns, lv, &sorted, &starts, j->leaf_sorted, j->leaf_starts)) != FSG_OK)
+            return st;
+        if (!level_bounds(S.X, lv, &st)) return st;
+        int64_t* scratch;
+        if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
+            FSG_OK)
+            return st;
+        StageTimer t(ctx, "leaf");
+        FSG_HIP(ctx, launch_leaf_items(j->leaf_starts, n_nodes, scratch, j->leaf_items,
+                                       j->leaf_items + 2 * j->leaf_items_max, ctx->stream));
+    }
+    LeafTables* T;
+    if ((st = leaf_tables(ctx, g, &T)) != FSG_OK) return st;
+    StageTimer t(ctx, "leaf");
+    FSG_HIP(ctx, launch_leaf(T->a0, T->slots, ctx->num_cus, ctx->stream));
+    for (fsg_job* j : g) FSG_HIP(ctx, launch_finish_inactive(j->S.node, j->S.ns, j->S.nbr, ctx->stream));
+    return FSG_OK;
+}
+
 }  // namespace fsg
 
 using namespace fsg;
@@ -1070,6 +1196,8 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
     }
     for (BatchTables* T : ctx->batch_cache) free_tables(T);
     ctx->batch_cache.clear();
+    for (LeafTables* T : ctx->leaf_cache) free_leaf_tables(T);
+    ctx->leaf_cache.clear();
     // live jobs are detached; their buffers are freed here
     for (fsg_job* j : ctx->jobs) {
         for (void* v : j->owned) {
@@ -1435,6 +1563,9 @@ void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, f
     *resident = pts + result + (uint64_t)n * (uint64_t)d * 4;
     const Plan plan = make_plan(n, L, ctx->budget, ctx->max_levels_per_pass);
     uint64_t job = ns * 8 + (uint64_t)n * 8;
+    // the leaf stage's grouped samples, node starts and work items
+    job += ns * 4 + (((uint64_t)1 << plan.leaf_level) + 1) * 4 +
+           (2 * (uint64_t)leaf_max_items((int64_t)ns, plan.leaf_level) + 1) * 4;
     if (!plan.passes.empty()) {
         const int D = plan.passes[0].second;
         const uint64_t n_uleaf = (uint64_t)(tree_depth(n) - plan.leaf_level);
@@ -1479,6 +1610,14 @@ fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int3
     if (!(j->S.deg = (double*)job_alloc(j, n * sizeof(double), &st))) return fail(st);
     if (j->S.n_uleaf > 0 && !(j->S.uleaf = (double*)job_alloc(j, ns * j->S.n_uleaf * sizeof(double), &st)))
         return fail(st);
+    {
+        const int lv = j->S.plan.leaf_level;
+        j->leaf_items_max = leaf_max_items(ns, lv);
+        if (!(j->leaf_sorted = (int32_t*)job_alloc(j, (size_t)ns * sizeof(int32_t), &st))) return fail(st);
+        if (!(j->leaf_starts = (int32_t*)job_alloc(j, (((size_t)1 << lv) + 1) * sizeof(int32_t), &st))) return fail(st);
+        if (!(j->leaf_items = (int32_t*)job_alloc(j, (size_t)(2 * j->leaf_items_max + 1) * sizeof(int32_t), &st)))
+            return fail(st);
+    }
     if (!j->S.plan.passes.empty()) {
         j->root_D = j->S.plan.passes[0].second;
         if (!(j->M = (double*)job_alloc(j, (size_t)(n << j->root_D) * sizeof(double), &st))) return fail(st);
@@ -1518,6 +1657,8 @@ fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, in
     }
     for (auto& kv : groups)
         if ((st = batch_root(ctx, kv.second)) != FSG_OK) return st;
+    // leaf stages: grouped by class of d, one launch per group
+    std::map<int, std::vector<fsg_job*>> leaf_groups;
     for (int32_t i = 0; i < n_jobs; ++i) {
         fsg_job* j = jobs[i];
         if (j->stage >= j->n_stages) continue;
@@ -1527,10 +1668,18 @@ fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, in
         } else if (j->stage < P) {
             if ((st = stage_pass(ctx, j->S, (size_t)j->stage)) != FSG_OK) return st;
         } else {
-            if ((st = stage_leaf(ctx, j->S)) != FSG_OK) return st;
-            if (P == 0 && (st = fsg_degrees(ctx, j->S.X, j->S.gamma, j->S.deg)) != FSG_OK) return st;
+            leaf_groups[leaf_class(j->S.X->d)].push_back(j);
+            continue;
         }
         ++j->stage;
+    }
+    for (auto& kv : leaf_groups) {
+        if ((st = batch_leaf(ctx, kv.second)) != FSG_OK) return st;
+        for (fsg_job* j : kv.second) {
+            if (j->S.plan.passes.empty() && (st = fsg_degrees(ctx, j->S.X, j->S.gamma, j->S.deg)) != FSG_OK)
+                return st;
+            ++j->stage;
+        }
     }
     int32_t done = 0;
     for (int32_t i = 0; i < n_jobs; ++i) done += (jobs[i]->stage >= jobs[i]->n_stages) ? 1 : 0;

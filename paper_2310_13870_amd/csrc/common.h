@@ -134,6 +134,7 @@ struct Arena;
 
 namespace fsg {
 struct BatchTables;  // device tables of a batched root pass (api.hip)
+struct LeafTables;   // device tables of a batched leaf stage (api.hip)
 }
 struct fsg_server;
 
@@ -169,6 +170,7 @@ struct fsg_ctx {
     bool autotune = true;
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     std::vector<fsg::BatchTables*> batch_cache;
+    std::vector<fsg::LeafTables*> leaf_cache;
     // live batch jobs; their buffers are freed and they are detached when the
     // context is destroyed
     std::set<fsg_job*> jobs;
@@ -321,8 +323,16 @@ struct LeafArgs {
     float* margin;
     const double* uleaf;            // precomputed uniforms of the leaf levels (NULL: computed here)
     int32_t n_uleaf;
+    // several point sets in one launch (jobs != NULL): job k's items take the
+    // work slots [job_slot_off[k], job_slot_off[k+1]) (at most its item bound;
+    // slots past its *n_items are idle), its arguments jobs[k]
+    const LeafArgs* jobs;
+    const int64_t* job_slot_off;
+    int32_t n_jobs;
 };
+// max_items: the item bound of one set, or the slots of all jobs
 hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st);
+int leaf_class(int32_t d);  // the class of d a leaf launch is built for (2, 4, ..., 128)
 
 // Samples: sort ids by node; inactive samples (node < 0) go last.
 hipError_t launch_init_samples(int64_t n_samples, int32_t* node, float* margin, hipStream_t st);

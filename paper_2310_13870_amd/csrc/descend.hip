@@ -189,8 +189,8 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
 // Leaf stage: each lane keeps its sample's (<= 64) kernel values
 // in registers; the child masses of every level are summed with static
 // predicates, so the descent has no dependent memory chains.
-template <int DMAX>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void leaf_reg_kernel(LeafArgs a) {
+template <int DMAX, bool MULTI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void leaf_reg_kernel(LeafArgs a0) {
     // d <= 32: the query row in registers, node points in LDS row by row, four
     // points at a time.  d > 32: features outer, the 64 points' cross terms in
     // registers, node points staged transposed (feature-major) in FP32 (the
@@ -204,9 +204,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
     __shared__ double exp_tab[256];
     load_exp2_table(exp_tab);
     const int lane = threadIdx.x;
-    const int32_t n_items = *a.n_items;
-    const double s256 = 256.0 * a.s, two_s = 2.0 * s256;
-    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t n_slots = MULTI ? a0.job_slot_off[a0.n_jobs] : (int64_t)*a0.n_items;
+    for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+        int64_t it = slot;
+        int32_t job = 0;
+        if (MULTI) {  // the job owning the slot (binary search, uniform)
+            int32_t lo_j = 0, hi_j = a0.n_jobs;
+            while (hi_j - lo_j > 1) {
+                const int32_t mid_j = (lo_j + hi_j) >> 1;
+                if (a0.job_slot_off[mid_j] <= slot) lo_j = mid_j; else hi_j = mid_j;
+            }
+            job = lo_j;
+            it = slot - a0.job_slot_off[job];
+        }
+        const LeafArgs& a = MULTI ? a0.jobs[job] : a0;
+        if (MULTI && it >= (int64_t)*a.n_items) continue;  // an idle slot (uniform: no barrier is skipped alone)
+        const double s256 = 256.0 * a.s, two_s = 2.0 * s256;
         const int32_t v = a.items[2 * it], p0 = a.items[2 * it + 1];
         const int32_t p1 = a.node_start[v + 1];
         const int32_t lo = a.bounds[v];
@@ -318,20 +331,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
     }
 }
 
+template <int DMAX>
+static void launch_leaf_t(const LeafArgs& a, int64_t blocks, hipStream_t st) {
+    if (a.jobs)
+        leaf_reg_kernel<DMAX, true><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else
+        leaf_reg_kernel<DMAX, false><<<(unsigned)blocks, 64, 0, st>>>(a);
+}
+
+// a.d is the largest d of the launch (every job of a multi-job launch is in
+// the same class of d)
 hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st) {
     int64_t blocks = max_items;
     const int64_t cap = (int64_t)num_cus * 32;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    if (a.d <= 2) leaf_reg_kernel<2><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 4) leaf_reg_kernel<4><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 8) leaf_reg_kernel<8><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 16) leaf_reg_kernel<16><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 32) leaf_reg_kernel<32><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 64) leaf_reg_kernel<64><<<(unsigned)blocks, 64, 0, st>>>(a);
-    else if (a.d <= 128) leaf_reg_kernel<128><<<(unsigned)blocks, 64, 0, st>>>(a);
+    if (a.d <= 2) launch_leaf_t<2>(a, blocks, st);
+    else if (a.d <= 4) launch_leaf_t<4>(a, blocks, st);
+    else if (a.d <= 8) launch_leaf_t<8>(a, blocks, st);
+    else if (a.d <= 16) launch_leaf_t<16>(a, blocks, st);
+    else if (a.d <= 32) launch_leaf_t<32>(a, blocks, st);
+    else if (a.d <= 64) launch_leaf_t<64>(a, blocks, st);
+    else if (a.d <= 128) launch_leaf_t<128>(a, blocks, st);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+int leaf_class(int32_t d) {
+    int c = 2;
+    while (c < d) c *= 2;
+    return c < 2 ? 2 : c;
 }
 
 // ---------------------------------------------------------------------------
