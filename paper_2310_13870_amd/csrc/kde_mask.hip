@@ -168,37 +168,61 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
                 }
             }
         };
-        // Software pipeline over the blocks: the matrix ops of block b + 1
-        // are issued before the keep bits of block b are taken, while the
-        // operands of a later block load: block b + 3 with three operand
-        // buffers in turn where one wave runs per SIMD (a load has two
-        // blocks' worth of matrix work to arrive), block b + 2 with two where
-        // two waves share the registers.  Two accumulator sets.  Past the end
-        // the last block is loaded and multiplied again (in bounds, results
-        // unused), so that every step issues the same instructions.
+        // Software pipeline over the blocks.  Past the end the last block is
+        // loaded and multiplied again (in bounds, results unused), so that
+        // every step issues the same instructions.
         auto clampb = [&](int32_t b) { return b < be ? b : be - 1; };
-        constexpr int AHEAD = (WAVES == 1) ? 3 : 2;
-        bf16x8_t x0[KB], x1[KB], x2[KB];
-        float a0, a1, a2;
+        bf16x8_t x0[KB], x1[KB], x2[KB], x3[KB];
+        float a0, a1, a2, a3;
         float4_t c0[QB], c1[QB];
         float f0, f1;  // -|x|^2/2 of the blocks whose keep bits are taken next
         int32_t blk = bb;
-        // one step: load block blk + AHEAD into the free buffer xl, multiply
-        // block blk + 1 (buffer xm) into cm, take the keep bits of block blk (cf)
-        auto step = [&](bf16x8_t (&xl)[KB], float& al, const bf16x8_t (&xm)[KB], float am, float4_t (&cm)[QB],
-                        float& fm, const float4_t (&cf)[QB], float ff) {
-            load(xl, al, clampb(blk + AHEAD));
-            mma(cm, xm);
-            fm = am;
-            finish(cf, ff, blk);
-        };
-        load(x0, a0, bb);
-        load(x1, a1, clampb(bb + 1));
-        if constexpr (AHEAD == 3) load(x2, a2, clampb(bb + 2));
-        mma(c0, x0);
-        f0 = a0;
-        for (;;) {
-            if constexpr (AHEAD == 3) {
+        if constexpr (WAVES == 2) {
+            // Two waves per SIMD: one accumulator set, whose keep bits are
+            // taken right after its matrix ops (the other wave's matrix ops
+            // fill the wait), which leaves the registers for four operand
+            // buffers: the loads run four blocks ahead.
+            load(x0, a0, bb);
+            load(x1, a1, clampb(bb + 1));
+            load(x2, a2, clampb(bb + 2));
+            load(x3, a3, clampb(bb + 3));
+            auto step = [&](bf16x8_t (&xb)[KB], float& ab) {
+                mma(c0, xb);
+                f0 = ab;
+                load(xb, ab, clampb(blk + 4));
+                finish(c0, f0, blk);
+            };
+            for (;;) {
+                step(x0, a0);
+                if (++blk >= be) break;
+                step(x1, a1);
+                if (++blk >= be) break;
+                step(x2, a2);
+                if (++blk >= be) break;
+                step(x3, a3);
+                if (++blk >= be) break;
+            }
+        } else {
+            // One wave per SIMD: the matrix ops of block b + 1 are issued
+            // before the keep bits of block b are taken (two accumulator
+            // sets), and the operands of block b + 3 load meanwhile (three
+            // buffers in turn: a load has two blocks' worth of matrix work to
+            // arrive; four buffers were slower).
+            // one step: load block blk + 3 into the free buffer xl, multiply
+            // block blk + 1 (buffer xm) into cm, take the keep bits of block blk (cf)
+            auto step = [&](bf16x8_t (&xl)[KB], float& al, const bf16x8_t (&xm)[KB], float am, float4_t (&cm)[QB],
+                            float& fm, const float4_t (&cf)[QB], float ff) {
+                load(xl, al, clampb(blk + 3));
+                mma(cm, xm);
+                fm = am;
+                finish(cf, ff, blk);
+            };
+            load(x0, a0, bb);
+            load(x1, a1, clampb(bb + 1));
+            load(x2, a2, clampb(bb + 2));
+            mma(c0, x0);
+            f0 = a0;
+            for (;;) {
                 step(x0, a0, x1, a1, c1, f1, c0, f0);
                 if (++blk >= be) break;
                 step(x1, a1, x2, a2, c0, f0, c1, f1);
@@ -210,11 +234,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
                 step(x1, a1, x2, a2, c1, f1, c0, f0);
                 if (++blk >= be) break;
                 step(x2, a2, x0, a0, c0, f0, c1, f1);
-                if (++blk >= be) break;
-            } else {
-                step(x0, a0, x1, a1, c1, f1, c0, f0);
-                if (++blk >= be) break;
-                step(x1, a1, x0, a0, c0, f0, c1, f1);
                 if (++blk >= be) break;
             }
         }
