@@ -16,6 +16,19 @@
 
 namespace fsg {
 
+// The descent rule of Algorithm 1 at one node: left iff u*(mL+mR) < mL, never
+// into a child of zero mass.  Returns true for left.  With want_margin (a
+// uniform flag: the caller keeps margins) *mg becomes min(*mg, |u - mL/t|);
+// without it the division is skipped.
+__device__ __forceinline__ bool choose_left(double u, double mL, double mR, bool want_margin, float* mg) {
+    const double t = mL + mR;
+    bool left = (u * t < mL);
+    if (left && mL == 0.0) left = false;
+    if (!left && mR == 0.0) left = true;
+    if (want_margin) *mg = fminf(*mg, (float)__builtin_fabs(u - mL / t));
+    return left;
+}
+
 // Root pass: one block of 256 threads per point.  LDS holds the sum tree
 // (2^(D+1) doubles) and the Philox blocks of up to 64 of the point's samples.
 constexpr int kDescThreads = 256;
@@ -96,9 +109,7 @@ __global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a, 
                             mL = M[2 * m];  // the children are bins
                             mR = M[2 * m + 1];
                         }
-                        double margin;
-                        const bool left = choose_left(u, mL, mR, &margin);
-                        mg = fminf(mg, (float)margin);
+                        const bool left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
                         m = 2 * m + (left ? 0 : 1);
                     }
                     a.node[smp] = m;
@@ -145,9 +156,7 @@ __global__ __launch_bounds__(256) void descend_entries_kernel(DescArgs a) {
             mL += (b >= lo && b < lo + w) ? bins[b] : 0.0;
             mR += (b >= lo + w && b < lo + 2 * w) ? bins[b] : 0.0;
         }
-        double margin;
-        const bool left = choose_left(uni.at(a.start_level + t), mL, mR, &margin);
-        mg = fminf(mg, (float)margin);
+        const bool left = choose_left(uni.at(a.start_level + t), mL, mR, a.margin != nullptr, &mg);
         m = 2 * m + (left ? 0 : 1);
     }
     a.node[smp] = (v << D) + m;
@@ -318,9 +327,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
                         mR += (in_node && !left) ? kv[j] : 0.0;
                     }
                     const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
-                    double margin;
-                    const bool go_left = choose_left(u, mL, mR, &margin);
-                    mg = fminf(mg, (float)margin);
+                    const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
                     if (go_left) nbd = mid; else na = mid;
                     ++level;
                 }

@@ -132,17 +132,6 @@ struct SampleUniforms {
     }
 };
 
-// The descent rule of Algorithm 1 at one node: left iff u*(mL+mR) < mL, never
-// into a child of zero mass.  Returns true for left; *margin = |u - mL/t|.
-__device__ __forceinline__ bool choose_left(double u, double mL, double mR, double* margin) {
-    const double t = mL + mR;
-    bool left = (u * t < mL);
-    if (left && mL == 0.0) left = false;
-    if (!left && mR == 0.0) left = true;
-    *margin = __builtin_fabs(u - mL / t);
-    return left;
-}
-
 // A value the whole wave agrees on, kept in a scalar register: loop bounds
 // and bin indices derived from LDS or vector loads would otherwise be
 // treated as per-lane values.
