@@ -54,17 +54,28 @@ constexpr double tab_coef(int k) {
     return v;
 }
 
-__device__ __forceinline__ double exp2_256_tab(double a, const double* tab) {
+// The two halves of exp2_256_tab, for callers that issue several table reads
+// before the first result is needed: the split gives m = rint(a) (a clamped)
+// and r = a - m; the join takes t = tab[m & 255].
+__device__ __forceinline__ int32_t exp2_256_split(double a, double* r) {
     a = __builtin_fmax(a, -512000.0);
     const double m = __builtin_rint(a);
-    const double r = a - m;  // exact: |r| <= 1/2
-    const int32_t mi = (int32_t)m;
-    const double t = tab[mi & 255];
+    *r = a - m;  // exact: |r| <= 1/2
+    return (int32_t)m;
+}
+
+__device__ __forceinline__ double exp2_256_join(double t, double r, int32_t mi) {
     double q = __builtin_fma(tab_coef(4), r, tab_coef(3));
     q = __builtin_fma(q, r, tab_coef(2));
     q = __builtin_fma(q, r, tab_coef(1));
     q *= r;
     return __builtin_ldexp(__builtin_fma(t, q, t), mi >> 8);
+}
+
+__device__ __forceinline__ double exp2_256_tab(double a, const double* tab) {
+    double r;
+    const int32_t mi = exp2_256_split(a, &r);
+    return exp2_256_join(tab[mi & 255], r, mi);
 }
 
 // ---------------------------------------------------------------------------

@@ -374,17 +374,33 @@ struct BinAccumulator1 {
 // |q|^2, neg_s = -256 s, two_s = 512 s, s = gamma log2 e), a power of two that
 // leaves every rounding as it is, and exp2_256_tab evaluates them; without it
 // (tab = nullptr, a compile-time choice of the caller) hq = -s |q|^2, neg_s =
-// -s, two_s = 2 s and exp2_fp64 does.  The self compare runs only when a query
-// of the block has its own index in [lo_col, hi_col].
-template <bool TAB>
+// -s, two_s = 2 s and exp2_fp64 does.  AHEAD (table form only) issues the
+// four table reads before the first is used; it pays where the kernel's other
+// vector work does not hide the LDS latency (the exact recompute), and the
+// values are the same either way.  The self compare runs only when a query of
+// the block has its own index in [lo_col, hi_col].
+template <bool TAB, bool AHEAD>
 __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq, const double (&xn)[4], double neg_s,
                                                    double two_s, const int32_t (&jj)[4], int32_t selfv, int32_t smin,
                                                    int32_t smax, int32_t lo_col, int32_t hi_col, const double* tab,
                                                    double (&kv)[4]) {
+    if constexpr (TAB && AHEAD) {
+        // the four table reads are issued before the first is used
+        double r[4], t[4];
+        int32_t mi[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double z = __builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq));
-        kv[i] = TAB ? exp2_256_tab(z, tab) : exp2_fp64(z);
+        for (int i = 0; i < 4; ++i) {
+            mi[i] = exp2_256_split(__builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq)), &r[i]);
+            t[i] = tab[mi[i] & 255];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) kv[i] = exp2_256_join(t[i], r[i], mi[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double z = __builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq));
+            kv[i] = TAB ? exp2_256_tab(z, tab) : exp2_fp64(z);
+        }
     }
     if (smax >= lo_col && smin <= hi_col && __ballot(selfv >= lo_col && selfv <= hi_col) != 0) {
 #pragma unroll
@@ -394,7 +410,7 @@ __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq
 }
 
 // The FP64 epilogue of all query blocks against one 16-column block.
-template <int RQ, bool TAB>
+template <int RQ, bool TAB, bool AHEAD = false>
 __device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const double (&hq)[RQ], const double (&xn)[4],
                                              double neg_s, double two_s, const int32_t (&jj)[4],
                                              const int32_t (&selfv)[RQ], const int32_t (&smin)[RQ],
@@ -402,7 +418,7 @@ __device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const dou
                                              const double* tab, double (&kv)[RQ][4]) {
 #pragma unroll
     for (int qb = 0; qb < RQ; ++qb)
-        exact_values_block<TAB>(c[qb], hq[qb], xn, neg_s, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col, hi_col,
+        exact_values_block<TAB, AHEAD>(c[qb], hq[qb], xn, neg_s, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col, hi_col,
                                 tab, kv[qb]);
 }
 

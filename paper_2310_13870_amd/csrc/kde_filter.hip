@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, true>(c, hq, g.xn, -s256, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
+            exact_values<RQ, true, true>(c, hq, g.xn, -s256, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
             bins.add(kv, g.jj, g.last);
         };
 
