@@ -30,7 +30,7 @@ __device__ __forceinline__ bool choose_left(double u, double mL, double mR, bool
 }
 
 // Root pass: one block of 256 threads per point.  LDS holds the sum tree
-// (2^(D+1) doubles) and the Philox blocks of up to 64 of the point's samples.
+// (2^D doubles) and the Philox blocks of up to 64 of the point's samples.
 constexpr int kDescThreads = 256;
 constexpr int kDescChunk = 64;
 
@@ -171,7 +171,10 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
         if (a.D < 1 || a.D > 11) return hipErrorInvalidValue;  // the tree build assumes 2 <= 2^D <= 8 * 256
         const int32_t last_level = a.start_level + a.D - 1 + (a.uleaf != nullptr ? a.n_uleaf : 0);
         const int32_t n_groups = (last_level >> 2) - (a.start_level >> 2) + 1;
-        const size_t lds = sizeof(double) * ((size_t)1 << a.D) + sizeof(uint64_t) * 4 * kDescChunk * n_groups;
+        // Philox blocks of at most min(L, kDescChunk) samples at a time: at
+        // L = 17 and D = 11 this keeps a block at 19 KB (8 blocks per CU)
+        const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
+        const size_t lds = sizeof(double) * ((size_t)1 << a.D) + sizeof(uint64_t) * 4 * chunk * n_groups;
         int64_t blocks = a.n_entries;
         if (blocks > (1 << 20)) blocks = 1 << 20;
         descend_root_kernel<<<(unsigned)blocks, kDescThreads, lds, st>>>(a, n_groups);
