@@ -252,6 +252,27 @@ def test_multi_pass_plans(ctx, cap):
         ctx.set_levels_per_pass(0)
 
 
+@pytest.mark.parametrize("prec,cap", [("fp32", 0), ("fp32", 2), ("bf16_split", 0)])
+def test_margin_output_changes_nothing(ctx, prec, cap):
+    """The branch margins are an output only: with or without them, in the
+    root descent, the later passes and the leaf walk, every neighbour and
+    degree is the same."""
+    X = _mix(5000, 8, 322)
+    pts = fsg.Points(ctx, to_dev(X), prec)
+    try:
+        ctx.set_levels_per_pass(cap)
+        a = fsg.sample_edges(ctx, pts, 0.25, 7, 31, want_margin=True)
+        b = fsg.sample_edges(ctx, pts, 0.25, 7, 31, want_margin=False)
+    finally:
+        ctx.set_levels_per_pass(0)
+    assert b[2] is None and a[2] is not None
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # margins lie in [0, 1]; +inf where no branch was taken (isolated points)
+    m = a[2].cpu().numpy()
+    assert not np.any(np.isnan(m)) and np.all((m >= 0.0) & ((m <= 1.0) | np.isposinf(m)))
+    pts.close()
+
+
 # --------------------------------------------------------------------------
 # Precision mode (BF16 split filter + exact FP64 recompute)
 # --------------------------------------------------------------------------
