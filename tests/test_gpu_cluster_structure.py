@@ -1,0 +1,33 @@
+"""The graph built on the GPU is a cluster-preserving sparsifier of the fully
+connected kernel graph (the main result of Section 4, with the definition of
+Section 3): on a well-separated four-component mixture in R^4, in both
+precisions, each component's conductance and the (k+1)-th eigenvalue of the
+normalised Laplacian stay within small constant factors of the full graph's."""
+import numpy as np
+import pytest
+
+from tests.cluster_common import case, check_cluster_preserving, dense_from_csr, full_kernel
+from tests.gpu_common import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_13870_amd as fsg  # noqa: E402
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_gpu_graph_preserves_clusters(prec):
+    X, lab, gamma, L = case("k4-4d", 52)
+    n = X.shape[0]
+    ctx = fsg.Context(0)
+    try:
+        pts = fsg.Points(ctx, to_dev(X), prec)
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 9)
+        rp, col, w = fsg.build_csr(ctx, pts, gamma, L, nbr, deg)
+        rp, col, w = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy().astype(np.float64)
+        pts.close()
+    finally:
+        ctx.close()
+    assert len(col) <= 2 * n * L
+    W = dense_from_csr(n, rp, col, w)
+    assert np.array_equal(W, W.T)
+    say(f"{prec}: " + check_cluster_preserving(full_kernel(X, gamma), W, lab))
