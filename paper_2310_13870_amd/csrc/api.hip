@@ -286,11 +286,13 @@ static int32_t root_bins_per_item(const fsg_ctx* ctx, int64_t tiles, int32_t nbi
 // go round-robin to the waves, so the slowest wave does rounds x chunk
 // blocks plus a start-up per item (loading its query operands, worth about
 // kItemStart blocks): the chunk is chosen to make that smallest, which mostly
-// means a chunk count that just fills whole rounds.  The waves work on about
-// two chunks at a time, so a chunk's operands (16 x 64 x KB bytes per block)
-// are kept within about a third of an XCD's 4 MB L2.
+// means a chunk count that just fills whole rounds.  A chunk's operands
+// (16 x 64 x KB bytes per block) are capped at 3 MB: every item reloads its
+// query operands, so longer chunks cut that traffic (at n = 1e6, 1.5 MB chunks
+// were 4% slower), while at 6 MB the chunks the waves share no longer stay in
+// an XCD's 4 MB L2 (2% slower).
 static int64_t mask_chunk_blocks(int64_t n_blocks, int64_t n_groups, int64_t n_waves, int KB) {
-    constexpr int64_t kItemStart = 16, kChunkBytes = 1536 * 1024;
+    constexpr int64_t kItemStart = 16, kChunkBytes = 3072 * 1024;
     const int64_t max_bpc = std::max<int64_t>(32, std::min<int64_t>(1024, kChunkBytes / (16 * 64 * KB)));
     int64_t best_bpc = n_blocks, best = INT64_MAX;
     for (int64_t c = (n_blocks + max_bpc - 1) / max_bpc; c <= (n_blocks + 31) / 32; ++c) {
