@@ -4,14 +4,17 @@
 One step = the whole hot path over one synthetic point set already resident
 in HBM: prep (FP64 operand fragments and norms), every binned KDE pass and
 tree descent, the leaf stage, degrees, reweighting and the symmetric CSR
-(Algorithms 1 and 2).  Default workload: 100,000 points in R^32 from a seeded
-10-component Gaussian mixture, sigma 2, L 17.
+(Algorithms 1 and 2).  Default workload: 1,000,000 points in R^64 from a
+seeded 50-component Gaussian mixture, sigma 3, L 20, in the precision mode
+(BF16 split filter, exact FP64 recompute of kept pairs), with the plain path
+(every pair in FP64) timed beside it.
 
-Prints one JSON line: value = sampled edges/s (n*L sampled edges per step /
-step time), plus kernel evaluations/s, p50/p99 step latency, a live roofline
-figure for the dominant kernel (the binned KDE over all points, timed with
-HIP events on the stream it runs on) and the CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line: value = sampled edges/s of the precision mode (n*L
+sampled edges per step / step time), plus kernel evaluations/s, p50/p99 step
+latency, live roofline figures for the two KDE kernels (timed with HIP events
+on the stream they run on), the plain path's figures and their ratio, and the
+CPU oracle timed on the workload's stated seeded row subsample, with the
+agreement of both precisions' results on those rows.
 """
 import argparse
 import hashlib
@@ -26,7 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PRECISION_NOTE = {
-    "fp32": "plain: fp32 points, every pair on the fp64 matrix cores, fp64 exp",
+    "plain_fp64": "plain: fp32 points, every pair on the fp64 matrix cores, fp64 exp",
     "bf16_split": "bf16 hi/lo split filter on bf16 matrix cores (fp32 accumulate), kept pairs exact in fp64",
 }
 METRIC = "kernel evals/s + sampled edges/s, BF16-split vs FP32 plain; p50/p99 latency"
@@ -193,7 +196,7 @@ def run_batched(args):
         seq_ms = 1e3 * (time.perf_counter() - t0)
         tuned = {}
         for D4 in (2, 8, 32):
-            for prec in ("fp32", "bf16_split"):
+            for prec in ("plain_fp64", "bf16_split"):
                 t = ctx.tuned_shape(D4, prec)
                 if t:
                     tuned[f"D4={D4},{prec}"] = {"waves_per_cu": t[0], "cols_per_item": t[1]}
@@ -243,31 +246,6 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def serving_trace(seconds: float, rate: float, seed: int = 1004):
-    """Seeded open-loop trace: Poisson arrivals; 80% builds of a point set from
-    a pool of 64 (n log-uniform in [2e3, 2e5], d 64, 20 components, means
-    U[-10,10], std U[0.5,2], sigma 3, L ceil(log2 n)), 20% KDE queries of
-    10,000 points of the same mixture family; precision 50/50 per request."""
-    import numpy as np
-    import workloads
-    rng = np.random.default_rng(seed)
-    pool = []
-    for k in range(64):
-        n = int(round(math.exp(rng.uniform(math.log(2e3), math.log(2e5)))))
-        pool.append(workloads.Workload(f"pool{k}-n{n}", n, 64, 3.0, workloads.depth_of(n), seed * 1000 + k,
-                                       seed * 1000 + 500 + k, 20, (-10.0, 10.0), (0.5, 2.0)))
-    t, reqs = 0.0, []
-    while True:
-        t += rng.exponential(1.0 / rate)
-        if t >= seconds:
-            break
-        kind = "build" if rng.random() < 0.8 else "kde"
-        prec = "bf16_split" if rng.random() < 0.5 else "fp32"
-        reqs.append({"t": t, "kind": kind, "pool": int(rng.integers(len(pool))), "prec": prec,
-                     "seed": int(rng.integers(1 << 62)), "pick": float(rng.random())})
-    return pool, reqs
-
-
 def run_serving(args):
     """Open-loop serving run of the request loop (fsg_server_*): completion
     minus scheduled arrival per request, aggregate sampled edges/s."""
@@ -277,16 +255,15 @@ def run_serving(args):
     import paper_2310_13870_amd as fsg
     import workloads
 
-    pool, reqs = serving_trace(args.serve_seconds, 50.0)
+    pool, reqs = workloads.serving_trace(args.serve_seconds, 50.0)
     dev = torch.device("cuda:0")
     Xp = [torch.from_numpy(w.points()).to(dev) for w in pool]
-    Qp = [torch.from_numpy(workloads.mixture(10_000, w.d, w.n_comp, w.data_seed + 7, w.mean_range, w.std_range))
-          .to(dev) for w in pool]
+    Qp = [torch.from_numpy(workloads.serving_queries(w)).to(dev) for w in pool]
     torch.cuda.synchronize()
     ctx = fsg.Context(0)
     srv = fsg.Server(ctx, 200 << 30, 16)
     # warm the kernels and the workspace on one build of each precision
-    for k, prec in enumerate(("fp32", "bf16_split")):
+    for k, prec in enumerate(("plain_fp64", "bf16_split")):
         rid = srv.submit_build(1_000_000 + k, Xp[0], pool[0].gamma, pool[0].L, 1, prec)
         while not any(r == rid for r, _ in srv.poll()):
             pass
@@ -338,7 +315,7 @@ def run_serving(args):
         for k, i in enumerate(batched_pick(len(pool))):
             w = pool[i]
             key = 2_000_000 + i
-            rid = srv.submit_build(key, Xp[i], w.gamma, w.L, w.philox_seed, ("bf16_split", "fp32")[k % 2])
+            rid = srv.submit_build(key, Xp[i], w.gamma, w.L, w.philox_seed, ("bf16_split", "plain_fp64")[k % 2])
             while not any(r == rid for r, _ in srv.poll()):
                 pass
             graph = srv.graph(key, w.n, w.L)
@@ -365,7 +342,7 @@ def run_serving(args):
         "data": "synthetic",
         "config": {"workload": f"serving-50rps-{args.serve_seconds:g}s", "requests": len(reqs), "builds": n_builds,
                    "kde_requests": len(reqs) - n_builds, "hbm_budget_gb": 200, "max_active_builds": 16,
-                   "precision": "50/50 fp32 / bf16_split per request",
+                   "precision": "50/50 plain_fp64 / bf16_split per request",
                    "note": "one step = one request; value = sampled edges of completed builds / wall time of the trace"},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
@@ -443,16 +420,187 @@ def cpu_baseline_batched(sets, target_s: float, results=None):
             "oracle_agreement": agreement}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def agreement_of(rows, L, rnbr, rdeg, rmargin, gnbr, gdeg):
+    """Degree error and sampled-neighbour mismatches of GPU results on the
+    oracle's rows (mismatches split by the 1e-6 band of the oracle's path)."""
+    import numpy as np
+    n_rows = len(rows)
+    gdeg = np.asarray(gdeg)[rows]
+    rel = np.abs(gdeg - rdeg) / np.maximum(rdeg, 1e-300)
+    rel[rdeg == 0] = np.abs(gdeg[rdeg == 0])
+    gnbr = np.asarray(gnbr).reshape(-1, L)[rows]
+    mism = gnbr != rnbr
+    exempt = rmargin < NEIGHBOUR_BAND
+    return {"rows": int(n_rows), "samples": int(n_rows * L),
+            "degree_max_rel_err": float(rel.max()), "degree_p99_rel_err": float(np.percentile(rel, 99)),
+            "neighbour_mismatches": int(mism.sum()), "band_exempt": int((mism & exempt).sum()),
+            "non_exempt": int((mism & ~exempt).sum())}
+
+
+def cpu_baseline_rows(X, w, rows, results):
+    """The oracle on a fixed seeded row sample (the workload's stated
+    subsample), compared with the GPU results of every precision run."""
+    import oracle
+    n, L = w.n, w.L
+    t0 = time.perf_counter()
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, w.gamma, L, w.philox_seed, rows=rows, want_margin=True)
+    dt = time.perf_counter() - t0
+    m = len(rows)
+    return {
+        "value": m * L / dt,
+        "unit": "sampled edges/s",
+        "kernel_evals_per_s": m * (n - 1) / dt,
+        "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
+        "kind": "oracle",
+        "seconds": dt,
+        "sample": f"the workload's stated {m}-row seeded subsample (seed {w.extra.get('subsample_seed')}) of the "
+                  f"{n}-point set: per row the full FP64 kernel row ({n - 1} evaluations), the degree and L={L} "
+                  f"descents (with the split margins); reweighting/CSR (O(nL)) not included",
+        "oracle_agreement": {prec: agreement_of(rows, L, rnbr, rdeg, rmargin, g[0], g[1])
+                             for prec, g in results.items()},
+    }
+
+
+def run_leg(ctx, w, Xd, prec, steps, warmup, args):
+    """Time `steps` steps of one precision (after `warmup` untimed ones):
+    prep + fsg_sample_edges + fsg_build_csr on the resident point set."""
+    import numpy as np
+    import torch
+
+    import paper_2310_13870_amd as fsg
+    n, d, L = w.n, w.d, w.L
+    last = {}
+
+    def step():
+        pts = fsg.Points(ctx, Xd, prec)
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, L, w.philox_seed)
+        row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, L, nbr, deg)
+        pts.close()
+        last["nbr"], last["deg"] = nbr, deg
+        return col.numel()
+
+    for _ in range(warmup):
+        nnz = step()
+    torch.cuda.synchronize()
+    ctx.reset_profiling()
+    ctx.set_profiling(True)
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        nnz = step()
+        times.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ctx.set_profiling(False)
+    kept, scanned = ctx.filter_stats()
+    stages = {}
+    for name in ("prep", "kde_mask", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
+        ms, cnt = ctx.stage_time(name)
+        if cnt:
+            stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / steps,
+                            "ms_per_step": ms / steps}
+    ms_per_step = 1e3 * total / steps
+    kde = stages.get("kde_root")
+    mask = stages.get("kde_mask")
+    root_pairs = n * (n - 1)
+    # Kernel evaluations of the root pass (the KDE over all points; later
+    # passes and the leaf stage are reported as stage times): in the plain path
+    # every pair gets an FP64 kernel value; in the precision mode the BF16
+    # split scans (column, 64-query tile) pairs and only the kept ones get an
+    # FP64 kernel value, the others add 0 within the stated bound.
+    if prec == "plain_fp64":
+        evaluated = root_pairs
+        scanned_pairs = None
+        kde_ms = kde["ms_per_launch"] if kde else None
+    else:
+        evaluated = kept / steps * 64
+        scanned_pairs = scanned / steps * 64
+        kde_ms = (kde["ms_per_launch"] if kde else 0.0) + (mask["ms_per_launch"] if mask else 0.0)
+    roofline, second = None, None
+    if kde:
+        flops = 2.0 * d * evaluated
+        achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
+        kname = "kde_bins" if prec == "plain_fp64" else "kde_exact_kept"
+        label = ("binned KDE over all point pairs (FP64 matrix cores)" if prec == "plain_fp64"
+                 else "exact FP64 recompute of the kept pairs (FP64 matrix cores)")
+        roofline = {"bound": "mfma", "kernel": label, "kernel_symbol": kname + "_kernel",
+                    "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic_from_profile(kname, w.name),
+                    "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops,
+                    "flops_basis": "2d FP64 flops (cross term) per evaluated pair"}
+    if mask:
+        # algorithmic: the 2d flops of one cross term per scanned pair; issued:
+        # the split contraction over K = 3d (hi.hi + hi.lo + lo.hi)
+        flops = 2.0 * d * scanned_pairs
+        achieved = flops / (mask["ms_per_launch"] * 1e-3) / 1e12
+        dist = {"bound": "mfma", "kernel": "BF16 split keep-mask kernel (distance tiles)",
+                "kernel_symbol": "kde_keep_mask_kernel",
+                "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
+                "issued_achieved": 3.0 * achieved, "issued_frac": 3.0 * achieved / BF16_MFMA_PEAK_TFLOPS,
+                "traffic": traffic_from_profile("kde_keep_mask", w.name),
+                "ms_per_launch": mask["ms_per_launch"], "algorithmic_flops_per_launch": flops,
+                "flops_basis": "2d flops per scanned (query, column) pair; issued = 3x (K = 3d split contraction)"}
+        if roofline is None or mask["ms_per_launch"] > kde["ms_per_launch"]:
+            roofline, second = dist, roofline
+        else:
+            second = dist
+    times_ms = np.array(times) * 1e3
+    leg = {
+        "precision": PRECISION_NOTE[prec],
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "edges_per_s": n * L / (total / steps),
+        "p50_ms": float(np.percentile(times_ms, 50)),
+        "p99_ms": float(np.percentile(times_ms, 99)),
+        "distinct_edges": nnz // 2,
+        "kde": {"root_pairs": root_pairs, "root_pairs_scanned_bf16": scanned_pairs,
+                "root_pairs_evaluated_fp64": evaluated, "root_kde_ms": kde_ms,
+                "kernel_evals_per_s": evaluated / (kde["ms_per_launch"] * 1e-3) if kde else None,
+                "pairs_scanned_per_s": (scanned_pairs / (mask["ms_per_launch"] * 1e-3)) if mask else None,
+                "pairs_resolved_per_s": root_pairs / (kde_ms * 1e-3) if kde_ms else None},
+        "stages": stages,
+        "filter": ({"kept_column_tiles": kept, "scanned_column_tiles": scanned,
+                    "all_column_tiles": (n + 63) // 64 * n * steps,
+                    "kept_fraction": kept / scanned} if scanned else None),
+        "roofline": roofline,
+        "second_kernel_roofline": second,
+    }
+    result = (last["nbr"].cpu().numpy(), last["deg"].cpu().numpy())
+    last.clear()
+    return leg, result
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mix32-n100k",
-                    help="mix32-n100k (default), blobs2d-n1000, mix64-n1m, batched-256, or serving")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mix64-n1m",
+                    help="mix64-n1m (default), mix32-n100k, blobs2d-n1000, batched-256, or serving")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
-    ap.add_argument("--precision", default="bf16_split", choices=["fp32", "bf16_split"])
+    ap.add_argument("--precision", default="both", choices=["both", "plain_fp64", "bf16_split"],
+                    help="both (default): the precision mode is the headline, the plain path is timed beside it")
+    ap.add_argument("--plain-steps", type=int, default=0,
+                    help="timed steps of the plain path beside the precision mode (0: max(3, steps // 4))")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU oracle sample")
+    ap.add_argument("--oracle-rows", type=int, default=0,
+                    help="oracle rows (0: the workload's stated subsample, else a sample of --cpu-seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--levels-per-pass", type=int, default=0,
                     help="cap on the tree levels one binned pass resolves (0: the library's choice)")
@@ -465,12 +613,13 @@ def main():
               "(the design notes describe how the path would shard over query points).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2310_13870_amd as fsg
     import workloads
 
+    if args.workload in ("batched-256", "serving") and args.precision == "both":
+        args.precision = "bf16_split"
     if args.workload == "batched-256":
         run_batched(args)
         return
@@ -493,111 +642,62 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    last = {}  # the last step's neighbours and degrees (compared with the oracle after timing)
-
-    def step():
-        pts = fsg.Points(ctx, Xd, args.precision)
-        nbr, deg, _ = fsg.sample_edges(ctx, pts, w.gamma, L, w.philox_seed)
-        row_ptr, col, wt = fsg.build_csr(ctx, pts, w.gamma, L, nbr, deg)
-        pts.close()
-        last["nbr"], last["deg"] = nbr, deg
-        return col.numel()
-
-    for _ in range(args.warmup):
-        nnz = step()
-    torch.cuda.synchronize()
-    ctx.reset_profiling()
-    ctx.set_profiling(True)
-    times = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        nnz = step()
-        times.append(time.perf_counter() - t0)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ctx.set_profiling(False)
-    kept, scanned = ctx.filter_stats()
-    stages = {}
-    for name in ("prep", "kde_mask", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
-        ms, cnt = ctx.stage_time(name)
-        if cnt:
-            stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps}
-    ms_per_step = 1e3 * total / args.steps
-    edges_per_s = n * L / (total / args.steps)
-    # kernel evaluations per step: the root pass evaluates n(n-1) pairs; later
-    # passes and the leaf stage evaluate (samples x node size) pairs
-    import paper_2310_13870_amd  # noqa: F401
-    depth_leaf = 0
-    while math.ceil(n / 2 ** depth_leaf) > 64:
-        depth_leaf += 1
-    evals = n * (n - 1) + n * L * n / 2 ** depth_leaf if depth_leaf > 0 else n * L * n
-
-    kde = stages.get("kde_root")
-    mask = stages.get("kde_mask")
-    roofline, distance_tiles = None, None
-    if kde:
-        # FP64 matrix-core flops of the exact cross terms: all n(n-1) pairs in the
-        # plain mode, the kept (column, 64-query tile) pairs in the precision mode
-        if args.precision == "fp32":
-            pairs = n * (n - 1)
+    precs = ["bf16_split", "plain_fp64"] if args.precision == "both" else [args.precision]
+    legs, results = {}, {}
+    for k, prec in enumerate(precs):
+        if k == 0:
+            steps, warmup = args.steps, args.warmup
         else:
-            pairs = kept / args.steps * 64
-        flops = 2.0 * d * pairs
-        achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
-        traffic = traffic_from_profile("kde_bins" if args.precision == "fp32" else "kde_exact_kept", args.workload)
-        label = ("binned KDE over all point pairs (FP64 matrix cores)" if args.precision == "fp32"
-                 else "exact FP64 recompute of the kept pairs (FP64 matrix cores)")
-        roofline = {"bound": "mfma", "kernel": label,
-                    "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic,
-                    "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops}
-    if mask:
-        # the split contraction over K = 3d (hi.hi + hi.lo + lo.hi) for every
-        # (query, column) pair; zero padding of K is not counted
-        flops = 2.0 * 3 * d * n * n
-        achieved = flops / (mask["ms_per_launch"] * 1e-3) / 1e12
-        distance_tiles = {"bound": "mfma", "kernel": "BF16 split keep-mask kernel (distance tiles)",
-                          "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
-                          "traffic": traffic_from_profile("kde_keep_mask", args.workload),
-                          "ms_per_launch": mask["ms_per_launch"],
-                          "algorithmic_flops_per_launch": flops}
-        if roofline is None or mask["ms_per_launch"] > kde["ms_per_launch"]:
-            roofline, distance_tiles = distance_tiles, roofline
-    times_ms = np.array(times) * 1e3
+            steps = args.plain_steps if args.plain_steps > 0 else max(3, args.steps // 4)
+            warmup = 1
+        print(f"[bench] {w.name} {prec}: {warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
+        legs[prec], results[prec] = run_leg(ctx, w, Xd, prec, steps, warmup, args)
+        print(f"[bench] {w.name} {prec}: {legs[prec]['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    ctx.close()
+    head = legs[precs[0]]
     out = {
         "metric": METRIC,
-        "value": edges_per_s,
+        "value": head["edges_per_s"],
         "unit": "sampled edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": d, "L": L, "sigma": w.sigma, "gamma": w.gamma,
-                   "components": w.n_comp, "precision": PRECISION_NOTE[args.precision]},
-        "kernel_evals_per_s": evals / (total / args.steps),
-        "p50_ms": float(np.percentile(times_ms, 50)),
-        "p99_ms": float(np.percentile(times_ms, 99)),
-        "distinct_edges": nnz // 2,
-        "stages": stages,
-        "filter": ({"kept_column_tiles": kept, "scanned_column_tiles": scanned,
-                    "kept_fraction": kept / scanned} if scanned else None),
-        "roofline": roofline,
-        "second_kernel_roofline": distance_tiles,
+                   "components": w.n_comp, "precision": precs[0],
+                   "precision_detail": PRECISION_NOTE[precs[0]]},
+        "kernel_evals_per_s": head["kde"]["kernel_evals_per_s"],
+        "pairs_scanned_per_s": head["kde"]["pairs_scanned_per_s"],
+        "pairs_resolved_per_s": head["kde"]["pairs_resolved_per_s"],
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "distinct_edges": head["distinct_edges"],
+        "roofline": head["roofline"],
+        "second_kernel_roofline": head["second_kernel_roofline"],
+        "legs": legs,
         "cpu_baseline": None,
     }
-    gpu_nbr, gpu_deg = last["nbr"].cpu().numpy(), last["deg"].cpu().numpy()
-    last.clear()
-    ctx.close()
+    if len(precs) == 2:
+        out["plain_fp64"] = {"ms_per_step": legs["plain_fp64"]["ms_per_step"],
+                             "edges_per_s": legs["plain_fp64"]["edges_per_s"],
+                             "kernel_evals_per_s": legs["plain_fp64"]["kde"]["kernel_evals_per_s"],
+                             "p50_ms": legs["plain_fp64"]["p50_ms"], "p99_ms": legs["plain_fp64"]["p99_ms"]}
+        out["edges_per_s_ratio_bf16_split_vs_plain_fp64"] = head["edges_per_s"] / legs["plain_fp64"]["edges_per_s"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, w, args.cpu_seconds, gpu_nbr, gpu_deg)
+        print(f"[bench] oracle on the CPU", file=sys.stderr, flush=True)
+        if args.oracle_rows > 0 or "subsample" in w.extra:
+            m = args.oracle_rows if args.oracle_rows > 0 else w.extra["subsample"]
+            rows = workloads.subsample(n, m, w.extra.get("subsample_seed", 4243))
+            out["cpu_baseline"] = cpu_baseline_rows(X, w, rows, results)
+        else:
+            cb = cpu_baseline(X, w, args.cpu_seconds, *results[precs[0]])
+            cb["cpu_model"] = cpu_model()
+            out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

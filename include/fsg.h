@@ -4,7 +4,7 @@
  * via Kernel Density Estimation", NeurIPS 2023) on AMD Instinct MI355X (gfx950).
  *
  * The library builds a sparse approximation of the fully connected Gaussian
- * similarity graph of n points (Section 2.3) without forming the n x n kernel
+ * similarity graph of n points (Section 2.1) without forming the n x n kernel
  * matrix: every point draws L neighbours j with probability k(x_i,x_j)/deg(x_i)
  * by a randomised descent of an index-order binary partition tree whose branch
  * probabilities are kernel density estimates over the tree nodes (Algorithm 1,
@@ -56,14 +56,18 @@ typedef enum {
 } fsg_status;
 
 typedef enum {
-    /* plain: every pair's cross term on the FP64 matrix cores, FP64 distance
-     * and exp */
-    FSG_FP32 = 0,
+    /* plain path: FP32 points, every pair's cross term on the FP64 matrix
+     * cores, FP64 distance, exp and masses (no pair is skipped).  It is not an
+     * FP32 path: FP32 distances from the norm expansion would move kernel
+     * values, and so node masses, by up to ~1e-5 relative at n = 1e5, d = 32
+     * and ~3e-5 at n = 1e6, d = 64 -- more than the 1e-6 decision band of the
+     * descent, and at the larger size more than a 1e-5 degree tolerance. */
+    FSG_PLAIN_FP64 = 0,
     /* precision mode: BF16 hi/lo split operands (hi = bf16(x), lo = bf16(x-hi))
      * on the BF16 matrix cores with FP32 accumulation give every pair an
      * approximate exponent with a guaranteed error bound; only pairs that can
      * carry more than e^-Delta of their row's largest term (Delta = ln n + 25)
-     * are recomputed in FP64 as in FSG_FP32, the others add 0.  Every degree
+     * are recomputed in FP64 as in FSG_PLAIN_FP64, the others add 0.  Every degree
      * and node mass then differs from the exact one by less than
      * (n-1) e^-Delta < e^-25 = 1.4e-11 of the degree.
      * Applies to the pass over all points (fsg_degrees, the first pass of
@@ -114,7 +118,7 @@ fsg_status fsg_ctx_set_levels_per_pass(fsg_ctx* ctx, int32_t max_levels);
  * "prep"); with FSG_BF16_SPLIT also the split BF16 operands, an upper bound on
  * each point's smallest squared distance (from 256 pivot points) and an order
  * of the points by nearest pivot (used to form coherent query tiles).
- * 1 <= n <= 2^31-1, 1 <= d <= 128 (FSG_FP32) or 64 (FSG_BF16_SPLIT). */
+ * 1 <= n <= 2^31-1, 1 <= d <= 128 (both precisions). */
 fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_t d, fsg_precision prec,
                              fsg_points** out);
 void fsg_points_destroy(fsg_points* pts);
@@ -122,11 +126,11 @@ void fsg_points_destroy(fsg_points* pts);
 uint64_t fsg_points_bytes(const fsg_points* pts);
 
 /* Degrees: deg_dev[i] = sum_{j != i} exp(-gamma ||x_i - x_j||^2), FP64 [n].
- * This is the KDE g_[1,n](x_i) of Algorithm 2 (eq. (1) of Section 2.4) without
+ * This is the KDE g_[1,n](x_i) of Algorithm 2 (eq. (1) of Section 2.2) without
  * the self term. */
 fsg_status fsg_degrees(fsg_ctx* ctx, const fsg_points* X, double gamma, double* deg_dev);
 
-/* Segmented KDE (eq. (1) of Section 2.4 over index ranges; the two KDEs of
+/* Segmented KDE (eq. (1) of Section 2.2 over index ranges; the two KDEs of
  * Algorithm 1).  Segment s pairs the query entries e in [q_ptr[s], q_ptr[s+1])
  * -- query point Q[q_idx[e]] -- with the data range X[lo[s]:hi[s]) split at
  * mid[s]:
@@ -228,7 +232,13 @@ fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int
  * fsg_graph_begin and fsg_graph_end (which must not synchronise; e.g.
  * fsg_batch_step, fsg_sample_edges) is recorded into a graph that
  * fsg_graph_launch replays on the stream.  The recorded calls must have run
- * once before (so that no workspace grows while recording).
+ * once before (so that no workspace grows while recording).  While a graph
+ * exists, device blocks it may name stay allocated: a later call that grows a
+ * workspace buffer parks the old one instead of freeing it, and parked blocks
+ * are freed when the context's last graph is destroyed.  The point sets and
+ * jobs a graph uses must outlive its launches; a graph is launched only on the
+ * context it was recorded on (FSG_E_INVALID otherwise); if the context is
+ * destroyed first, the graph is valid for fsg_graph_destroy only.
  * ------------------------------------------------------------------------ */
 typedef struct fsg_graph fsg_graph;
 fsg_status fsg_graph_begin(fsg_ctx* ctx);

@@ -13,10 +13,10 @@
  * Conventions (every reading of the paper is listed in the design notes):
  *  - points are FP32, row-major n x d; every value is promoted exactly to FP64;
  *  - kernel k(x,y) = exp(-gamma * ||x - y||^2), difference form, FP64
- *    (Section 2.3, Gaussian kernel; gamma = 1/sigma^2 in the paper's
+ *    (Section 2.1, Gaussian kernel; gamma = 1/sigma^2 in the paper's
  *    notation, 1/(2 sigma^2) in the workload descriptions);
  *  - the self term j == i is excluded from every mass and degree (the
- *    similarity graph of Section 2.3 has no self loops);
+ *    similarity graph of Section 2.1 has no self loops);
  *  - the partition tree is over index order; node [a,b) splits at
  *    mid = a + floor((b-a)/2), i.e. |X1| = floor(|X|/2) (Section 4.1);
  *  - uniforms come from Philox4x64-10 (Salmon et al., SC'11):
@@ -47,14 +47,14 @@ double fsgo_uniform(uint64_t seed, uint64_t i, uint64_t l, uint32_t level);
 /* Split point of node [a,b): the left child holds floor((b-a)/2) points (Section 4.1). */
 int64_t fsgo_split(int64_t a, int64_t b);
 
-/* Gaussian kernel between two FP32 points, evaluated in FP64 (Section 2.3). */
+/* Gaussian kernel between two FP32 points, evaluated in FP64 (Section 2.1). */
 double fsgo_kernel(const float* x, const float* y, int32_t d, double gamma);
 
 /* deg[i] = sum_{j != i} k(x_i, x_j)  (the KDE g_[1,n](x_i) of Algorithm 2
  * with the self term removed). */
 int fsgo_degrees(const float* X, int64_t n, int32_t d, double gamma, double* deg);
 
-/* Segmented KDE (the KDE problem of Section 2.4 restricted to index ranges):
+/* Segmented KDE (the KDE problem of Section 2.2 restricted to index ranges):
  * for segment s and every entry e in [q_ptr[s], q_ptr[s+1]):
  *   out_left[e]  = sum_{j in [lo[s], mid[s]), j != self_idx[e]} k(Q[q_idx[e]], X[j])
  *   out_right[e] = sum_{j in [mid[s], hi[s]), j != self_idx[e]} k(Q[q_idx[e]], X[j])

@@ -14,8 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsg.so")
 
 FSG_OK, FSG_E_INVALID, FSG_E_NOMEM, FSG_E_DEVICE, FSG_E_UNSUPPORTED, FSG_E_BUDGET = 0, -1, -2, -3, -4, -5
-FSG_FP32, FSG_BF16_SPLIT = 0, 1
-PRECISIONS = {"fp32": FSG_FP32, "bf16_split": FSG_BF16_SPLIT}
+FSG_PLAIN_FP64, FSG_BF16_SPLIT = 0, 1
+PRECISIONS = {"plain_fp64": FSG_PLAIN_FP64, "bf16_split": FSG_BF16_SPLIT}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfsg.so is not built ({LIB_PATH}); run paper_2310_13870_amd/build.py")
@@ -158,7 +158,7 @@ class Context:
     def set_autotune(self, enabled: bool):
         self.check(_lib.fsg_ctx_set_autotune(self._h, 1 if enabled else 0))
 
-    def tuned_shape(self, D4: int, precision=FSG_FP32):
+    def tuned_shape(self, D4: int, precision=FSG_PLAIN_FP64):
         """(waves per CU, data columns per work item) tuned for a class, or None."""
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
@@ -181,7 +181,7 @@ class Context:
 class Points:
     """fsg_points: a resident point set.  Keeps a reference to X (borrowed by the library)."""
 
-    def __init__(self, ctx: Context, X: torch.Tensor, precision=FSG_FP32):
+    def __init__(self, ctx: Context, X: torch.Tensor, precision=FSG_PLAIN_FP64):
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         _dev_tensor(X, torch.float32, "X")
@@ -262,7 +262,7 @@ def build_csr(ctx: Context, pts: Points, gamma: float, L: int, nbr: torch.Tensor
     return row_ptr, col[: nnz.value], w[: nnz.value]
 
 
-def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_FP32):
+def build_graph(ctx: Context, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_PLAIN_FP64):
     """Algorithm 2 end to end: prep, sampling, degrees, reweighting and CSR."""
     pts = Points(ctx, X, precision)
     nbr, deg, _ = sample_edges(ctx, pts, gamma, L, seed)
@@ -382,7 +382,7 @@ class Server:
         self._h = h
         self._keep = {}  # request id -> tensors that must stay valid until completion
 
-    def submit_build(self, set_id: int, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_FP32) -> int:
+    def submit_build(self, set_id: int, X: torch.Tensor, gamma: float, L: int, seed: int, precision=FSG_PLAIN_FP64) -> int:
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         _dev_tensor(X, torch.float32, "X")

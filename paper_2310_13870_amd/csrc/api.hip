@@ -44,6 +44,28 @@ StageTimer::~StageTimer() {
     ctx->marks.push_back({name, {start, stop}});
 }
 
+void dev_free(fsg_ctx* ctx, void* p) {
+    if (!p) return;
+    if (ctx && !ctx->graphs.empty()) ctx->retired.push_back(p);
+    else (void)hipFree(p);
+}
+
+void host_free(fsg_ctx* ctx, void* p) {
+    if (!p) return;
+    if (ctx && !ctx->graphs.empty()) ctx->retired_host.push_back(p);
+    else (void)hipHostFree(p);
+}
+
+// free what was parked while graphs existed (none exists any more)
+static void free_retired(fsg_ctx* ctx) {
+    if (ctx->retired.empty() && ctx->retired_host.empty()) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : ctx->retired) (void)hipFree(p);
+    for (void* p : ctx->retired_host) (void)hipHostFree(p);
+    ctx->retired.clear();
+    ctx->retired_host.clear();
+}
+
 fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
@@ -55,9 +77,10 @@ fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out) {
     size_t old = 0;
     if (it != ctx->bufs.end()) {
         old = it->second.second;
-        // the stream may still use the old buffer
+        // the stream may still use the old buffer, and a recorded graph may
+        // name it (then it is parked until the last graph is destroyed)
         FSG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        FSG_HIP(ctx, hipFree(it->second.first));
+        dev_free(ctx, it->second.first);
         ctx->held -= old;
         ctx->bufs.erase(it);
     }
@@ -110,7 +133,7 @@ hipError_t pool_alloc(fsg_ctx* ctx, size_t bytes, void** out) {
         (void)hipStreamSynchronize(ctx->stream);
         for (auto& kv : ctx->pool_free) {
             ctx->pool_size.erase(kv.second);
-            (void)hipFree(kv.second);
+            dev_free(ctx, kv.second);
         }
         ctx->pool_free.clear();
         ctx->pool_cached = 0;
@@ -126,12 +149,12 @@ void pool_release(fsg_ctx* ctx, void* p) {
     if (!p) return;
     auto it = ctx->pool_size.find(p);
     if (it == ctx->pool_size.end()) {
-        (void)hipFree(p);
+        dev_free(ctx, p);
         return;
     }
     if (ctx->pool_cached + it->second > kPoolCacheCap) {
         (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(p);
+        dev_free(ctx, p);
         ctx->pool_size.erase(it);
         return;
     }
@@ -737,10 +760,10 @@ struct BatchTables {
     unsigned long long* counter = nullptr;
 };
 
-static void free_tables(BatchTables* T) {
-    if (T->dev) (void)hipFree(T->dev);
-    if (T->items) (void)hipFree(T->items);
-    if (T->host) (void)hipHostFree(T->host);
+static void free_tables(fsg_ctx* ctx, BatchTables* T) {
+    dev_free(ctx, T->dev);
+    dev_free(ctx, T->items);
+    host_free(ctx, T->host);
     delete T;
 }
 
@@ -756,9 +779,9 @@ struct LeafTables {
     int64_t slots = 0;
 };
 
-static void free_leaf_tables(LeafTables* T) {
-    if (T->dev) (void)hipFree(T->dev);
-    if (T->host) (void)hipHostFree(T->host);
+static void free_leaf_tables(fsg_ctx* ctx, LeafTables* T) {
+    dev_free(ctx, T->dev);
+    host_free(ctx, T->host);
     delete T;
 }
 
@@ -783,6 +806,7 @@ struct fsg_job {
 };
 
 struct fsg_graph {
+    fsg_ctx* ctx = nullptr;  // cleared if the context is destroyed first
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -805,7 +829,7 @@ static void batch_cache_drop(fsg_ctx* ctx, const fsg_job* j) {
     for (size_t i = 0; i < c.size();) {
         if (std::find(c[i]->jobs.begin(), c[i]->jobs.end(), j) != c[i]->jobs.end()) {
             (void)hipStreamSynchronize(ctx->stream);
-            free_tables(c[i]);
+            free_tables(ctx, c[i]);
             c.erase(c.begin() + i);
         } else {
             ++i;
@@ -815,7 +839,7 @@ static void batch_cache_drop(fsg_ctx* ctx, const fsg_job* j) {
     for (size_t i = 0; i < lc.size();) {
         if (std::find(lc[i]->jobs.begin(), lc[i]->jobs.end(), j) != lc[i]->jobs.end()) {
             (void)hipStreamSynchronize(ctx->stream);
-            free_leaf_tables(lc[i]);
+            free_leaf_tables(ctx, lc[i]);
             lc.erase(lc.begin() + i);
         } else {
             ++i;
@@ -870,7 +894,7 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
     T->cols = cols;
     T->bytes = bytes;
     auto fail = [&](fsg_status s) {
-        free_tables(T);
+        free_tables(ctx, T);
         return s;
     };
     if (hipMalloc(&T->dev, bytes) != hipSuccess || hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
@@ -1041,7 +1065,7 @@ static fsg_status batch_root(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
         auto& c = ctx->batch_cache;
         for (size_t i = 0; i < c.size();) {
             if (c[i]->jobs == g && !(c[i]->waves_per_cu == waves && c[i]->cols == cols)) {
-                free_tables(c[i]);
+                free_tables(ctx, c[i]);
                 c.erase(c.begin() + i);
             } else {
                 ++i;
@@ -1067,7 +1091,7 @@ static fsg_status leaf_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, Leaf
     LeafTables* T = new LeafTables();
     T->jobs = g;
     auto fail = [&](fsg_status s) {
-        free_leaf_tables(T);
+        free_leaf_tables(ctx, T);
         return s;
     };
     if (hipMalloc(&T->dev, bytes) != hipSuccess || hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
@@ -1184,6 +1208,10 @@ fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes
 void fsg_ctx_destroy(fsg_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    // live graphs are detached (they can no longer be launched); what they
+    // may name is freed below
+    for (fsg_graph* g : ctx->graphs) g->ctx = nullptr;
+    ctx->graphs.clear();
     // live point sets stay valid: their pooled blocks become theirs to free
     for (fsg_points* p : ctx->points) {
         for (void* v : {(void*)p->Xp, (void*)p->norm, (void*)p->Xb, (void*)p->Qb, (void*)p->dmin, (void*)p->order,
@@ -1196,9 +1224,9 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
         const std::set<fsg_server*> servers = ctx->servers;
         for (fsg_server* srv : servers) server_detach(srv);
     }
-    for (BatchTables* T : ctx->batch_cache) free_tables(T);
+    for (BatchTables* T : ctx->batch_cache) free_tables(ctx, T);
     ctx->batch_cache.clear();
-    for (LeafTables* T : ctx->leaf_cache) free_leaf_tables(T);
+    for (LeafTables* T : ctx->leaf_cache) free_leaf_tables(ctx, T);
     ctx->leaf_cache.clear();
     // live jobs are detached; their buffers are freed here
     for (fsg_job* j : ctx->jobs) {
@@ -1210,6 +1238,7 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
         j->ctx = nullptr;
     }
     pool_clear(ctx);
+    free_retired(ctx);
     for (auto& kv : ctx->bufs) (void)hipFree(kv.second.first);
     for (auto& m : ctx->marks) {
         (void)hipEventDestroy(m.second.first);
@@ -1294,7 +1323,7 @@ fsg_status fsg_points_create(fsg_ctx* ctx, const float* X_dev, int64_t n, int32_
     if (!X_dev) return set_error(ctx, FSG_E_INVALID, "X_dev is NULL");
     if (n < 1 || n > 2147483647LL) return set_error(ctx, FSG_E_INVALID, "n must be in [1, 2^31-1]");
     if (d < 1 || d > 1024) return set_error(ctx, FSG_E_INVALID, "d must be in [1, 1024]");
-    if (prec != FSG_FP32 && prec != FSG_BF16_SPLIT) return set_error(ctx, FSG_E_INVALID, "unknown precision");
+    if (prec != FSG_PLAIN_FP64 && prec != FSG_BF16_SPLIT) return set_error(ctx, FSG_E_INVALID, "unknown precision");
     const int D4 = feature_steps(d);
     if (D4 < 0) return set_error(ctx, FSG_E_UNSUPPORTED, "d > 128 is not built in this version");
     if (prec == FSG_BF16_SPLIT && filter_steps(D4) < 0)
@@ -1760,20 +1789,29 @@ fsg_status fsg_graph_end(fsg_ctx* ctx, fsg_graph** out) {
         delete g;
         return set_error(ctx, FSG_E_DEVICE, std::string("graph: ") + hipGetErrorString(e));
     }
+    g->ctx = ctx;
+    ctx->graphs.insert(g);
     *out = g;
     return FSG_OK;
 }
 
 fsg_status fsg_graph_launch(fsg_ctx* ctx, fsg_graph* g) {
     if (!ctx || !g) return FSG_E_INVALID;
+    if (g->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "the graph was not recorded on this context");
     FSG_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
     return FSG_OK;
 }
 
 void fsg_graph_destroy(fsg_graph* g) {
     if (!g) return;
+    fsg_ctx* ctx = g->ctx;
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);  // a replay may still run
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (ctx) {
+        ctx->graphs.erase(g);
+        if (ctx->graphs.empty()) free_retired(ctx);
+    }
     delete g;
 }
 

@@ -177,6 +177,14 @@ struct fsg_ctx {
     // live servers: their sets and requests are released when the context is
     // destroyed (the handles stay valid for fsg_server_destroy)
     std::set<fsg_server*> servers;
+    // HIP graphs recorded on this context and not yet destroyed.  While any
+    // exists, device and pinned host blocks the context would free (a grown
+    // workspace buffer, released pool blocks, dropped batch tables) may still
+    // be named by a graph node: they are parked here and freed when the last
+    // graph is destroyed.
+    std::set<fsg_graph*> graphs;
+    std::vector<void*> retired;
+    std::vector<void*> retired_host;
 };
 
 
@@ -187,7 +195,7 @@ struct fsg_points {
     int32_t d = 0;
     int32_t D4 = 0;            // padded feature steps
     int64_t n_pad = 0;         // rows padded to a multiple of 16
-    fsg_precision prec = FSG_FP32;
+    fsg_precision prec = FSG_PLAIN_FP64;
     double* Xp = nullptr;      // FP64 operand rows [n_pad][4*D4] (layout above)
     double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
     // precision mode (FSG_BF16_SPLIT)
@@ -233,6 +241,10 @@ struct StageTimer {
 
 // Workspace buffer of at least `bytes`, keyed by name (reused across calls).
 fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out);
+// Free a device block (hipMalloc) or pinned host block (hipHostMalloc) of the
+// context, or park it while a recorded graph may name it.
+void dev_free(fsg_ctx* ctx, void* p);
+void host_free(fsg_ctx* ctx, void* p);
 
 // Feature-step count used for a dimension d (a size the KDE kernel is built for).
 int feature_steps(int d);

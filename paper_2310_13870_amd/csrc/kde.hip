@@ -1,6 +1,6 @@
 // Segmented Gaussian KDE over tree bins on the FP64 matrix cores (hot-path
 // step "segmented KDE"; the two KDEs of Algorithm 1 and the degree KDE of
-// Algorithm 2, eq. (1) of Section 2.4 over index ranges).
+// Algorithm 2, eq. (1) of Section 2.2 over index ranges).
 //
 // A wave owns one work item: up to 16*RQ query entries of one segment and a
 // run of that segment's bins (consecutive index ranges of the data).  It

@@ -26,7 +26,7 @@ struct SetRec {
     double gamma = 0.0;
     int32_t L = 0;
     uint64_t seed = 0;
-    fsg_precision prec = FSG_FP32;
+    fsg_precision prec = FSG_PLAIN_FP64;
     float* X = nullptr;        // the server's copy of the points
     fsg_points* pts = nullptr;
     fsg_job* job = nullptr;    // while the build runs
@@ -189,7 +189,7 @@ fsg_status admit_build(fsg_server* s, Req* q) {
 fsg_status admit_kde(fsg_server* s, Req* q, SetRec* r) {
     fsg_ctx* ctx = s->ctx;
     fsg_status st;
-    if ((st = fsg_points_create(ctx, q->Q, q->m, r->d, FSG_FP32, &q->qpts)) != FSG_OK) return st;
+    if ((st = fsg_points_create(ctx, q->Q, q->m, r->d, FSG_PLAIN_FP64, &q->qpts)) != FSG_OK) return st;
     int64_t* q_ptr = (int64_t*)blk(ctx, q->blocks, 2 * sizeof(int64_t));
     int32_t* q_idx = (int32_t*)blk(ctx, q->blocks, (size_t)q->m * sizeof(int32_t));
     int32_t* seg = (int32_t*)blk(ctx, q->blocks, 3 * sizeof(int32_t));

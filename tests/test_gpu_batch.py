@@ -35,7 +35,7 @@ def _reference(ctx, pts):
     return ref
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
 def test_batch_equals_single(prec):
     sets = SETS
     say(f"batch {prec}: {len(sets)} jobs")
@@ -69,13 +69,13 @@ def test_batch_autotune_off_same_result():
     ctx = fsg.Context(0)
     try:
         ctx.set_autotune(False)
-        pts = _points(ctx, sets, "fp32", 7300)
+        pts = _points(ctx, sets, "plain_fp64", 7300)
         jobs = [fsg.Job(ctx, p, gamma, L, seed) for p, gamma, L, seed in pts]
         fsg.batch_run(ctx, jobs)
         a = [j.result() for j in jobs]
         assert ctx.tuned_shape(8) is None
         ctx2 = fsg.Context(0)
-        pts2 = _points(ctx2, sets, "fp32", 7300)
+        pts2 = _points(ctx2, sets, "plain_fp64", 7300)
         jobs2 = [fsg.Job(ctx2, p, gamma, L, seed) for p, gamma, L, seed in pts2]
         fsg.batch_run(ctx2, jobs2)
         say(f"tuned shape D4=8: {ctx2.tuned_shape(8)}")
@@ -90,7 +90,7 @@ def test_batch_autotune_off_same_result():
         ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
 def test_batch_graph_replay(prec):
     """A batch recorded into a HIP graph and replayed several times, with eager
     work on the same stream between replays: every replay gives the eager result."""
@@ -124,6 +124,55 @@ def test_batch_graph_replay(prec):
                 # eager work between replays
                 fsg.sample_edges(ctx, pts[0][0], pts[0][1], pts[0][2], pts[0][3])
             g.close()
+            for j in jobs:
+                j.close()
+        finally:
+            s.synchronize()
+            ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
+def test_graph_replay_after_workspace_growth(prec):
+    """A larger build between replays grows the context's workspace buffers;
+    the blocks the recorded graph names are parked, not freed, so later
+    replays still give the eager result."""
+    sets = [s for s in SETS[1:7] if s[1] <= 64]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = fsg.Context(0, stream=s)
+        try:
+            pts = _points(ctx, sets, prec, 7700)
+            jobs = [fsg.Job(ctx, p, gamma, L, seed) for p, gamma, L, seed in pts]
+            fsg.batch_run(ctx, jobs)
+            eager = [tuple(t.clone() for t in j.result()) for j in jobs]
+            outs = [(torch.empty_like(a), torch.empty_like(b)) for a, b in eager]
+            for j in jobs:
+                j.reset()
+            g = fsg.Graph(ctx)
+            g.begin()
+            fsg.batch_run(ctx, jobs)
+            for j, (a, b) in zip(jobs, outs):
+                j.result(a, b)
+            g.end()
+            ws0 = ctx.workspace_bytes
+            big = workloads.mixture(40_000, 32, 6, 7790, (-4.0, 4.0), (0.5, 1.5))
+            pbig = fsg.Points(ctx, to_dev(big), prec)
+            for rep in range(3):
+                for a, b in outs:
+                    a.fill_(-7)
+                    b.fill_(-7.0)
+                g.launch()
+                s.synchronize()
+                for (ea, eb), (a, b) in zip(eager, outs):
+                    assert torch.equal(ea, a), f"replay {rep}"
+                    assert torch.equal(eb, b), f"replay {rep}"
+                if rep == 0:
+                    fsg.sample_edges(ctx, pbig, 1 / 16, 16, 99)
+                    s.synchronize()
+                    say(f"workspace {ws0} -> {ctx.workspace_bytes} bytes")
+                    assert ctx.workspace_bytes > ws0, "the larger build did not grow the workspace"
+            g.close()
+            pbig.close()
             for j in jobs:
                 j.close()
         finally:

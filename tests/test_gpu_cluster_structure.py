@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 import paper_2310_13870_amd as fsg  # noqa: E402
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
 def test_gpu_graph_preserves_clusters(prec):
     X, lab, gamma, L = case("k4-4d", 52)
     n = X.shape[0]

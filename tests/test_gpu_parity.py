@@ -209,7 +209,7 @@ def test_points_outlive_context():
     pts.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
 def test_pooled_point_arrays_reused(prec):
     """A point set built from blocks another point set released (the
     context's pool) gives exactly what it gives on a fresh context."""
@@ -252,7 +252,7 @@ def test_multi_pass_plans(ctx, cap):
         ctx.set_levels_per_pass(0)
 
 
-@pytest.mark.parametrize("prec,cap", [("fp32", 0), ("fp32", 2), ("bf16_split", 0)])
+@pytest.mark.parametrize("prec,cap", [("plain_fp64", 0), ("plain_fp64", 2), ("bf16_split", 0)])
 def test_margin_output_changes_nothing(ctx, prec, cap):
     """The branch margins are an output only: with or without them, in the
     root descent, the later passes and the leaf walk, every neighbour and

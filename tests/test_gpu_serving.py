@@ -16,9 +16,9 @@ pytestmark = pytest.mark.gpu
 import paper_2310_13870_amd as fsg  # noqa: E402
 
 # set id -> (n, d, gamma, L, seed, precision)
-BUILDS = {0: (3000, 64, 1 / 18, 12, 11, "bf16_split"), 1: (1200, 64, 1 / 18, 11, 12, "fp32"),
-          2: (4097, 16, 0.1, 13, 13, "fp32"), 3: (800, 64, 1 / 18, 10, 14, "bf16_split"),
-          4: (2500, 16, 0.1, 12, 15, "bf16_split"), 5: (50, 8, 0.2, 6, 16, "fp32")}
+BUILDS = {0: (3000, 64, 1 / 18, 12, 11, "bf16_split"), 1: (1200, 64, 1 / 18, 11, 12, "plain_fp64"),
+          2: (4097, 16, 0.1, 13, 13, "plain_fp64"), 3: (800, 64, 1 / 18, 10, 14, "bf16_split"),
+          4: (2500, 16, 0.1, 12, 15, "bf16_split"), 5: (50, 8, 0.2, 6, 16, "plain_fp64")}
 KDES = [(0, 700, 1 / 18), (2, 300, 0.1), (5, 64, 0.2)]  # (set id, query points, gamma)
 
 
@@ -110,7 +110,7 @@ def test_server_budget_evicts_and_defers():
     Xd = {k: to_dev(v) for k, v in sets.items()}
     probe = fsg.Server(ctx, 1 << 40, 1)
     # the budget: the first build's resident bytes, measured, times 2.5
-    r0 = probe.submit_build(100, Xd[0], 1 / 18, 12, 1, "fp32")
+    r0 = probe.submit_build(100, Xd[0], 1 / 18, 12, 1, "plain_fp64")
     _drain(probe, {r0})
     one = probe.stats()["bytes"]
     probe.close()
@@ -121,7 +121,7 @@ def test_server_budget_evicts_and_defers():
     srv = fsg.Server(ctx, 3 * one, 1)
     status = {}
     for k in range(5):
-        rid = srv.submit_build(k, Xd[k], 1 / 18, 12, k, "fp32")
+        rid = srv.submit_build(k, Xd[k], 1 / 18, 12, k, "plain_fp64")
         status.update(_drain(srv, {rid}))
     st = srv.stats()
     say(f"stats {st}")
@@ -134,7 +134,7 @@ def test_server_budget_evicts_and_defers():
     rid, _ = srv.submit_kde(0, q, 1 / 18)
     assert _drain(srv, {rid})[rid] == fsg.FSG_E_INVALID
     # deferred: KDE submitted right after its set's build request
-    rid_b = srv.submit_build(50, Xd[1], 1 / 18, 12, 3, "fp32")
+    rid_b = srv.submit_build(50, Xd[1], 1 / 18, 12, 3, "plain_fp64")
     rid_k, out = srv.submit_kde(50, q, 1 / 18)
     done = _drain(srv, {rid_b, rid_k})
     assert done[rid_b] == fsg.FSG_OK and done[rid_k] == fsg.FSG_OK

@@ -119,4 +119,36 @@ def batched_sets(count: int = 256, seed: int = 1003):
     return out
 
 
+def serving_trace(seconds: float = 60.0, rate: float = 50.0, seed: int = 1004):
+    """Seeded open-loop request trace: Poisson arrivals at `rate` per second
+    for `seconds`; 80% builds of a point set from a pool of 64 (n log-uniform
+    in [2e3, 2e5], d 64, 20 components, means U[-10,10], std U[0.5,2], sigma
+    3, L ceil(log2 n)), 20% KDE queries of 10,000 points of the same mixture
+    family against a finished set; precision 50/50 per request.  Returns
+    (pool of Workloads, requests as dicts with arrival time t, kind, pool
+    index, precision, Philox seed and a uniform `pick` for the KDE target)."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(64):
+        n = int(round(math.exp(rng.uniform(math.log(2e3), math.log(2e5)))))
+        pool.append(Workload(f"pool{k}-n{n}", n, 64, 3.0, depth_of(n), seed * 1000 + k, seed * 1000 + 500 + k,
+                             20, (-10.0, 10.0), (0.5, 2.0)))
+    t, reqs = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        kind = "build" if rng.random() < 0.8 else "kde"
+        prec = "bf16_split" if rng.random() < 0.5 else "plain_fp64"
+        reqs.append({"t": t, "kind": kind, "pool": int(rng.integers(len(pool))), "prec": prec,
+                     "seed": int(rng.integers(1 << 62)), "pick": float(rng.random())})
+    return pool, reqs
+
+
+def serving_queries(w: Workload, m: int = 10_000) -> np.ndarray:
+    """The KDE query points of a serving request against pool set w: m fresh
+    points of the set's mixture family (its own seed + 7)."""
+    return mixture(m, w.d, w.n_comp, w.data_seed + 7, w.mean_range, w.std_range)
+
+
 WORKLOADS = {"blobs2d-n1000": tiny_blobs, "mix32-n100k": mixture32, "mix64-n1m": mixture64}
