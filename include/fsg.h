@@ -149,6 +149,28 @@ fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points
                              const int32_t* lo, const int32_t* mid, const int32_t* hi,
                              const int32_t* self_idx, double* out_left, double* out_right);
 
+/* Size of the static device scratch of fsg_kde_segmented_noalloc (per GPU). */
+#define FSG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments, results and errors as fsg_kde_segmented, but it
+ * calls no allocating routine.  Its work lists and pair sums live in a static
+ * device array of FSG_NOALLOC_SCRATCH_BYTES (64 MiB) on each GPU, held until
+ * the process ends, instead of the context's workspace.  A call needs about
+ * 16 bytes per query entry plus 70 per segment (each of six regions rounded
+ * up to 256 bytes); larger calls return FSG_E_UNSUPPORTED with the byte count
+ * in fsg_last_error, and enqueue nothing.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (nothing in it needs to start at
+ * zero): calls that overlap on one GPU -- on two streams or two contexts of
+ * the same device -- race, and the caller must order them.  FSG_E_DEVICE if
+ * the array's address could not be looked up when the context was created.
+ * Point sets Q and X must already exist (fsg_points_create allocates). */
+fsg_status fsg_kde_segmented_noalloc(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma,
+                                     int64_t n_seg, int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx,
+                                     const int32_t* lo, const int32_t* mid, const int32_t* hi,
+                                     const int32_t* self_idx, double* out_left, double* out_right);
+
 /* Algorithm 1 run L times from the root for every point (Algorithm 2's
  * sampling loop).  nbr_dev int32 [n*L]: nbr[i*L+l] = the neighbour sampled by
  * sample l of point i, or -1 when deg_i == 0.  deg_dev FP64 [n] (may be NULL)

@@ -51,6 +51,8 @@ _lib_fns = dict(
     fsg_degrees=_sig("fsg_degrees", ctypes.c_int, _vp, _vp, _dbl, _vp),
     fsg_kde_segmented=_sig("fsg_kde_segmented", ctypes.c_int, _vp, _vp, _vp, _dbl, _i64, _i64, _vp, _vp, _vp,
                            _vp, _vp, _vp, _vp, _vp),
+    fsg_kde_segmented_noalloc=_sig("fsg_kde_segmented_noalloc", ctypes.c_int, _vp, _vp, _vp, _dbl, _i64, _i64, _vp,
+                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp),
     fsg_sample_edges=_sig("fsg_sample_edges", ctypes.c_int, _vp, _vp, _dbl, _i32, _u64, _vp, _vp, _vp),
     fsg_build_csr=_sig("fsg_build_csr", ctypes.c_int, _vp, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
                        ctypes.POINTER(_i64)),
@@ -230,6 +232,30 @@ def kde_segmented(ctx: Context, Q: Points, X: Points, gamma: float, q_ptr, q_idx
     ctx.check(_lib.fsg_kde_segmented(ctx._h, Q._h, X._h, gamma, n_seg, n_ent, _ptr(q_ptr), _ptr(q_idx), _ptr(lo),
                                      _ptr(mid), _ptr(hi), _ptr(self_idx), _ptr(left), _ptr(right)))
     return left, right
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FSG_NOALLOC_SCRATCH_BYTES
+
+
+def kde_segmented_noalloc(ctx: Context, Q: Points, X: Points, gamma: float, q_ptr, q_idx, lo, mid, hi,
+                          out_left: torch.Tensor, out_right: torch.Tensor, self_idx=None):
+    """fsg_kde_segmented_noalloc: the segmented KDE into caller-given outputs,
+    with the library's static scratch instead of workspace allocations."""
+    _dev_tensor(q_ptr, torch.int64, "q_ptr")
+    for name, t in (("q_idx", q_idx), ("lo", lo), ("mid", mid), ("hi", hi)):
+        _dev_tensor(t, torch.int32, name)
+    if self_idx is not None:
+        _dev_tensor(self_idx, torch.int32, "self_idx")
+    _dev_tensor(out_left, torch.float64, "out_left")
+    _dev_tensor(out_right, torch.float64, "out_right")
+    n_seg = lo.shape[0]
+    n_ent = q_idx.shape[0]
+    if out_left.numel() < n_ent or out_right.numel() < n_ent:
+        raise ValueError("outputs hold fewer entries than q_idx")
+    ctx.check(_lib.fsg_kde_segmented_noalloc(ctx._h, Q._h, X._h, gamma, n_seg, n_ent, _ptr(q_ptr), _ptr(q_idx),
+                                             _ptr(lo), _ptr(mid), _ptr(hi), _ptr(self_idx), _ptr(out_left),
+                                             _ptr(out_right)))
+    return out_left, out_right
 
 
 def sample_edges(ctx: Context, pts: Points, gamma: float, L: int, seed: int, want_deg: bool = True,

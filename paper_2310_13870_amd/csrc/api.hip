@@ -111,6 +111,7 @@ static fsg_status ws(fsg_ctx* ctx, const char* name, size_t count, T** out) {
 
 static bool gamma_ok(double g) { return std::isfinite(g) && g > 0.0; }
 
+
 // Largest total of cached point-set blocks; beyond it released blocks are freed.
 constexpr size_t kPoolCacheCap = (size_t)16 << 30;
 
@@ -358,6 +359,62 @@ static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus) {
     m.blocks_per_chunk = mask_chunk_blocks(m.n_blocks, (m.n_tiles + tp - 1) / tp, keep_mask_waves(m.KB, num_cus), m.KB);
     m.n_chunks = (m.n_blocks + m.blocks_per_chunk - 1) / m.blocks_per_chunk;
     return m;
+}
+
+fsg_status kde_segmented_check(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma, int64_t n_seg,
+                               int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx, const int32_t* lo,
+                               const int32_t* mid, const int32_t* hi, const double* out_left,
+                               const double* out_right, bool* empty) {
+    *empty = false;
+    if (!ctx) return FSG_E_INVALID;
+    if (!Q || !X) return set_error(ctx, FSG_E_INVALID, "NULL points");
+    if (Q->ctx != ctx || X->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
+    if (Q->d != X->d) return set_error(ctx, FSG_E_INVALID, "Q and X differ in d");
+    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
+    if (n_seg < 0 || n_entries < 0) return set_error(ctx, FSG_E_INVALID, "negative count");
+    if (n_seg > 2147483647LL || n_entries > 2147483647LL)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "more than 2^31-1 segments or entries");
+    if (n_seg == 0 || n_entries == 0) {
+        *empty = true;
+        return FSG_OK;
+    }
+    if (!q_ptr || !q_idx || !lo || !mid || !hi || !out_left || !out_right)
+        return set_error(ctx, FSG_E_INVALID, "NULL array");
+    return FSG_OK;
+}
+
+KdeSegSizes kde_segmented_sizes(const fsg_points* X, int64_t n_seg, int64_t n_entries) {
+    KdeSegSizes z;
+    z.tile = kde_tile(X->D4);
+    z.max_items = n_entries / z.tile + n_seg + 1;
+    z.bounds = 3 * n_seg;
+    // segment item counts and offsets (n_seg + 1 each), their total, scan partials
+    z.counts = 2 * (n_seg + 1) + 1 + scan_partials(n_seg);
+    z.pairs = 2 * n_entries;
+    return z;
+}
+
+fsg_status kde_segmented_enqueue(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma,
+                                 int64_t n_seg, int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx,
+                                 const int32_t* lo, const int32_t* mid, const int32_t* hi, const int32_t* self_idx,
+                                 double* out_left, double* out_right, const KdeSegBufs& b) {
+    const KdeSegSizes z = kde_segmented_sizes(X, n_seg, n_entries);
+    FSG_HIP(ctx, launch_api_segments(lo, mid, hi, n_seg, b.bounds, b.segs, ctx->stream));
+    FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, z.tile, b.counts, b.items, b.n_items, z.max_items,
+                                    ctx->stream));
+    KdeArgs a = kde_args(Q, X, gamma);
+    a.q_idx = q_idx;
+    a.self_idx = self_idx;
+    a.self_mode = self_idx ? SELF_ARRAY : SELF_NONE;
+    a.bounds = b.bounds;
+    a.segs = b.segs;
+    a.items = b.items;
+    a.n_items = b.n_items;
+    a.out = b.pairs;
+    a.out_stride = 2;
+    FSG_HIP(ctx, launch_kde(a, z.max_items, ctx->num_cus, ctx->stream));
+    FSG_HIP(ctx, launch_split_pairs(b.pairs, n_entries, out_left, out_right, ctx->stream));
+    return FSG_OK;
 }
 
 // entries of a keep-threshold array for n entries
@@ -1197,6 +1254,7 @@ fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes
     c->stream = (hipStream_t)hip_stream;
     c->budget = ws_budget_bytes ? ws_budget_bytes : ((uint64_t)32 << 30);
     c->num_cus = prop.multiProcessorCount;
+    c->noalloc_scratch = noalloc_scratch_setup(device);  // with `device` current
     if (hipHostMalloc((void**)&c->host_scratch, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return FSG_E_NOMEM;
@@ -1414,48 +1472,20 @@ fsg_status fsg_kde_segmented(fsg_ctx* ctx, const fsg_points* Q, const fsg_points
                              int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx, const int32_t* lo,
                              const int32_t* mid, const int32_t* hi, const int32_t* self_idx, double* out_left,
                              double* out_right) {
-    if (!ctx) return FSG_E_INVALID;
-    if (!Q || !X) return set_error(ctx, FSG_E_INVALID, "NULL points");
-    if (Q->ctx != ctx || X->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
-    if (Q->d != X->d) return set_error(ctx, FSG_E_INVALID, "Q and X differ in d");
-    if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
-    if (n_seg < 0 || n_entries < 0) return set_error(ctx, FSG_E_INVALID, "negative count");
-    if (n_seg > 2147483647LL || n_entries > 2147483647LL)
-        return set_error(ctx, FSG_E_UNSUPPORTED, "more than 2^31-1 segments or entries");
-    if (n_seg == 0 || n_entries == 0) return FSG_OK;
-    if (!q_ptr || !q_idx || !lo || !mid || !hi || !out_left || !out_right)
-        return set_error(ctx, FSG_E_INVALID, "NULL array");
-    fsg_status st;
-    int32_t* bounds;
-    SegDesc* segs;
-    WorkItem* items;
-    int32_t* n_items;
-    int64_t* scratch;
-    double* pairs;
-    const int32_t tile = kde_tile(X->D4);
-    const int64_t max_items = n_entries / tile + n_seg + 1;
-    if ((st = ws(ctx, "seg_bounds", (size_t)(3 * n_seg), &bounds)) != FSG_OK) return st;
-    if ((st = ws(ctx, "seg_descs", (size_t)n_seg, &segs)) != FSG_OK) return st;
-    if ((st = ws(ctx, "seg_items", (size_t)max_items, &items)) != FSG_OK) return st;
-    if ((st = ws(ctx, "seg_nitems", 1, &n_items)) != FSG_OK) return st;
-    if ((st = ws(ctx, "seg_scratch", (size_t)(2 * (n_seg + 1) + 1 + scan_partials(n_seg)), &scratch)) != FSG_OK)
-        return st;
-    if ((st = ws(ctx, "seg_pairs", (size_t)(2 * n_entries), &pairs)) != FSG_OK) return st;
-    FSG_HIP(ctx, launch_api_segments(lo, mid, hi, n_seg, bounds, segs, ctx->stream));
-    FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, tile, scratch, items, n_items, max_items, ctx->stream));
-    KdeArgs a = kde_args(Q, X, gamma);
-    a.q_idx = q_idx;
-    a.self_idx = self_idx;
-    a.self_mode = self_idx ? SELF_ARRAY : SELF_NONE;
-    a.bounds = bounds;
-    a.segs = segs;
-    a.items = items;
-    a.n_items = n_items;
-    a.out = pairs;
-    a.out_stride = 2;
-    FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
-    FSG_HIP(ctx, launch_split_pairs(pairs, n_entries, out_left, out_right, ctx->stream));
-    return FSG_OK;
+    bool empty = false;
+    fsg_status st = kde_segmented_check(ctx, Q, X, gamma, n_seg, n_entries, q_ptr, q_idx, lo, mid, hi, out_left,
+                                        out_right, &empty);
+    if (st != FSG_OK || empty) return st;
+    const KdeSegSizes z = kde_segmented_sizes(X, n_seg, n_entries);
+    KdeSegBufs b;
+    if ((st = ws(ctx, "seg_bounds", (size_t)z.bounds, &b.bounds)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_descs", (size_t)n_seg, &b.segs)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_items", (size_t)z.max_items, &b.items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_nitems", 1, &b.n_items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_scratch", (size_t)z.counts, &b.counts)) != FSG_OK) return st;
+    if ((st = ws(ctx, "seg_pairs", (size_t)z.pairs, &b.pairs)) != FSG_OK) return st;
+    return kde_segmented_enqueue(ctx, Q, X, gamma, n_seg, n_entries, q_ptr, q_idx, lo, mid, hi, self_idx, out_left,
+                                 out_right, b);
 }
 
 fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int32_t L, uint64_t seed,

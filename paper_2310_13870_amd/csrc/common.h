@@ -185,6 +185,9 @@ struct fsg_ctx {
     std::set<fsg_graph*> graphs;
     std::vector<void*> retired;
     std::vector<void*> retired_host;
+    // device address of the no-allocation entry point's static scratch on
+    // this context's device (nullptr if it could not be located)
+    void* noalloc_scratch = nullptr;
 };
 
 
@@ -241,6 +244,36 @@ struct StageTimer {
 
 // Workspace buffer of at least `bytes`, keyed by name (reused across calls).
 fsg_status ws_get(fsg_ctx* ctx, const char* name, size_t bytes, void** out);
+// Segmented KDE (fsg_kde_segmented and its no-allocation variant): argument
+// checks, buffer sizes (elements) and the launches on given buffers.
+struct KdeSegSizes {
+    int32_t tile = 0;
+    int64_t max_items = 0;  // WorkItem
+    int64_t bounds = 0;     // int32
+    int64_t counts = 0;     // int64
+    int64_t pairs = 0;      // double
+};
+struct KdeSegBufs {
+    int32_t* bounds = nullptr;
+    SegDesc* segs = nullptr;  // [n_seg]
+    WorkItem* items = nullptr;
+    int32_t* n_items = nullptr;  // [1]
+    int64_t* counts = nullptr;
+    double* pairs = nullptr;
+};
+fsg_status kde_segmented_check(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma, int64_t n_seg,
+                               int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx, const int32_t* lo,
+                               const int32_t* mid, const int32_t* hi, const double* out_left,
+                               const double* out_right, bool* empty);
+KdeSegSizes kde_segmented_sizes(const fsg_points* X, int64_t n_seg, int64_t n_entries);
+fsg_status kde_segmented_enqueue(fsg_ctx* ctx, const fsg_points* Q, const fsg_points* X, double gamma,
+                                 int64_t n_seg, int64_t n_entries, const int64_t* q_ptr, const int32_t* q_idx,
+                                 const int32_t* lo, const int32_t* mid, const int32_t* hi, const int32_t* self_idx,
+                                 double* out_left, double* out_right, const KdeSegBufs& b);
+// The static scratch of the no-allocation entry point: its device address on
+// `device` (looked up once per device, with that device current), or nullptr.
+void* noalloc_scratch_setup(int device);
+
 // Free a device block (hipMalloc) or pinned host block (hipHostMalloc) of the
 // context, or park it while a recorded graph may name it.
 void dev_free(fsg_ctx* ctx, void* p);
