@@ -508,7 +508,7 @@ def run_leg(ctx, w, Xd, prec, steps, warmup, args):
     ctx.set_profiling(False)
     kept, scanned = ctx.filter_stats()
     stages = {}
-    for name in ("prep", "kde_mask", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
+    for name in ("prep", "prune", "kde_mask", "mask_convert", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
         ms, cnt = ctx.stage_time(name)
         if cnt:
             stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / steps,
@@ -602,6 +602,8 @@ def main():
     ap.add_argument("--oracle-rows", type=int, default=0,
                     help="oracle rows (0: the workload's stated subsample, else a sample of --cpu-seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pruning", action="store_true",
+                    help="precision mode: scan every (query tile, column) pair (no tile pruning)")
     ap.add_argument("--levels-per-pass", type=int, default=0,
                     help="cap on the tree levels one binned pass resolves (0: the library's choice)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -635,6 +637,8 @@ def main():
     ctx = fsg.Context(0)
     if args.levels_per_pass:
         ctx.set_levels_per_pass(args.levels_per_pass)
+    if args.no_pruning:
+        ctx.set_pruning(False)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -670,7 +674,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": d, "L": L, "sigma": w.sigma, "gamma": w.gamma,
                    "components": w.n_comp, "precision": precs[0],
-                   "precision_detail": PRECISION_NOTE[precs[0]]},
+                   "precision_detail": PRECISION_NOTE[precs[0]], "tile_pruning": not args.no_pruning},
         "kernel_evals_per_s": head["kde"]["kernel_evals_per_s"],
         "pairs_scanned_per_s": head["kde"]["pairs_scanned_per_s"],
         "pairs_resolved_per_s": head["kde"]["pairs_resolved_per_s"],

@@ -95,7 +95,9 @@ uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
 /* Stage timing.  When enabled, the context records a pair of HIP events on
  * its stream around every stage it launches; fsg_ctx_stage_time synchronises
  * the stream and returns the summed elapsed time (ms) and the number of
- * launches of one stage since the last reset.  Stages: "prep", "kde_root"
+ * launches of one stage since the last reset.  Stages: "prep", "prune" (the
+ * precision mode's tile pruning plan), "kde_mask" (its BF16 keep-mask scan),
+ * "mask_convert" (keep bits back to index order), "kde_root"
  * (the binned KDE over all points), "kde_pass" (binned KDE of later passes),
  * "descend" (descent over bins), "group" (sample sort by node), "leaf"
  * (leaf stage), "csr" (reweighting and CSR).  Unknown names report 0. */
@@ -107,6 +109,18 @@ fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);
  * *scanned = (data column, 64-query tile) pairs it examined.  Synchronises the
  * stream. */
 fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned);
+
+/* Tile pruning of the precision mode (default on): before the BF16 keep-mask
+ * scan of a pass over all points, each 64-query tile is checked against the
+ * cells of the 256 pivots (points grouped by nearest pivot, each with an upper
+ * bound on its radius); by the triangle inequality a (tile, cell) pair whose
+ * every query is farther than radius + sqrt(T_q) from the cell's pivot --
+ * T_q the largest squared distance the keep test can accept for query q --
+ * cannot keep a column and is not scanned.  The kept set, and so every
+ * result, is the same with and without it; on well-separated clusters the
+ * scan shrinks to the tiles' own clusters (Section 1 and Theorem 1 rely on a
+ * KDE that is fast on such data).  Off: every pair is scanned. */
+fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled);
 
 /* Cap the number of tree levels one binned KDE pass resolves (0 restores the
  * automatic choice, which is bounded by the workspace budget).  Results do not

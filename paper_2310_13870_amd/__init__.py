@@ -39,6 +39,7 @@ _lib_fns = dict(
     fsg_ctx_sync=_sig("fsg_ctx_sync", ctypes.c_int, _vp),
     fsg_ctx_workspace_bytes=_sig("fsg_ctx_workspace_bytes", _u64, _vp),
     fsg_ctx_set_levels_per_pass=_sig("fsg_ctx_set_levels_per_pass", ctypes.c_int, _vp, _i32),
+    fsg_ctx_set_pruning=_sig("fsg_ctx_set_pruning", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_stage_time=_sig("fsg_ctx_stage_time", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_dbl),
                             ctypes.POINTER(_i64)),
@@ -133,6 +134,10 @@ class Context:
     def set_levels_per_pass(self, max_levels: int):
         """Cap the tree levels one binned pass resolves (0 = automatic)."""
         self.check(_lib.fsg_ctx_set_levels_per_pass(self._h, max_levels))
+
+    def set_pruning(self, enabled: bool):
+        """Precision mode: skip (query tile, cell) pairs that cannot keep a column (default on)."""
+        self.check(_lib.fsg_ctx_set_pruning(self._h, 1 if enabled else 0))
 
     def set_profiling(self, enabled: bool):
         self.check(_lib.fsg_ctx_set_profiling(self._h, 1 if enabled else 0))

@@ -420,6 +420,69 @@ fsg_status kde_segmented_enqueue(fsg_ctx* ctx, const fsg_points* Q, const fsg_po
 // entries of a keep-threshold array for n entries
 static int64_t theta_entries(int64_t n) { return (n + kThetaPad - 1) / kThetaPad * kThetaPad; }
 
+// The keep masks of a root pass (m: the full scan's arguments, mask in index
+// order) from the pruned scan: cells the tiles may keep columns of, work items
+// over the data in pivot order, the scan, and the conversion of its keep bits
+// to index order.  The kept set equals the full scan's.
+static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const MaskArgs& m0) {
+    fsg_status st;
+    const int64_t n = X->n;
+    const int TP = mask_tiles_per_item(m0.KB);
+    PruneArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.X = X->X;
+    pa.n = n;
+    pa.d = X->d;
+    pa.P = X->P;
+    pa.order = X->order;
+    pa.qnorm = X->norm;
+    pa.dmin = X->dmin;
+    pa.xmax = X->xmax;
+    pa.margin_z = m0.margin_z;
+    pa.eps = m0.eps;
+    pa.gamma = m0.gamma;
+    pa.cell_pivot = X->cell_pivot;
+    pa.pnorm = X->pnorm;
+    pa.prad = X->prad;
+    pa.cell_start = X->cell_start;
+    pa.n_tiles = m0.n_tiles;
+    pa.words = (X->P + 31) / 32;
+    pa.TP = TP;
+    pa.n_groups = (m0.n_tiles + TP - 1) / TP;
+    pa.max_blocks = (int32_t)std::min<int64_t>(m0.blocks_per_chunk, 1 << 20);
+    const int64_t n_blocks_p = theta_entries(n) / 16;
+    const int64_t max_items = pa.n_groups * prune_max_items_per_group(pa.P, n_blocks_p, pa.max_blocks);
+    int64_t* partials;
+    uint16_t* maskp;
+    if ((st = ws(ctx, "prune_surv", (size_t)(pa.n_tiles * pa.words), &pa.surv)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_counts", (size_t)pa.n_groups + 1, &pa.counts)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_offsets", (size_t)pa.n_groups + 1, &pa.offsets)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_total", 1, &pa.total)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_partials", (size_t)scan_partials(pa.n_groups + 1), &partials)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_items", (size_t)(3 * max_items), &pa.items)) != FSG_OK) return st;
+    if ((st = ws(ctx, "keep_mask_pivot", (size_t)(m0.n_tiles * n_blocks_p), &maskp)) != FSG_OK) return st;
+    pa.scanned = m0.kept ? m0.kept + 1 : nullptr;
+    {
+        StageTimer t(ctx, "prune");
+        FSG_HIP(ctx, launch_prune_plan(pa, ctx->stream));
+        FSG_HIP(ctx, launch_prune_items(pa, partials, ctx->stream));
+    }
+    MaskArgs m = m0;
+    m.Xb = X->Xbp;
+    m.xa = X->xap;
+    m.mask = maskp;
+    m.n_blocks = n_blocks_p;
+    m.list = pa.items;
+    m.n_list = pa.total;
+    {
+        StageTimer t(ctx, "kde_mask");
+        FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));
+    }
+    StageTimer t(ctx, "mask_convert");
+    FSG_HIP(ctx, launch_mask_to_index(pa, maskp, n_blocks_p, m0.mask, m0.n_blocks, ctx->stream));
+    return FSG_OK;
+}
+
 // Binned KDE of all n points against the nodes of tree level D (one segment).
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
@@ -467,9 +530,11 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
             FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
         }
         m.kept = ctx->filter_counts;
-        // pairs examined: every data column once per 64-query tile
-        FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, tiles * n, ctx->stream));
-        {
+        if (ctx->pruning && X->Xbp) {
+            if ((st = pruned_keep_mask(ctx, X, m)) != FSG_OK) return st;
+        } else {
+            // pairs examined: every data column once per 64-query tile
+            FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, tiles * n, ctx->stream));
             StageTimer t(ctx, "kde_mask");
             FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));
         }
@@ -549,21 +614,42 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if (pts_alloc(p, (size_t)n, &p->order) != hipSuccess) return fail("pivot order");
     if (pts_alloc(p, 1, &p->xmax) != hipSuccess) return fail("norm bound");
     if (pts_alloc(p, (size_t)p->n_pad, &p->xa) != hipSuccess) return fail("norm terms");
-    p->bytes += split_bytes + q_split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) +
-                p->n_pad * sizeof(float);
+    const int32_t P = (int32_t)(n < 256 ? n : 256);
+    p->P = P;
+    char* xbp = nullptr;
+    if (pts_alloc(p, q_split_bytes, &xbp) != hipSuccess) return fail("split operands");
+    p->Xbp = xbp;
+    if (pts_alloc(p, (size_t)q_rows, &p->xap) != hipSuccess) return fail("norm terms");
+    if (pts_alloc(p, (size_t)P + 1, &p->cell_start) != hipSuccess) return fail("cell table");
+    if (pts_alloc(p, (size_t)P, &p->cell_pivot) != hipSuccess) return fail("cell table");
+    if (pts_alloc(p, (size_t)P, &p->pnorm) != hipSuccess) return fail("cell table");
+    if (pts_alloc(p, (size_t)P, &p->prad) != hipSuccess) return fail("cell table");
+    p->bytes += split_bytes + 2 * q_split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) +
+                p->n_pad * sizeof(float) + q_rows * sizeof(float) + (4 * (size_t)P + 1) * 4;
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
     if (st != FSG_OK) return st;
     double* part;
     if ((st = ws(ctx, "max_norm_parts", (size_t)max_norm_parts(n), &part)) != FSG_OK) return st;
+    uint16_t* d16;
+    int32_t* rank;
+    if ((st = ws(ctx, "pivot_dist16", (size_t)P * P, &d16)) != FSG_OK) return st;
+    if ((st = ws(ctx, "pivot_rank", (size_t)P, &rank)) != FSG_OK) return st;
     StageTimer t(ctx, "prep");
     FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->xa, ctx->stream));
-    const int32_t P = (int32_t)(n < 256 ? n : 256);
     FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
+    // cells labelled along a nearest-neighbour chain of the pivots, so that
+    // neighbouring cells of the pivot order are close together
+    FSG_HIP(ctx, launch_pivot_chain(p->X, n, p->d, P, d16, rank, p->cell_pivot, label, ctx->stream));
     FSG_HIP(ctx, radix_sort_u32(label, p->order, n, 8, b, ctx->stream));
     FSG_HIP(ctx, launch_prep_query_split(p->X, p->order, n, p->d, KB, q_rows, p->Qb, ctx->stream));
     FSG_HIP(ctx, launch_max_norm(p->norm, n, part, p->xmax, ctx->stream));
+    // the pruned scan: cells of the pivot order, data operands in that order
+    FSG_HIP(ctx, launch_node_starts(label, n, P, p->cell_start, ctx->stream));
+    FSG_HIP(ctx, launch_prep_split_order(p->X, p->norm, p->order, n, p->d, KB, q_rows, p->Xbp, p->xap, ctx->stream));
+    FSG_HIP(ctx, launch_cell_geometry(p->X, p->d, P, p->dmin, p->order, p->cell_start, p->cell_pivot, p->pnorm,
+                                      p->prad, ctx->stream));
     return FSG_OK;
 }
 
@@ -1273,7 +1359,8 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
     // live point sets stay valid: their pooled blocks become theirs to free
     for (fsg_points* p : ctx->points) {
         for (void* v : {(void*)p->Xp, (void*)p->norm, (void*)p->Xb, (void*)p->Qb, (void*)p->dmin, (void*)p->order,
-                        (void*)p->xmax, (void*)p->xa})
+                        (void*)p->xmax, (void*)p->xa, (void*)p->Xbp, (void*)p->xap, (void*)p->cell_start,
+                        (void*)p->cell_pivot, (void*)p->pnorm, (void*)p->prad})
             if (v) ctx->pool_size.erase(v);
         for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
         p->ctx = nullptr;
@@ -1318,6 +1405,12 @@ fsg_status fsg_ctx_sync(fsg_ctx* ctx) {
 }
 
 uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled) {
+    if (!ctx) return FSG_E_INVALID;
+    ctx->pruning = enabled != 0;
+    return FSG_OK;
+}
 
 fsg_status fsg_ctx_set_levels_per_pass(fsg_ctx* ctx, int32_t max_levels) {
     if (!ctx) return FSG_E_INVALID;
@@ -1445,6 +1538,12 @@ void fsg_points_destroy(fsg_points* p) {
     pts_free(p, p->order);
     pts_free(p, p->xmax);
     pts_free(p, p->xa);
+    pts_free(p, p->Xbp);
+    pts_free(p, p->xap);
+    pts_free(p, p->cell_start);
+    pts_free(p, p->cell_pivot);
+    pts_free(p, p->pnorm);
+    pts_free(p, p->prad);
     for (auto& kv : p->levels) pts_free(p, kv.second);
     delete p;
 }

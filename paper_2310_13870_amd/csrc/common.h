@@ -111,6 +111,41 @@ struct MaskArgs {
     const int64_t* job_item_off;
     int32_t n_jobs;
     int64_t n_items_total;
+    // pruned scan: work items {first tile, first block, end block} of the
+    // data in pivot order (Xb, xa, mask then refer to that order), their
+    // number on the device
+    const int32_t* list;
+    const int64_t* n_list;
+};
+
+// Tile pruning ahead of the keep-mask scan (kde_prune.hip).
+struct PruneArgs {
+    const float* X;            // FP32 points, row-major n x d
+    int64_t n;
+    int32_t d;
+    int32_t P;                 // pivots (= cells)
+    const int32_t* cell_pivot; // [P]: the point that is the pivot of cell c
+    const int32_t* order;      // entry (pivot order) -> point
+    const double* qnorm;       // FP64 |x|^2 per point
+    const double* dmin;        // per point: upper bound on its smallest squared distance
+    const double* xmax;        // device scalar: max |x|
+    double margin_z;           // Delta
+    double eps;                // relative error bound of the split cross term
+    double gamma;
+    const float* pnorm;        // FP32 |p_c|^2 per cell
+    const float* prad;         // upper bound on each cell's radius
+    const int32_t* cell_start; // [P + 1]: cell c holds entries [cell_start[c], cell_start[c+1])
+    int64_t n_tiles;           // 64-entry query tiles
+    int32_t words;             // 32-bit words of a tile's cell set, (P + 31) / 32 <= 8
+    uint32_t* surv;            // [n_tiles][words]: cells a tile may keep columns of
+    int32_t TP;                // tiles per keep-mask work item
+    int64_t n_groups;          // groups of TP tiles
+    int32_t max_blocks;        // blocks per work item at most
+    int64_t* counts;           // [n_groups + 1] items per group
+    int64_t* offsets;          // [n_groups + 1] exclusive scan of counts
+    int64_t* total;            // device scalar: the number of items
+    int32_t* items;            // [3 x items]
+    int64_t* scanned;          // optional: adds the scanned (column, tile) pairs
 };
 
 constexpr int kThetaPad = 128;  // padding of MaskArgs::ntheta: a whole number of tile groups
@@ -155,6 +190,8 @@ struct fsg_ctx {
     std::vector<hipEvent_t> free_events;
     // cap on the tree levels one binned pass resolves (0: automatic)
     int max_levels_per_pass = 0;
+    // precision mode: skip (query tile, cell) pairs that cannot keep a column
+    bool pruning = true;
     // precision-mode statistics (device counters)
     int64_t* filter_counts = nullptr;  // [kept, scanned]
     // live point sets; detached (their ctx cleared) when the context is destroyed
@@ -209,6 +246,17 @@ struct fsg_points {
     double* dmin = nullptr;    // upper bound on each point's smallest squared distance
     int32_t* order = nullptr;  // points ordered by nearest pivot
     double* xmax = nullptr;    // device scalar: max |x|
+    // precision mode, pruned scan: data-side split fragments and -|x|^2/2 in
+    // pivot order (rows as Qb), the cells of the pivots (entries
+    // [cell_start[c], cell_start[c+1]) are nearest to pivot c), each pivot's
+    // FP32 squared norm and an upper bound on each cell's radius
+    void* Xbp = nullptr;
+    float* xap = nullptr;
+    int32_t* cell_start = nullptr;
+    int32_t* cell_pivot = nullptr;
+    float* pnorm = nullptr;
+    float* prad = nullptr;
+    int32_t P = 0;
     // tree level boundaries, computed on demand: level -> int32 [2^level + 1]
     std::map<int, int32_t*> levels;
     size_t bytes = 0;
@@ -313,6 +361,18 @@ hipError_t launch_prep_query_split(const float* X, const int32_t* order, int64_t
                                    int64_t rows, void* Qb, hipStream_t st);
 hipError_t launch_pivots(const float* X, int64_t n, int32_t d, int32_t P, double* dmin, uint32_t* label, int32_t* ids,
                          hipStream_t st);
+hipError_t launch_prep_split_order(const float* X, const double* norm, const int32_t* order, int64_t n, int32_t d,
+                                   int32_t KB, int64_t rows, void* Xbp, float* xap, hipStream_t st);
+hipError_t launch_pivot_chain(const float* X, int64_t n, int32_t d, int32_t P, uint16_t* D16, int32_t* rank,
+                              int32_t* cell_pivot, uint32_t* label, hipStream_t st);
+hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const double* dmin, const int32_t* order,
+                                const int32_t* cell_start, const int32_t* cell_pivot, float* pnorm, float* prad,
+                                hipStream_t st);
+hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st);
+hipError_t launch_prune_items(const PruneArgs& a, int64_t* partials, hipStream_t st);
+int64_t prune_max_items_per_group(int32_t P, int64_t n_blocks_p, int32_t max_blocks);
+hipError_t launch_mask_to_index(const PruneArgs& a, const uint16_t* maskp, int64_t n_blocks_p, uint16_t* mask,
+                                int64_t n_blocks, hipStream_t st);
 int max_norm_parts(int64_t n);  // partial maxima launch_max_norm needs in `part`
 hipError_t launch_max_norm(const double* norm, int64_t n, double* part, double* out, hipStream_t st);
 int filter_steps(int D4);

@@ -45,8 +45,13 @@ int64_t keep_mask_waves(int KB, int num_cus) {
 // no swizzle, no index stride.
 constexpr int kBufferFlags = 0x00020000;
 
-template <int KB, int TP, int WAVES, bool MULTI>
+// Work items: MODE 0 = (tile group, chunk of blocks) of one point set; 1 =
+// the same over the point sets of a multi-set launch; 2 = a list of
+// {first tile, first block, end block} (the pruned scan over the data in
+// pivot order, whose number is read from the device).
+template <int KB, int TP, int WAVES, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m0) {
+    constexpr bool MULTI = MODE == 1;
     // Queries are the A operand and data the B operand, so lane l receives
     // query rows 4(l/16) + i of a query block and data column l % 16: a column
     // is kept for a tile when any of the 4 lane groups sees a compare succeed
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int grp = lane >> 4;
     const int r = lane & 15;
-    const int64_t n_items = MULTI ? m0.n_items_total : mask_items(m0);
+    const int64_t n_items = MULTI ? m0.n_items_total : (MODE == 2 ? *m0.n_list : mask_items(m0));
     int64_t kept = 0;
     for (int64_t it = wave; it < n_items; it += n_waves) {
         int64_t local = it;
@@ -74,8 +79,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             local = it - m0.job_item_off[job];
         }
         const MaskArgs& m = MULTI ? m0.jobs[job] : m0;
-        const int64_t n_groups = (m.n_tiles + TP - 1) / TP;
-        const int64_t chunk = local / n_groups, tile0 = (local - chunk * n_groups) * TP;
+        int64_t tile0;
+        int32_t bb, be;  // the item's blocks [bb, be)
+        if constexpr (MODE == 2) {
+            const int32_t* li = m.list + 3 * it;
+            tile0 = li[0];
+            bb = li[1];
+            be = li[2];
+        } else {
+            // block indices fit in 32 bits (n < 2^31 columns), so that the
+            // loop control stays on the scalar unit
+            const int64_t n_groups = (m.n_tiles + TP - 1) / TP;
+            const int64_t chunk = local / n_groups;
+            tile0 = (local - chunk * n_groups) * TP;
+            bb = (int32_t)(chunk * m.blocks_per_chunk);
+            be = (int32_t)min(m.n_blocks, (int64_t)bb + m.blocks_per_chunk);
+        }
         const int64_t e0 = tile0 * kTileQ;
         const int32_t ne = (int32_t)min((int64_t)(TP * kTileQ), m.n_entries - e0);
         bf16x8_t qb16[QB][KB];
@@ -97,10 +116,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
             ntheta[qb] = *(const float4_t*)(m.ntheta + e0 + 16 * qb + 4 * grp);
         }
         __builtin_amdgcn_wave_barrier();
-        // block indices fit in 32 bits (n < 2^31 columns), so that the loop
-        // control stays on the scalar unit
-        const int32_t bb = (int32_t)(chunk * m.blocks_per_chunk);
-        const int32_t be = (int32_t)min(m.n_blocks, (int64_t)bb + m.blocks_per_chunk);
         const int32_t n_data = (int32_t)m.n_data;
         const int32_t n_live = (int32_t)min((int64_t)TP, m.n_tiles - tile0);  // tiles of this item that exist
         uint16_t* mrow = m.mask + tile0 * m.n_blocks;
@@ -283,10 +298,14 @@ static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) 
     int64_t waves = (int64_t)num_cus * 4 * WAVES;
     if (n_items < waves) waves = n_items;
     if (waves < 1) waves = 1;
-    if (m.jobs)
-        kde_keep_mask_kernel<KB, TP, WAVES, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
-    else
-        kde_keep_mask_kernel<KB, TP, WAVES, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    if (m.list) {
+        waves = (int64_t)num_cus * 4 * WAVES;  // the item count is on the device
+        kde_keep_mask_kernel<KB, TP, WAVES, 2><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    } else if (m.jobs) {
+        kde_keep_mask_kernel<KB, TP, WAVES, 1><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    } else {
+        kde_keep_mask_kernel<KB, TP, WAVES, 0><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+    }
     return hipGetLastError();
 }
 

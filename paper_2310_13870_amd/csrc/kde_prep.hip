@@ -99,6 +99,23 @@ __global__ void prep_query_split_kernel(const float* __restrict__ X, const int32
     Qb[idx] = split_fragment(X, e < n ? (int64_t)order[e] : -1, d, kb, lane, true);
 }
 
+// data-side fragments and -|x|^2/2 in entry (pivot) order: the operands of
+// the pruned keep-mask scan (zero rows past the last entry)
+__global__ void prep_split_order_kernel(const float* __restrict__ X, const double* __restrict__ norm,
+                                        const int32_t* __restrict__ order, int64_t n, int32_t d, int32_t KB,
+                                        int64_t rows, int64_t total, bf16x8_t* __restrict__ Xbp,
+                                        float* __restrict__ xap) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < rows) xap[idx] = (idx < n) ? (float)(-0.5 * norm[order[idx]]) : 0.0f;
+    if (idx >= total) return;
+    const int64_t per_blk = (int64_t)KB * 64;
+    const int64_t blk = idx / per_blk;
+    const int32_t rem = (int32_t)(idx - blk * per_blk);
+    const int32_t kb = rem >> 6, lane = rem & 63;
+    const int64_t e = blk * 16 + (lane & 15);
+    Xbp[idx] = split_fragment(X, e < n ? (int64_t)order[e] : -1, d, kb, lane, false);
+}
+
 // dmin[i] = an upper bound on min_{j != i} |x_i - x_j|^2 over P pivot points
 // (indices floor(p n / P)); label[i] = the nearest pivot.  The squared
 // distances come from FP32 norms and cross terms, |x|^2 + |p|^2 - 2 x.p (one
@@ -216,6 +233,17 @@ hipError_t launch_prep_query_split(const float* X, const int32_t* order, int64_t
     if (total == 0) return hipSuccess;
     prep_query_split_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, order, n, d, KB, total,
                                                                              (bf16x8_t*)Qb);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_split_order(const float* X, const double* norm, const int32_t* order, int64_t n, int32_t d,
+                                   int32_t KB, int64_t rows, void* Xbp, float* xap, hipStream_t st) {
+    if (rows % 16 != 0 || rows < n) return hipErrorInvalidValue;
+    const int64_t total = (rows / 16) * KB * 64;
+    const int64_t threads = total > rows ? total : rows;
+    if (threads == 0) return hipSuccess;
+    prep_split_order_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(X, norm, order, n, d, KB, rows, total,
+                                                                               (bf16x8_t*)Xbp, xap);
     return hipGetLastError();
 }
 

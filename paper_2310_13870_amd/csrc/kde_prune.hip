@@ -1,0 +1,372 @@
+// Lossless tile pruning ahead of the keep-mask scan of the precision mode.
+//
+// The points are grouped into cells by their nearest pivot (the pivot order
+// the query tiles already use).  For a cell c with pivot p_c and a radius r_c
+// (an upper bound on |x - p_c| over its members) and a query q, the triangle
+// inequality gives |q - x| >= |q - p_c| - r_c for every member x.  The keep
+// test of the scan can pass for a pair only if its squared distance is at
+// most
+//     T_q = dmin_q (1 + 1e-6) + Delta / gamma + 4 E_q + 2^-20 |theta_q|
+// (the threshold of the test, its error bound E_q counted on both sides of
+// the comparison, and the FP32 rounding of theta_q), so a (query tile, cell)
+// pair with |q - p_c| > r_c + sqrt(T_q) for all queries of the tile cannot
+// keep any column: the scan skips it, and the kept set -- hence every mass --
+// is the same as with the full scan.  This is the first pruning step towards
+// the sub-quadratic KDE regime the paper relies on (Section 1 and Theorem 1
+// use an approximate KDE; here the pruning is exact).
+//
+// Steps per call: (1) a plan kernel marks the cells each 64-query tile may
+// keep columns of; (2) the cells of each group of tiles are merged into runs
+// of 16-column blocks of the data in pivot order, cut into work items; (3)
+// the keep-mask kernel scans those items on data operands in pivot order
+// (kde_mask.hip); (4) a conversion kernel writes each tile's keep bits back
+// in index order, which the exact pass reads.
+#include "common.h"
+#include "device.h"
+
+namespace fsg {
+
+// the smallest float >= v (v finite, >= 0): one step up when the rounding
+// went down (the next float above a non-negative one has the next bit pattern)
+__device__ __forceinline__ float float_up(double v) {
+    float f = (float)v;
+    if ((double)f < v) f = __int_as_float(__float_as_int(f) + 1);
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// Pivot chain (once per point set): new labels for the pivots such that
+// consecutive labels are near each other -- a greedy nearest-neighbour chain
+// from pivot 0 over the pivots' squared distances (FP32, truncated to their
+// upper 16 bits, which keeps their order).  Cells are laid out in label
+// order, so neighbouring cells are close and a 64-query tile that spans two
+// cells stays within one cluster.  Only the layout depends on the chain,
+// never a result.
+// ---------------------------------------------------------------------------
+constexpr int kMaxPivots = 256;
+
+__global__ __launch_bounds__(256) void pivot_dist_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t P,
+                                                         uint16_t* __restrict__ D16) {
+    const int32_t a = blockIdx.x, b = threadIdx.x;
+    if (b >= P) return;
+    const float* pa = X + ((int64_t)a * n / P) * d;
+    const float* pb = X + ((int64_t)b * n / P) * d;
+    float s = 0.0f;
+    for (int32_t t = 0; t < d; ++t) {
+        const float u = pa[t] - pb[t];
+        s = __builtin_fmaf(u, u, s);
+    }
+    D16[a * P + b] = (uint16_t)(__float_as_uint(s) >> 16);
+}
+
+// one wave: lane l holds candidates l, l + 64, l + 128, l + 192
+__global__ __launch_bounds__(64) void pivot_chain_kernel(const uint16_t* __restrict__ D16, int32_t P, int64_t n,
+                                                         int32_t* __restrict__ rank, int32_t* __restrict__ cell_pivot) {
+    __shared__ uint16_t dl[kMaxPivots * kMaxPivots];
+    const int lane = threadIdx.x;
+    for (int32_t k = lane; k < P * P; k += 64) dl[k] = D16[k];
+    __syncthreads();
+    uint32_t visited = (lane == 0) ? 1u : 0u;
+    int32_t cur = 0;
+    if (lane == 0) {
+        rank[0] = 0;
+        cell_pivot[0] = 0;
+    }
+    for (int32_t s = 1; s < P; ++s) {
+        // key = distance bits << 8 | candidate: the smallest is the nearest
+        // unvisited pivot (ties to the lower index)
+        uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t j = lane + 64 * i;
+            if (j < P && !((visited >> i) & 1u)) key = min(key, ((uint32_t)dl[cur * P + j] << 8) | (uint32_t)j);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) key = min(key, (uint32_t)__shfl_xor((int)key, off));
+        const int32_t next = (int32_t)(key & 255u);
+        if (lane == 0) {
+            rank[next] = s;
+            cell_pivot[s] = (int32_t)((int64_t)next * n / P);
+        }
+        if ((next & 63) == lane) visited |= 1u << (next >> 6);
+        cur = next;
+    }
+}
+
+__global__ void relabel_kernel(uint32_t* __restrict__ label, int64_t n, const int32_t* __restrict__ rank) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) label[i] = (uint32_t)rank[label[i]];
+}
+
+hipError_t launch_pivot_chain(const float* X, int64_t n, int32_t d, int32_t P, uint16_t* D16, int32_t* rank,
+                              int32_t* cell_pivot, uint32_t* label, hipStream_t st) {
+    if (P < 1 || P > kMaxPivots) return hipErrorInvalidValue;
+    pivot_dist_kernel<<<(unsigned)P, 256, 0, st>>>(X, n, d, P, D16);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pivot_chain_kernel<<<1, 64, 0, st>>>(D16, P, n, rank, cell_pivot);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    relabel_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(label, n, rank);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cell geometry (once per point set): the pivot's squared norm in FP32 (four
+// partial sums, as the plan kernel forms norms) and an upper bound on the
+// cell's radius.  dmin[i] is an upper bound on |x_i - p_label(i)|^2 (the
+// pivot kernel's distance to the nearest pivot, whose point is
+// cell_pivot[c]), so the largest dmin over a cell's members bounds its
+// squared radius.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cell_geometry_kernel(const float* __restrict__ X, int32_t d,
+                                                            const double* __restrict__ dmin,
+                                                            const int32_t* __restrict__ order,
+                                                            const int32_t* __restrict__ cell_start,
+                                                            const int32_t* __restrict__ cell_pivot,
+                                                            float* __restrict__ pnorm, float* __restrict__ prad) {
+    __shared__ double red[256];
+    const int32_t c = blockIdx.x;
+    const int32_t cs = cell_start[c], ce = cell_start[c + 1];
+    double m = 0.0;
+    for (int32_t e = cs + (int32_t)threadIdx.x; e < ce; e += 256) m = fmax(m, dmin[order[e]]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    prad[c] = float_up(__builtin_sqrt(red[0]) * (1.0 + 0x1p-40));
+    const float* pc = X + (int64_t)cell_pivot[c] * d;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t t = 0; t < d; ++t) acc[t & 3] = __builtin_fmaf(pc[t], pc[t], acc[t & 3]);
+    pnorm[c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const double* dmin, const int32_t* order,
+                                const int32_t* cell_start, const int32_t* cell_pivot, float* pnorm, float* prad,
+                                hipStream_t st) {
+    if (P < 1) return hipErrorInvalidValue;
+    cell_geometry_kernel<<<(unsigned)P, 256, 0, st>>>(X, d, dmin, order, cell_start, cell_pivot, pnorm, prad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// (1) Plan: bit c of surv[t] is set when some query of tile t may keep a
+// column of cell c.  One wave per tile, a lane per query entry; the pivot
+// coordinates are read with wave-uniform addresses.  The squared distance to
+// the pivot is bounded from below from FP32 norms and cross terms (four
+// partial sums each): their errors and the roundings that combine them stay
+// below (d + 32) 2^-24 (|q|^2 + |p|^2) (as in the pivot kernel), and the last
+// fused multiply-add adds at most 2^-24 of the same magnitude, so subtracting
+// (d + 40) 2^-24 (|q|^2 + |p|^2) gives a lower bound D_lb.  A keep is
+// possible iff D_lb <= (r_c + sqrt(T_q))^2, the right side rounded up.
+// ---------------------------------------------------------------------------
+template <int DMAX>
+__global__ __launch_bounds__(256) void prune_plan_kernel(PruneArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));
+    if (t >= a.n_tiles) return;
+    const int64_t e = t * kTileQ + lane;
+    const bool valid = e < a.n;
+    const int32_t d = a.d;
+    const int32_t p = valid ? a.order[e] : 0;
+    float q[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) q[k] = (valid && k < d) ? a.X[(int64_t)p * d + k] : 0.0f;
+    float qn;
+    {
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < DMAX; ++k) acc[k & 3] = __builtin_fmaf(q[k], q[k], acc[k & 3]);
+        qn = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+    // square root of the largest squared distance a kept pair can have
+    float sT = 0.0f;
+    if (valid) {
+        const double xmax = *a.xmax;
+        const double nq = a.qnorm[p];
+        const double dm = a.dmin[p] * (1.0 + 1e-6);
+        const double err = a.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
+        const double th = 0.5 * nq - 0.5 * dm - a.margin_z / (2.0 * a.gamma) - err;
+        double T = dm + a.margin_z / a.gamma + 4.0 * err + 0x1p-20 * __builtin_fabs(th);
+        T *= 1.0 + 0x1p-30;
+        sT = float_up(__builtin_sqrt(T) * (1.0 + 0x1p-40));
+    }
+    const float sl = (float)(d + 40) * 0x1p-24f;
+    const int32_t P = a.P;
+    uint32_t word = 0;
+    for (int32_t c = 0; c < P; ++c) {
+        const int32_t cs = a.cell_start[c], ce = a.cell_start[c + 1];
+        bool need = false;
+        if (ce > cs) {
+            const float* pc = a.X + (int64_t)a.cell_pivot[c] * d;
+            float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k)
+                if (k < d) acc[k & 3] = __builtin_fmaf(q[k], pc[k], acc[k & 3]);
+            const float dot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            const float s = qn + a.pnorm[c];
+            const float dlb = __builtin_fmaf(-sl, s, __builtin_fmaf(-2.0f, dot, s));
+            const float lim = a.prad[c] + sT;
+            need = valid && dlb <= lim * lim * (1.0f + 0x1p-20f);
+        }
+        if (__ballot(need) != 0) word |= 1u << (c & 31);
+        if ((c & 31) == 31 || c == P - 1) {
+            if (lane == 0) a.surv[t * a.words + (c >> 5)] = word;
+            word = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (2) Work items of the pruned scan: per group of TP tiles, the cells any of
+// its tiles may keep, in pivot order, as runs of 16-column blocks (cells
+// sharing or touching a block merge into one run), cut into items of at most
+// max_blocks blocks: {first tile, first block, end block}.  One thread per
+// group, run twice: to count the items, and to write them at the group's
+// offset.  The count pass also adds the scanned (column, tile) pairs to the
+// filter statistics.
+// ---------------------------------------------------------------------------
+__device__ int64_t group_items(const PruneArgs& a, int64_t g, int32_t* out) {
+    const int64_t t0 = g * a.TP;
+    const int64_t tl = min((int64_t)a.TP, a.n_tiles - t0);
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint32_t v = 0;
+        if (k < a.words)
+            for (int64_t t = t0; t < t0 + tl; ++t) v |= a.surv[t * a.words + k];
+        w[k] = v;
+    }
+    int64_t items = 0, blocks = 0;
+    int64_t rb0 = -1, rb1 = -1;
+    auto emit = [&](int64_t b0, int64_t b1) {
+        for (int64_t s = b0; s < b1; s += a.max_blocks) {
+            if (out) {
+                out[3 * items] = (int32_t)t0;
+                out[3 * items + 1] = (int32_t)s;
+                out[3 * items + 2] = (int32_t)min(b1, s + a.max_blocks);
+            }
+            ++items;
+        }
+        blocks += b1 - b0;
+    };
+    for (int32_t c = 0; c < a.P; ++c) {
+        if (!((w[c >> 5] >> (c & 31)) & 1u)) continue;
+        const int32_t cs = a.cell_start[c], ce = a.cell_start[c + 1];
+        if (ce <= cs) continue;
+        const int64_t b0 = cs >> 4, b1 = ((int64_t)ce + 15) >> 4;
+        if (rb0 >= 0 && b0 <= rb1) {
+            rb1 = max(rb1, b1);
+        } else {
+            if (rb0 >= 0) emit(rb0, rb1);
+            rb0 = b0;
+            rb1 = b1;
+        }
+    }
+    if (rb0 >= 0) emit(rb0, rb1);
+    if (!out && a.scanned) atomicAdd((unsigned long long*)a.scanned, (unsigned long long)(blocks * 16 * tl));
+    return items;
+}
+
+__global__ void prune_count_kernel(PruneArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > a.n_groups) return;
+    a.counts[g] = (g < a.n_groups) ? group_items(a, g, nullptr) : 0;
+}
+
+__global__ void prune_fill_kernel(PruneArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n_groups) return;
+    group_items(a, g, a.items + 3 * a.offsets[g]);
+}
+
+hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st) {
+    if (a.words < 1 || a.words > 8 || a.P > 32 * a.words) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((a.n_tiles + 3) / 4);
+    if (blocks == 0) return hipSuccess;
+    const int d = a.d;
+    if (d <= 4) prune_plan_kernel<4><<<blocks, 256, 0, st>>>(a);
+    else if (d <= 8) prune_plan_kernel<8><<<blocks, 256, 0, st>>>(a);
+    else if (d <= 16) prune_plan_kernel<16><<<blocks, 256, 0, st>>>(a);
+    else if (d <= 32) prune_plan_kernel<32><<<blocks, 256, 0, st>>>(a);
+    else if (d <= 64) prune_plan_kernel<64><<<blocks, 256, 0, st>>>(a);
+    else if (d <= 128) prune_plan_kernel<128><<<blocks, 256, 0, st>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// counts[n_groups + 1] -> offsets[n_groups + 1] (offsets[n_groups] = the item
+// total, also in *total), then the items
+hipError_t launch_prune_items(const PruneArgs& a, int64_t* partials, hipStream_t st) {
+    const int64_t ng = a.n_groups;
+    prune_count_kernel<<<(unsigned)((ng + 1 + 255) / 256), 256, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan_i64(a.counts, a.offsets, ng + 1, a.total, partials, st);
+    if (e != hipSuccess) return e;
+    prune_fill_kernel<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// an upper bound on the items of one group (the allocation of a.items)
+int64_t prune_max_items_per_group(int32_t P, int64_t n_blocks_p, int32_t max_blocks) {
+    return (int64_t)P + n_blocks_p / max_blocks + 2;
+}
+
+// ---------------------------------------------------------------------------
+// (4) Keep bits back to index order.  One workgroup per tile: the bits of the
+// tile's scanned blocks (pivot order, position e = point order[e]) are set in
+// a bitmap of columns in LDS, a window of 2^20 columns at a time, which is
+// then written out whole, so that every block of the tile's index-order row is
+// written (blocks without kept columns get 0).
+// ---------------------------------------------------------------------------
+constexpr int kConvThreads = 512;
+constexpr int64_t kConvWindow = (int64_t)1 << 20;  // columns per LDS window (128 KB)
+
+__global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a, const uint16_t* __restrict__ maskp,
+                                                                    int64_t n_blocks_p, uint16_t* __restrict__ mask,
+                                                                    int64_t n_blocks) {
+    __shared__ uint32_t bits[kConvWindow / 32];
+    const int64_t t = blockIdx.x;
+    const int64_t g = t / a.TP;
+    const int64_t i0 = a.offsets[g], i1 = a.offsets[g + 1];
+    const uint16_t* mrow = maskp + t * n_blocks_p;
+    const int64_t n_cols = n_blocks * 16;
+    for (int64_t w0 = 0; w0 < n_cols; w0 += kConvWindow) {
+        for (int32_t k = threadIdx.x; k < (int32_t)(kConvWindow / 32); k += kConvThreads) bits[k] = 0u;
+        __syncthreads();
+        for (int64_t it = i0; it < i1; ++it) {
+            const int32_t b0 = a.items[3 * it + 1], b1 = a.items[3 * it + 2];
+            for (int32_t b = b0 + (int32_t)threadIdx.x; b < b1; b += kConvThreads) {
+                uint32_t m = mrow[b];
+                while (m) {
+                    const int32_t c = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const int64_t j = (int64_t)a.order[16 * (int64_t)b + c] - w0;
+                    if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
+                }
+            }
+        }
+        __syncthreads();
+        // write the window's blocks of the tile's row: block k of the window
+        // is half k % 2 of word k / 2
+        const int64_t kb0 = w0 / 16;
+        const int64_t kbn = min(kConvWindow / 16, n_blocks - kb0);
+        uint16_t* out = mask + t * n_blocks + kb0;
+        for (int64_t k = threadIdx.x; k < kbn; k += kConvThreads)
+            out[k] = (uint16_t)(bits[k >> 1] >> (16 * (k & 1)));
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mask_to_index(const PruneArgs& a, const uint16_t* maskp, int64_t n_blocks_p, uint16_t* mask,
+                                int64_t n_blocks, hipStream_t st) {
+    if (a.n_tiles == 0) return hipSuccess;
+    mask_to_index_kernel<<<(unsigned)a.n_tiles, kConvThreads, 0, st>>>(a, maskp, n_blocks_p, mask, n_blocks);
+    return hipGetLastError();
+}
+
+}  // namespace fsg

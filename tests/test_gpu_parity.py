@@ -322,3 +322,58 @@ def test_bf16_split_matches_plain_and_prunes(ctx):
     rel = ((a[1] - b[1]).abs() / a[1]).max().item()
     assert rel < 2e-11, rel
     assert 0 < kept < scanned  # how much is pruned depends on how separated the clusters are
+
+
+@pytest.mark.parametrize("n,d,L,spread,comps", [(1, 3, 2, 10.0, 1), (100, 8, 5, 10.0, 3), (255, 2, 6, 20.0, 4),
+                                                (4097, 16, 8, 12.0, 10), (20_001, 64, 6, 10.0, 30),
+                                                (6000, 100, 6, 10.0, 12), (9000, 128, 5, 10.0, 16),
+                                                (12_345, 32, 7, 2.0, 5)])
+def test_pruned_scan_keeps_the_same_set(ctx, n, d, L, spread, comps):
+    """The tile-pruned keep-mask scan (cells of pivots, triangle-inequality
+    bound) keeps exactly the columns the full scan keeps: neighbours and
+    degrees are bit-identical with pruning on and off, and on well-separated
+    clusters it scans fewer pairs."""
+    X = workloads.mixture(n, d, comps, 880 + n + d, (-spread, spread), (0.5, 1.5))
+    gamma = 1.0 / (2.0 * (0.25 * math.sqrt(d)) ** 2)
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    res = {}
+    for prune in (False, True):
+        ctx.set_pruning(prune)
+        ctx.reset_profiling()
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 4242)
+        kept, scanned = ctx.filter_stats()
+        res[prune] = (nbr.cpu().numpy(), deg.cpu().numpy(), kept, scanned)
+    ctx.set_pruning(True)
+    (n0, d0, k0, s0), (n1, d1, k1, s1) = res[False], res[True]
+    say(f"n={n} d={d}: kept {k0} / {k1}, scanned {s0} (full) / {s1} (pruned)")
+    assert k0 == k1, "the pruned scan keeps a different number of (column, tile) pairs"
+    assert np.array_equal(n0, n1) and np.array_equal(d0, d1)
+    assert s1 <= s0 + 16 * ((n + 63) // 64)  # padding of the last block at most
+    if spread >= 10.0 and comps >= 10:
+        assert s1 < s0
+        if n >= 6000 and d >= 64:
+            # cells of >= 20 points: tiles rarely span several clusters
+            assert s1 < 0.5 * s0, "well-separated clusters should prune most of the scan"
+    pts.close()
+
+
+def test_pruned_scan_against_oracle_full_rows(ctx):
+    """Well-separated clusters in R^64 (the pruned scan skips most cells):
+    every row against the oracle."""
+    n, d, L = 6000, 64, 9
+    X = workloads.mixture(n, d, 20, 8801, (-10.0, 10.0), (0.5, 2.0))
+    gamma = 1.0 / 18.0
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    ctx.reset_profiling()
+    nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 99)
+    kept, scanned = ctx.filter_stats()
+    say(f"pruned: scanned {scanned} of {((n + 63) // 64) * n} column-tile pairs, kept {kept}")
+    assert scanned < 0.4 * ((n + 63) // 64) * n
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, gamma, L, 99)
+    rel = np.abs(deg - rdeg) / rdeg
+    assert rel.max() < 1e-9, rel.max()
+    mism, exempt, non_exempt = compare_neighbours(nbr, rnbr, rmargin)
+    say(f"  mismatches {mism} (band-exempt {exempt}, non-exempt {non_exempt})")
+    assert non_exempt == 0
+    pts.close()
