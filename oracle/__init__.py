@@ -48,20 +48,20 @@ def lib():
         L.fsgo_uniform.restype = c_dbl
         L.fsgo_split.argtypes = [c_i64, c_i64]
         L.fsgo_split.restype = c_i64
-        L.fsgo_kernel.argtypes = [_F32P, _F32P, c_i32, c_dbl]
+        L.fsgo_kernel.argtypes = [_F32P, _F32P, c_i32, c_i32, c_dbl]
         L.fsgo_kernel.restype = c_dbl
-        L.fsgo_degrees.argtypes = [_F32P, c_i64, c_i32, c_dbl, _F64P]
+        L.fsgo_degrees.argtypes = [_F32P, c_i64, c_i32, c_i32, c_dbl, _F64P]
         L.fsgo_degrees.restype = ctypes.c_int
-        L.fsgo_kde_segmented.argtypes = [_F32P, c_i64, _F32P, c_i64, c_i32, c_dbl, c_i64, _I64P, _I32P,
+        L.fsgo_kde_segmented.argtypes = [_F32P, c_i64, _F32P, c_i64, c_i32, c_i32, c_dbl, c_i64, _I64P, _I32P,
                                          _I32P, _I32P, _I32P, _opt(_I32P), _F64P, _F64P]
         L.fsgo_kde_segmented.restype = ctypes.c_int
-        L.fsgo_sample_rows.argtypes = [_F32P, c_i64, c_i32, c_dbl, c_i32, c_u64, _opt(_I32P), c_i64, _I32P,
+        L.fsgo_sample_rows.argtypes = [_F32P, c_i64, c_i32, c_i32, c_dbl, c_i32, c_u64, _opt(_I32P), c_i64, _I32P,
                                        _opt(_F64P), _opt(_F64P)]
         L.fsgo_sample_rows.restype = ctypes.c_int
-        L.fsgo_path_probability.argtypes = [_F32P, c_i64, c_i32, c_dbl, c_i64, c_i64,
+        L.fsgo_path_probability.argtypes = [_F32P, c_i64, c_i32, c_i32, c_dbl, c_i64, c_i64,
                                             ctypes.POINTER(ctypes.c_double)]
         L.fsgo_path_probability.restype = ctypes.c_int
-        L.fsgo_build_csr.argtypes = [_F32P, c_i64, c_i32, c_dbl, c_i32, _I32P, _opt(_F64P), _I64P, _I32P,
+        L.fsgo_build_csr.argtypes = [_F32P, c_i64, c_i32, c_i32, c_dbl, c_i32, _I32P, _opt(_F64P), _I64P, _I32P,
                                      _F64P, c_i64, ctypes.POINTER(ctypes.c_int64)]
         L.fsgo_build_csr.restype = ctypes.c_int
         L.fsgo_num_threads.argtypes = []
@@ -110,20 +110,28 @@ def split(a: int, b: int) -> int:
     return int(lib().fsgo_split(a, b))
 
 
-def kernel(x, y, gamma: float) -> float:
+# kernel kinds of Section 2.1 (the exponent holds ||x-y||_2^2, ||x-y||_2 or ||x-y||_1)
+KERNELS = {"gaussian": 0, "exponential": 1, "laplacian": 2}
+
+
+def _kind(kernel) -> int:
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def kernel(x, y, gamma: float, kernel="gaussian") -> float:
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
-    return float(lib().fsgo_kernel(x, y, x.shape[0], gamma))
+    return float(lib().fsgo_kernel(x, y, x.shape[0], _kind(kernel), gamma))
 
 
-def degrees(X, gamma: float):
+def degrees(X, gamma: float, kernel="gaussian"):
     X = _points(X)
     deg = np.zeros(X.shape[0], dtype=np.float64)
-    _check(lib().fsgo_degrees(X, X.shape[0], X.shape[1], gamma, deg), "degrees")
+    _check(lib().fsgo_degrees(X, X.shape[0], X.shape[1], _kind(kernel), gamma, deg), "degrees")
     return deg
 
 
-def kde_segmented(Q, X, gamma, q_ptr, q_idx, lo, mid, hi, self_idx=None):
+def kde_segmented(Q, X, gamma, q_ptr, q_idx, lo, mid, hi, self_idx=None, kernel="gaussian"):
     Q = _points(Q)
     X = _points(X)
     q_ptr = np.ascontiguousarray(q_ptr, dtype=np.int64)
@@ -137,12 +145,12 @@ def kde_segmented(Q, X, gamma, q_ptr, q_idx, lo, mid, hi, self_idx=None):
     n_ent = int(q_ptr[-1]) if n_seg > 0 else 0
     left = np.zeros(max(n_ent, 1), dtype=np.float64)
     right = np.zeros(max(n_ent, 1), dtype=np.float64)
-    _check(lib().fsgo_kde_segmented(Q, Q.shape[0], X, X.shape[0], X.shape[1], gamma, n_seg, q_ptr, q_idx,
+    _check(lib().fsgo_kde_segmented(Q, Q.shape[0], X, X.shape[0], X.shape[1], _kind(kernel), gamma, n_seg, q_ptr, q_idx,
                                     lo, mid, hi, self_idx, left, right), "kde_segmented")
     return left[:n_ent], right[:n_ent]
 
 
-def sample_rows(X, gamma, L, seed, rows=None, want_margin=True):
+def sample_rows(X, gamma, L, seed, rows=None, want_margin=True, kernel="gaussian"):
     """Returns (nbr[n_rows, L], deg[n_rows], margin[n_rows, L] or None)."""
     X = _points(X)
     n = X.shape[0]
@@ -154,22 +162,22 @@ def sample_rows(X, gamma, L, seed, rows=None, want_margin=True):
     nbr = np.zeros(max(n_rows * L, 1), dtype=np.int32)
     deg = np.zeros(max(n_rows, 1), dtype=np.float64)
     margin = np.zeros(max(n_rows * L, 1), dtype=np.float64) if want_margin else None
-    _check(lib().fsgo_sample_rows(X, n, X.shape[1], gamma, L, seed, rows, n_rows, nbr, deg, margin),
+    _check(lib().fsgo_sample_rows(X, n, X.shape[1], _kind(kernel), gamma, L, seed, rows, n_rows, nbr, deg, margin),
            "sample_rows")
     nbr = nbr[: n_rows * L].reshape(n_rows, L)
     margin = margin[: n_rows * L].reshape(n_rows, L) if want_margin else None
     return nbr, deg[:n_rows], margin
 
 
-def path_probability(X, gamma, i, j) -> float:
+def path_probability(X, gamma, i, j, kernel="gaussian") -> float:
     X = _points(X)
     p = ctypes.c_double(0.0)
-    _check(lib().fsgo_path_probability(X, X.shape[0], X.shape[1], gamma, i, j, ctypes.byref(p)),
+    _check(lib().fsgo_path_probability(X, X.shape[0], X.shape[1], _kind(kernel), gamma, i, j, ctypes.byref(p)),
            "path_probability")
     return p.value
 
 
-def build_csr(X, gamma, L, nbr, deg=None):
+def build_csr(X, gamma, L, nbr, deg=None, kernel="gaussian"):
     """Returns (row_ptr int64[n+1], col int32[nnz], w float64[nnz])."""
     X = _points(X)
     n = X.shape[0]
@@ -181,6 +189,7 @@ def build_csr(X, gamma, L, nbr, deg=None):
     col = np.zeros(max(cap, 1), dtype=np.int32)
     w = np.zeros(max(cap, 1), dtype=np.float64)
     nnz = ctypes.c_int64(0)
-    _check(lib().fsgo_build_csr(X, n, X.shape[1], gamma, L, nbr, deg, row_ptr, col, w, cap, ctypes.byref(nnz)),
+    _check(lib().fsgo_build_csr(X, n, X.shape[1], _kind(kernel), gamma, L, nbr, deg, row_ptr, col, w, cap,
+                                ctypes.byref(nnz)),
            "build_csr")
     return row_ptr, col[: nnz.value].copy(), w[: nnz.value].copy()

@@ -69,20 +69,26 @@ void fsgo_philox_batch(const uint64_t* ctrs, int64_t m, const uint64_t key[2], u
 /* ------------------------------------------------------------------------ */
 int64_t fsgo_split(int64_t a, int64_t b) { return a + (b - a) / 2; }
 
-double fsgo_kernel(const float* x, const float* y, int32_t d, double gamma) {
-    double dist2 = 0.0;
+/* The three kernels of Section 2.1: Gaussian exp(-gamma ||x-y||_2^2), exponential
+ * exp(-gamma ||x-y||_2) and Laplacian exp(-gamma ||x-y||_1), each from the
+ * coordinate differences in FP64. */
+double fsgo_kernel(const float* x, const float* y, int32_t d, int32_t kind, double gamma) {
+    double dist2 = 0.0, dist1 = 0.0;
     for (int32_t t = 0; t < d; ++t) {
         double diff = (double)x[t] - (double)y[t];
         dist2 += diff * diff;
+        dist1 += fabs(diff);
     }
+    if (kind == FSGO_EXPONENTIAL) return exp(-gamma * sqrt(dist2));
+    if (kind == FSGO_LAPLACIAN) return exp(-gamma * dist1);
     return exp(-gamma * dist2);
 }
 
 /* r[j] = k(x_i, x_j) for every j, with r[i] = 0 (no self loop). */
-static void kernel_row(const float* X, int64_t n, int32_t d, double gamma, int64_t i, double* r) {
+static void kernel_row(const float* X, int64_t n, int32_t d, int32_t kind, double gamma, int64_t i, double* r) {
     const float* xi = X + (size_t)i * (size_t)d;
     for (int64_t j = 0; j < n; ++j)
-        r[j] = (j == i) ? 0.0 : fsgo_kernel(xi, X + (size_t)j * (size_t)d, d, gamma);
+        r[j] = (j == i) ? 0.0 : fsgo_kernel(xi, X + (size_t)j * (size_t)d, d, kind, gamma);
 }
 
 /* Mass of the index range [a,b) of a kernel row: the KDE g_[a,b] of eq. (1). */
@@ -92,8 +98,12 @@ static double range_mass(const double* r, int64_t a, int64_t b) {
     return s;
 }
 
-static int valid_common(int64_t n, int32_t d, double gamma) {
-    return n >= 1 && d >= 1 && isfinite(gamma) && gamma > 0.0;
+static int valid_kind(int32_t kind) {
+    return kind == FSGO_GAUSSIAN || kind == FSGO_EXPONENTIAL || kind == FSGO_LAPLACIAN;
+}
+
+static int valid_common(int64_t n, int32_t d, int32_t kind, double gamma) {
+    return n >= 1 && d >= 1 && valid_kind(kind) && isfinite(gamma) && gamma > 0.0;
 }
 
 int fsgo_num_threads(void) {
@@ -108,14 +118,14 @@ int fsgo_num_threads(void) {
 /* Degrees: g_[1,n](x_i) without the self term (Algorithm 2, the KDE after  */
 /* the sampling loop).                                                      */
 /* ------------------------------------------------------------------------ */
-int fsgo_degrees(const float* X, int64_t n, int32_t d, double gamma, double* deg) {
-    if (!X || !deg || !valid_common(n, d, gamma)) return -1;
+int fsgo_degrees(const float* X, int64_t n, int32_t d, int32_t kind, double gamma, double* deg) {
+    if (!X || !deg || !valid_common(n, d, kind, gamma)) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
         const float* xi = X + (size_t)i * (size_t)d;
         double s = 0.0;
         for (int64_t j = 0; j < n; ++j)
-            if (j != i) s += fsgo_kernel(xi, X + (size_t)j * (size_t)d, d, gamma);
+            if (j != i) s += fsgo_kernel(xi, X + (size_t)j * (size_t)d, d, kind, gamma);
         deg[i] = s;
     }
     return 0;
@@ -125,11 +135,11 @@ int fsgo_degrees(const float* X, int64_t n, int32_t d, double gamma, double* deg
 /* Segmented KDE                                                            */
 /* ------------------------------------------------------------------------ */
 int fsgo_kde_segmented(const float* Q, int64_t nq, const float* X, int64_t nx, int32_t d,
-                       double gamma, int64_t n_seg, const int64_t* q_ptr, const int32_t* q_idx,
+                       int32_t kind, double gamma, int64_t n_seg, const int64_t* q_ptr, const int32_t* q_idx,
                        const int32_t* lo, const int32_t* mid, const int32_t* hi,
                        const int32_t* self_idx, double* out_left, double* out_right) {
     if (!Q || !X || !q_ptr || !q_idx || !lo || !mid || !hi || !out_left || !out_right) return -1;
-    if (nq < 1 || nx < 1 || d < 1 || !isfinite(gamma) || gamma <= 0.0 || n_seg < 0) return -1;
+    if (nq < 1 || nx < 1 || d < 1 || !valid_kind(kind) || !isfinite(gamma) || gamma <= 0.0 || n_seg < 0) return -1;
     for (int64_t s = 0; s < n_seg; ++s) {
         if (!(0 <= lo[s] && lo[s] <= mid[s] && mid[s] <= hi[s] && hi[s] <= nx)) return -1;
         if (q_ptr[s] > q_ptr[s + 1] || q_ptr[s] < 0) return -1;
@@ -151,9 +161,9 @@ int fsgo_kde_segmented(const float* Q, int64_t nq, const float* X, int64_t nx, i
         const float* q = Q + (size_t)qi * (size_t)d;
         double left = 0.0, right = 0.0;
         for (int64_t j = lo[s]; j < mid[s]; ++j)
-            if (j != self) left += fsgo_kernel(q, X + (size_t)j * (size_t)d, d, gamma);
+            if (j != self) left += fsgo_kernel(q, X + (size_t)j * (size_t)d, d, kind, gamma);
         for (int64_t j = mid[s]; j < hi[s]; ++j)
-            if (j != self) right += fsgo_kernel(q, X + (size_t)j * (size_t)d, d, gamma);
+            if (j != self) right += fsgo_kernel(q, X + (size_t)j * (size_t)d, d, kind, gamma);
         out_left[e] = left;
         out_right[e] = right;
     }
@@ -189,10 +199,10 @@ static int32_t descend(const double* r, int64_t n, uint64_t seed, int64_t i, int
     return (int32_t)a;
 }
 
-int fsgo_sample_rows(const float* X, int64_t n, int32_t d, double gamma, int32_t L,
+int fsgo_sample_rows(const float* X, int64_t n, int32_t d, int32_t kind, double gamma, int32_t L,
                      uint64_t seed, const int32_t* rows, int64_t n_rows, int32_t* nbr,
                      double* deg, double* margin) {
-    if (!X || !nbr || !valid_common(n, d, gamma) || L < 1 || n_rows < 0) return -1;
+    if (!X || !nbr || !valid_common(n, d, kind, gamma) || L < 1 || n_rows < 0) return -1;
     if (!rows && n_rows != n) return -1;
     if (n > 2147483647LL) return -1;
     int failed = 0;
@@ -211,7 +221,7 @@ int fsgo_sample_rows(const float* X, int64_t n, int32_t d, double gamma, int32_t
                 for (int32_t l = 0; l < L; ++l) nbr[t * L + l] = -2;
                 continue;
             }
-            kernel_row(X, n, d, gamma, i, r);
+            kernel_row(X, n, d, kind, gamma, i, r);
             double deg_i = range_mass(r, 0, n);
             if (deg) deg[t] = deg_i;
             for (int32_t l = 0; l < L; ++l) {
@@ -227,13 +237,13 @@ int fsgo_sample_rows(const float* X, int64_t n, int32_t d, double gamma, int32_t
     return failed ? -2 : 0;
 }
 
-int fsgo_path_probability(const float* X, int64_t n, int32_t d, double gamma, int64_t i,
+int fsgo_path_probability(const float* X, int64_t n, int32_t d, int32_t kind, double gamma, int64_t i,
                           int64_t j, double* prob) {
-    if (!X || !prob || !valid_common(n, d, gamma) || i < 0 || i >= n || j < 0 || j >= n)
+    if (!X || !prob || !valid_common(n, d, kind, gamma) || i < 0 || i >= n || j < 0 || j >= n)
         return -1;
     double* r = (double*)malloc((size_t)n * sizeof(double));
     if (!r) return -2;
-    kernel_row(X, n, d, gamma, i, r);
+    kernel_row(X, n, d, kind, gamma, i, r);
     double p = 1.0;
     int64_t a = 0, b = n;
     while (b - a > 1) {
@@ -265,10 +275,10 @@ static int cmp_entry(const void* pa, const void* pb) {
     return 0;
 }
 
-int fsgo_build_csr(const float* X, int64_t n, int32_t d, double gamma, int32_t L,
+int fsgo_build_csr(const float* X, int64_t n, int32_t d, int32_t kind, double gamma, int32_t L,
                    const int32_t* nbr, const double* deg_in, int64_t* row_ptr, int32_t* col,
                    double* w, int64_t cap, int64_t* nnz) {
-    if (!X || !nbr || !row_ptr || !nnz || !valid_common(n, d, gamma) || L < 1 || cap < 0)
+    if (!X || !nbr || !row_ptr || !nnz || !valid_common(n, d, kind, gamma) || L < 1 || cap < 0)
         return -1;
     if (cap > 0 && (!col || !w)) return -1;
     int64_t n_samples = n * (int64_t)L;
@@ -279,7 +289,7 @@ int fsgo_build_csr(const float* X, int64_t n, int32_t d, double gamma, int32_t L
     if (!deg_in) {
         deg = (double*)malloc((size_t)n * sizeof(double));
         if (!deg) return -2;
-        fsgo_degrees(X, n, d, gamma, deg);
+        fsgo_degrees(X, n, d, kind, gamma, deg);
         deg_in = deg;
     }
     /* Each sampled edge {i, y} as the two directed entries (i,y) and (y,i). */
@@ -306,7 +316,7 @@ int fsgo_build_csr(const float* X, int64_t n, int32_t d, double gamma, int32_t L
 
     for (int64_t k = 0; k < u; ++k) {
         int64_t i = ent[k].row, j = ent[k].col;
-        double kij = fsgo_kernel(X + (size_t)i * (size_t)d, X + (size_t)j * (size_t)d, d, gamma);
+        double kij = fsgo_kernel(X + (size_t)i * (size_t)d, X + (size_t)j * (size_t)d, d, kind, gamma);
         double p_i = fmin((double)L * kij / deg_in[i], 1.0);
         double p_j = fmin((double)L * kij / deg_in[j], 1.0);
         double p_hat = p_i + p_j - p_i * p_j;
