@@ -75,6 +75,14 @@ typedef enum {
     FSG_BF16_SPLIT = 1
 } fsg_precision;
 
+/* The kernels of Section 2.1 (its last sentence names the Laplacian and the
+ * exponential kernel beside the Gaussian one), all with scale gamma > 0. */
+typedef enum {
+    FSG_GAUSSIAN = 0,    /* k = exp(-gamma ||x - y||_2^2) */
+    FSG_EXPONENTIAL = 1, /* k = exp(-gamma ||x - y||_2)   */
+    FSG_LAPLACIAN = 2    /* k = exp(-gamma ||x - y||_1)   */
+} fsg_kernel;
+
 typedef struct fsg_ctx fsg_ctx;
 typedef struct fsg_points fsg_points;
 
@@ -109,6 +117,22 @@ fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);
  * *scanned = (data column, 64-query tile) pairs it examined.  Synchronises the
  * stream. */
 fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned);
+
+/* Kernel of every later call on the context (default FSG_GAUSSIAN): degrees,
+ * segmented KDE, sampling and the CSR weights all use it, with the same
+ * gamma argument.  The exponential kernel runs like the Gaussian one (cross
+ * terms on the FP64 matrix cores, the distance from the norm expansion, then
+ * its square root), in both precisions: the precision mode's keep test then
+ * accepts squared distances up to (sqrt(dmin) + Delta/gamma)^2.  The
+ * Laplacian kernel has no inner-product form: its L1 distances are summed on
+ * the FP64 vector units, in the plain path only (FSG_E_UNSUPPORTED for
+ * FSG_BF16_SPLIT point sets).  Batch jobs and servers use the Gaussian kernel
+ * only (FSG_E_UNSUPPORTED otherwise).  Near-duplicate pairs of the
+ * exponential kernel carry the norm expansion's absolute error into the
+ * square root: |x - y|_2 is then known to about 1e-7 (relative error of k
+ * about gamma 1e-7), a bound the other distances do not need.
+ * FSG_E_INVALID for an unknown kind. */
+fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind);
 
 /* Tile pruning of the precision mode (default on): before the BF16 keep-mask
  * scan of a pass over all points, each 64-query tile is checked against the

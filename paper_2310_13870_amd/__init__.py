@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libfsg.so")
 FSG_OK, FSG_E_INVALID, FSG_E_NOMEM, FSG_E_DEVICE, FSG_E_UNSUPPORTED, FSG_E_BUDGET = 0, -1, -2, -3, -4, -5
 FSG_PLAIN_FP64, FSG_BF16_SPLIT = 0, 1
 PRECISIONS = {"plain_fp64": FSG_PLAIN_FP64, "bf16_split": FSG_BF16_SPLIT}
+FSG_GAUSSIAN, FSG_EXPONENTIAL, FSG_LAPLACIAN = 0, 1, 2
+KERNELS = {"gaussian": FSG_GAUSSIAN, "exponential": FSG_EXPONENTIAL, "laplacian": FSG_LAPLACIAN}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfsg.so is not built ({LIB_PATH}); run paper_2310_13870_amd/build.py")
@@ -40,6 +42,7 @@ _lib_fns = dict(
     fsg_ctx_workspace_bytes=_sig("fsg_ctx_workspace_bytes", _u64, _vp),
     fsg_ctx_set_levels_per_pass=_sig("fsg_ctx_set_levels_per_pass", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_pruning=_sig("fsg_ctx_set_pruning", ctypes.c_int, _vp, _i32),
+    fsg_ctx_set_kernel=_sig("fsg_ctx_set_kernel", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_stage_time=_sig("fsg_ctx_stage_time", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_dbl),
                             ctypes.POINTER(_i64)),
@@ -134,6 +137,12 @@ class Context:
     def set_levels_per_pass(self, max_levels: int):
         """Cap the tree levels one binned pass resolves (0 = automatic)."""
         self.check(_lib.fsg_ctx_set_levels_per_pass(self._h, max_levels))
+
+    def set_kernel(self, kind):
+        """Kernel of later calls: "gaussian" (default), "exponential" or "laplacian"."""
+        if isinstance(kind, str):
+            kind = KERNELS[kind]
+        self.check(_lib.fsg_ctx_set_kernel(self._h, kind))
 
     def set_pruning(self, enabled: bool):
         """Precision mode: skip (query tile, cell) pairs that cannot keep a column (default on)."""

@@ -271,9 +271,13 @@ static int tree_depth(int64_t n) {
     return dpt;
 }
 
-static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma) {
+static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma, int32_t kind = FSG_GAUSSIAN) {
     KdeArgs a;
     std::memset(&a, 0, sizeof(a));
+    a.kind = kind;
+    a.qpts = Q->X;
+    a.xpts = X->X;
+    a.d = X->d;
     a.Qp = Q->Xp;
     a.qnorm = Q->norm;
     a.Xp = X->Xp;
@@ -335,9 +339,10 @@ static int64_t mask_chunk_blocks(int64_t n_blocks, int64_t n_groups, int64_t n_w
 // Keep-mask arguments of a root pass over point set X (precision mode):
 // entries are the points in pivot order, so that each 64-query tile holds
 // points close together and keeps few columns.
-static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus) {
+static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus, int32_t kind = FSG_GAUSSIAN) {
     MaskArgs m;
     std::memset(&m, 0, sizeof(m));
+    m.kind = kind;
     const int64_t n = X->n;
     m.Xb = X->Xb;
     m.Qb = X->Qb;
@@ -402,7 +407,7 @@ fsg_status kde_segmented_enqueue(fsg_ctx* ctx, const fsg_points* Q, const fsg_po
     FSG_HIP(ctx, launch_api_segments(lo, mid, hi, n_seg, b.bounds, b.segs, ctx->stream));
     FSG_HIP(ctx, launch_build_items(q_ptr, n_seg, 2, 2, z.tile, b.counts, b.items, b.n_items, z.max_items,
                                     ctx->stream));
-    KdeArgs a = kde_args(Q, X, gamma);
+    KdeArgs a = kde_args(Q, X, gamma, ctx->kernel);
     a.q_idx = q_idx;
     a.self_idx = self_idx;
     a.self_mode = self_idx ? SELF_ARRAY : SELF_NONE;
@@ -441,6 +446,7 @@ static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const Mask
     pa.margin_z = m0.margin_z;
     pa.eps = m0.eps;
     pa.gamma = m0.gamma;
+    pa.kind = m0.kind;
     pa.cell_pivot = X->cell_pivot;
     pa.pnorm = X->pnorm;
     pa.prad = X->prad;
@@ -486,6 +492,8 @@ static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const Mask
 // Binned KDE of all n points against the nodes of tree level D (one segment).
 static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
     fsg_status st;
+    if (X->prec == FSG_BF16_SPLIT && ctx->kernel == FSG_LAPLACIAN)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "the Laplacian kernel runs in the plain path only");
     const int32_t* bnd = level_bounds(X, D, &st);
     if (!bnd) return st;
     const int64_t n = X->n;
@@ -502,7 +510,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if ((st = ws(ctx, "root_nitems", 1, &n_items_dev)) != FSG_OK) return st;
     FSG_HIP(ctx, launch_uniform_segs(segs, 1, 0, nbins, ctx->stream));
     FSG_HIP(ctx, launch_regular_items(n, nbins, bpc, tile, items, n_items_dev, ctx->stream));
-    KdeArgs a = kde_args(X, X, gamma);
+    KdeArgs a = kde_args(X, X, gamma, ctx->kernel);
     a.q_idx = nullptr;
     a.self_mode = SELF_POINT;
     a.bounds = bnd;
@@ -516,7 +524,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         // together and keep few columns; rows are written by point
         a.q_idx = X->order;
         a.out_rows = X->order;
-        MaskArgs m = root_mask_args(X, gamma, ctx->num_cus);
+        MaskArgs m = root_mask_args(X, gamma, ctx->num_cus, ctx->kernel);
         float* ntheta;
         if ((st = ws(ctx, "mask_theta", (size_t)theta_entries(n), &ntheta)) != FSG_OK) return st;
         FSG_HIP(ctx, launch_mask_theta(m, ntheta, theta_entries(n), ctx->stream));
@@ -663,6 +671,7 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
 struct Sampler {
     fsg_points* X = nullptr;
     double gamma = 0.0;
+    int32_t kind = FSG_GAUSSIAN;  // fsg_kernel
     int32_t L = 0;
     uint64_t seed = 0;
     Plan plan;
@@ -746,7 +755,7 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     FSG_HIP(ctx, launch_uniform_segs(segs, n_nodes, nbins, nbins, ctx->stream));
     FSG_HIP(ctx, launch_build_items(q_ptr, n_nodes, nbins, nbins, tile, scratch, items, n_items, max_items,
                                     ctx->stream));
-    KdeArgs a = kde_args(X, X, S.gamma);
+    KdeArgs a = kde_args(X, X, S.gamma, S.kind);
     a.q_idx = q_idx;
     a.self_idx = q_idx;
     a.self_mode = SELF_ARRAY;
@@ -786,6 +795,7 @@ static LeafArgs leaf_args(const Sampler& S, const int32_t* bnd, const int32_t* s
     la.bounds = bnd;
     la.level = S.plan.leaf_level;
     la.s = S.gamma * 1.442695040888963407359924681001892137;
+    la.kind = S.kind;
     la.L = S.L;
     la.seed = S.seed;
     la.sorted_samples = sorted;
@@ -860,6 +870,7 @@ fsg_status csr_rows_async(fsg_ctx* ctx, const fsg_points* X, double gamma, int32
     a.X = X->X;
     a.deg = deg_dev;
     a.s = gamma * 1.442695040888963407359924681001892137;
+    a.kind = ctx->kernel;
     a.L = L;
     a.row_ptr = row_ptr_dev;
     a.col = col_dev;
@@ -1406,6 +1417,14 @@ fsg_status fsg_ctx_sync(fsg_ctx* ctx) {
 
 uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx) { return ctx ? ctx->held : 0; }
 
+fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind) {
+    if (!ctx) return FSG_E_INVALID;
+    if (kind != FSG_GAUSSIAN && kind != FSG_EXPONENTIAL && kind != FSG_LAPLACIAN)
+        return set_error(ctx, FSG_E_INVALID, "unknown kernel kind");
+    ctx->kernel = kind;
+    return FSG_OK;
+}
+
 fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled) {
     if (!ctx) return FSG_E_INVALID;
     ctx->pruning = enabled != 0;
@@ -1594,9 +1613,12 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
     if (Xc->ctx != ctx) return set_error(ctx, FSG_E_INVALID, "points belong to another context");
     if (!gamma_ok(gamma)) return set_error(ctx, FSG_E_INVALID, "gamma must be finite and > 0");
     if (L < 1) return set_error(ctx, FSG_E_INVALID, "L must be >= 1");
+    if (ctx->kernel == FSG_LAPLACIAN && Xc->prec == FSG_BF16_SPLIT)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "the Laplacian kernel runs in the plain path only");
     Sampler S;
     S.X = const_cast<fsg_points*>(Xc);
     S.gamma = gamma;
+    S.kind = ctx->kernel;
     S.L = L;
     S.seed = seed;
     S.deg = deg_dev;
@@ -1684,6 +1706,7 @@ fsg_status fsg_build_csr(fsg_ctx* ctx, const fsg_points* X, double gamma, int32_
     a.X = X->X;
     a.deg = deg_dev;
     a.s = gamma * 1.442695040888963407359924681001892137;
+    a.kind = ctx->kernel;
     a.L = L;
     a.row_ptr = row_ptr_dev;
     a.col = col_dev;
@@ -1743,6 +1766,8 @@ extern "C" {
 
 fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int32_t L, uint64_t seed,
                           fsg_job** out) {
+    if (ctx && ctx->kernel != FSG_GAUSSIAN)
+        return set_error(ctx, FSG_E_UNSUPPORTED, "batch jobs use the Gaussian kernel only");
     if (!ctx || !out) return FSG_E_INVALID;
     *out = nullptr;
     if (!Xc) return set_error(ctx, FSG_E_INVALID, "NULL points");

@@ -71,6 +71,10 @@ struct KdeArgs {
     const WorkItem* items;
     const int32_t* n_items;  // device-side count
     double s;                // gamma * log2(e)
+    int32_t kind;            // fsg_kernel of the exponent
+    const float* qpts;       // FP32 query points, row-major (the Laplacian kernel's L1 distances)
+    const float* xpts;       // FP32 data points
+    int32_t d;
     double* out;             // out[row * out_stride + bin]
     int64_t out_stride;
     const int32_t* out_rows; // entry -> output row (NULL: the entry index)
@@ -97,6 +101,7 @@ struct MaskArgs {
     double margin_z;           // Delta
     double eps;                // relative error bound of the split cross term
     double gamma;
+    int32_t kind;              // fsg_kernel: Gaussian or exponential
     int64_t n_tiles;           // 64-entry query tiles
     int64_t n_blocks;          // 16-column data blocks
     int64_t blocks_per_chunk;
@@ -132,6 +137,7 @@ struct PruneArgs {
     double margin_z;           // Delta
     double eps;                // relative error bound of the split cross term
     double gamma;
+    int32_t kind;              // fsg_kernel: Gaussian or exponential
     const float* pnorm;        // FP32 |p_c|^2 per cell
     const float* prad;         // upper bound on each cell's radius
     const int32_t* cell_start; // [P + 1]: cell c holds entries [cell_start[c], cell_start[c+1])
@@ -192,6 +198,8 @@ struct fsg_ctx {
     int max_levels_per_pass = 0;
     // precision mode: skip (query tile, cell) pairs that cannot keep a column
     bool pruning = true;
+    // kernel of later calls (fsg_ctx_set_kernel)
+    fsg_kernel kernel = FSG_GAUSSIAN;
     // precision-mode statistics (device counters)
     int64_t* filter_counts = nullptr;  // [kept, scanned]
     // live point sets; detached (their ctx cleared) when the context is destroyed
@@ -339,6 +347,8 @@ hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t s
 
 // KDE over a work list; grid = waves / 4 blocks of 256 threads.
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu = 8);
+// the Laplacian kernel's binned KDE on the vector units (kde_l1.hip)
+hipError_t launch_kde_l1(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
 int kde_tile(int D4);  // query entries per work item of the plain kernel
 int exact_tile(int D4);  // query entries per work item of the exact recompute (precision mode)
 hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
@@ -418,6 +428,7 @@ struct LeafArgs {
     const int32_t* bounds;     // boundaries of the nodes at `level`
     int32_t level;
     double s;                  // gamma * log2(e)
+    int32_t kind;              // fsg_kernel of the exponent
     int32_t L;
     uint64_t seed;
     const int32_t* sorted_samples;  // samples ordered by node
@@ -485,6 +496,7 @@ struct CsrArgs {
     const float* X;
     const double* deg;
     double s;                // gamma * log2(e)
+    int32_t kind;            // fsg_kernel of the weights
     int32_t L;
     int64_t* row_ptr;
     int32_t* col;
@@ -500,6 +512,7 @@ struct CsrRowArgs {
     const float* X;
     const double* deg;
     double s;                // gamma * log2(e)
+    int32_t kind;            // fsg_kernel of the weights
     int32_t L;
     int64_t* row_ptr;        // [n + 1]: exclusive scan of the unique counts (written by the caller)
     int32_t* col;

@@ -65,28 +65,8 @@ __global__ void csr_fill_kernel(CsrArgs a) {
         const int64_t j = (int64_t)(key - (uint64_t)i * (uint64_t)a.n);
         const float* xi = a.X + i * a.d;
         const float* xj = a.X + j * a.d;
-        double D = 0.0;
-        if ((a.d & 3) == 0 && (((uintptr_t)a.X) & 15) == 0) {
-            // 16-byte loads; the same summation order as the scalar loop
-            const float4* vi = (const float4*)xi;
-            const float4* vj = (const float4*)xj;
-            for (int32_t t4 = 0; t4 < (a.d >> 2); ++t4) {
-                const float4 p = vi[t4], q = vj[t4];
-                double df = (double)p.x - (double)q.x;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.y - (double)q.y;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.z - (double)q.z;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.w - (double)q.w;
-                D = __builtin_fma(df, df, D);
-            }
-        } else {
-            for (int32_t t = 0; t < a.d; ++t) {
-                const double df = (double)xi[t] - (double)xj[t];
-                D = __builtin_fma(df, df, D);
-            }
-        }
+        // 16-byte loads where the rows allow, the same summation order
+        const double D = kernel_distance(a.kind, xi, xj, a.d, (a.d & 3) == 0 && (((uintptr_t)a.X) & 15) == 0);
         const double k = exp2_fp64(-a.s * D);
         const double pi = fmin((double)a.L * k / a.deg[i], 1.0);
         const double pj = fmin((double)a.L * k / a.deg[j], 1.0);
@@ -229,27 +209,7 @@ __global__ __launch_bounds__(256) void csr_row_fill_kernel(CsrRowArgs a) {
     for (int64_t k = lane; k < cnt; k += 64) {
         const int64_t j = seg[k];
         const float* xj = a.X + j * a.d;
-        double D = 0.0;
-        if (vec) {
-            const float4* vi = (const float4*)xi;
-            const float4* vj = (const float4*)xj;
-            for (int32_t t4 = 0; t4 < (a.d >> 2); ++t4) {
-                const float4 p = vi[t4], q = vj[t4];
-                double df = (double)p.x - (double)q.x;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.y - (double)q.y;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.z - (double)q.z;
-                D = __builtin_fma(df, df, D);
-                df = (double)p.w - (double)q.w;
-                D = __builtin_fma(df, df, D);
-            }
-        } else {
-            for (int32_t t = 0; t < a.d; ++t) {
-                const double df = (double)xi[t] - (double)xj[t];
-                D = __builtin_fma(df, df, D);
-            }
-        }
+        const double D = kernel_distance(a.kind, xi, xj, a.d, vec);
         const double kv = exp2_fp64(-a.s * D);
         const double pi = fmin((double)a.L * kv / a.deg[row], 1.0);
         const double pj = fmin((double)a.L * kv / a.deg[j], 1.0);

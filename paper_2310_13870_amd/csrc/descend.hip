@@ -201,7 +201,21 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
 // Leaf stage: each lane keeps its sample's (<= 64) kernel values
 // in registers; the child masses of every level are summed with static
 // predicates, so the descent has no dependent memory chains.
-template <int DMAX, bool MULTI>
+// The scaled exponent (for exp2_256_tab) of one leaf pair from its sum over
+// the features (a cross term, or an L1 distance for the Laplacian kernel).
+template <int KIND>
+__device__ __forceinline__ double leaf_exponent(double sum, double hq, double xn, double s256, double two_s,
+                                                double qn) {
+    if constexpr (KIND == kKindLaplacian) return -s256 * sum;
+    if constexpr (KIND == kKindExponential)
+        return -s256 * __builtin_sqrt(__builtin_fmax(__builtin_fma(-2.0, sum, qn + xn), 0.0));
+    return __builtin_fma(two_s, sum, hq - s256 * xn);
+}
+
+// KIND: the Gaussian kernel (cross terms, the norm expansion), the exponential
+// one (the same, then the square root) or the Laplacian one (the L1 distance
+// from coordinate differences, summed in coordinate order).
+template <int DMAX, bool MULTI, int KIND = kKindGaussian>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void leaf_reg_kernel(LeafArgs a0) {
     // d <= 32: the query row in registers, node points in LDS row by row, four
     // points at a time.  d > 32: features outer, the 64 points' cross terms in
@@ -243,7 +257,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
         const int32_t i = smp / a.L, l = smp - i * a.L;
         const float* xi = a.X + (int64_t)i * a.d;
         const int32_t self = i - lo;  // the sample's own point, if it lies in the node
-        const double hq = -s256 * a.norm[i];
+        const double qn = a.norm[i];
+        const double hq = -s256 * qn;
         xns[lane] = (lane < cnt) ? a.norm[lo + lane] : 0.0;
         double kv[kLeafMax];
         if constexpr (kWide) {
@@ -259,13 +274,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
                 const double qt = (double)xi[t];
                 const stage_t* xt = xs + t * kLeafMax;
 #pragma unroll
-                for (int j = 0; j < kLeafMax; ++j) kv[j] = __builtin_fma(qt, (double)xt[j], kv[j]);
+                for (int j = 0; j < kLeafMax; ++j) {
+                    if constexpr (KIND == kKindLaplacian)
+                        kv[j] += __builtin_fabs(qt - (double)xt[j]);
+                    else
+                        kv[j] = __builtin_fma(qt, (double)xt[j], kv[j]);
+                }
             }
 #pragma unroll
             for (int j = 0; j < kLeafMax; ++j) {
                 // (a uniform branch per point: evaluated unconditionally, the 64
                 // exponentials get interleaved and spill)
-                const double k = (j < cnt) ? exp2_256_tab(__builtin_fma(two_s, kv[j], hq - s256 * xns[j]), exp_tab)
+                const double k = (j < cnt) ? exp2_256_tab(leaf_exponent<KIND>(kv[j], hq, xns[j], s256, two_s, qn),
+                                                          exp_tab)
                                            : 0.0;
                 kv[j] = (j != self) ? k : 0.0;
             }
@@ -290,12 +311,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
 #pragma unroll
                     for (int t = 0; t < DMAX; ++t) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) c[u] = __builtin_fma((double)q[t], (double)xj[u * DMAX + t], c[u]);
+                        for (int u = 0; u < 4; ++u) {
+                            if constexpr (KIND == kKindLaplacian)
+                                c[u] += __builtin_fabs((double)q[t] - (double)xj[u * DMAX + t]);
+                            else
+                                c[u] = __builtin_fma((double)q[t], (double)xj[u * DMAX + t], c[u]);
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int j = j0 + u;
-                        const double k = exp2_256_tab(__builtin_fma(two_s, c[u], hq - s256 * xns[j]), exp_tab);
+                        const double k = exp2_256_tab(leaf_exponent<KIND>(c[u], hq, xns[j], s256, two_s, qn), exp_tab);
                         kv[j] = (j < cnt && j != self) ? k : 0.0;
                     }
                 } else {
@@ -345,6 +371,10 @@ template <int DMAX>
 static void launch_leaf_t(const LeafArgs& a, int64_t blocks, hipStream_t st) {
     if (a.jobs)
         leaf_reg_kernel<DMAX, true><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.kind == kKindExponential)
+        leaf_reg_kernel<DMAX, false, kKindExponential><<<(unsigned)blocks, 64, 0, st>>>(a);
+    else if (a.kind == kKindLaplacian)
+        leaf_reg_kernel<DMAX, false, kKindLaplacian><<<(unsigned)blocks, 64, 0, st>>>(a);
     else
         leaf_reg_kernel<DMAX, false><<<(unsigned)blocks, 64, 0, st>>>(a);
 }

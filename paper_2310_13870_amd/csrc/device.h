@@ -155,4 +155,56 @@ __device__ uint32_t writelane_u32(uint32_t val, uint32_t lane, uint32_t old) __a
 // Split of node [a,b): the left half holds floor((b-a)/2) points.
 __device__ __forceinline__ int32_t tree_split(int32_t a, int32_t b) { return a + ((b - a) >> 1); }
 
+// Kernel kinds (fsg_kernel): what enters the exponent, times gamma.
+constexpr int kKindGaussian = 0;     // ||x - y||_2^2
+constexpr int kKindExponential = 1;  // ||x - y||_2
+constexpr int kKindLaplacian = 2;    // ||x - y||_1
+
+// The exponent's distance of kernel `kind` between two FP32 points from their
+// coordinate differences (exact in FP64), summed in coordinate order:
+// squared for the Gaussian kernel, its square root for the exponential one,
+// absolute values for the Laplacian one.  vec: 16-byte loads (d % 4 == 0,
+// aligned rows), the same summation order.
+__device__ __forceinline__ double kernel_distance(int32_t kind, const float* xi, const float* xj, int32_t d,
+                                                  bool vec) {
+    double D = 0.0;
+    if (kind == kKindLaplacian) {
+        for (int32_t t = 0; t < d; ++t) D += __builtin_fabs((double)xi[t] - (double)xj[t]);
+        return D;
+    }
+    if (vec) {
+        const float4* vi = (const float4*)xi;
+        const float4* vj = (const float4*)xj;
+        for (int32_t t4 = 0; t4 < (d >> 2); ++t4) {
+            const float4 p = vi[t4], q = vj[t4];
+            double df = (double)p.x - (double)q.x;
+            D = __builtin_fma(df, df, D);
+            df = (double)p.y - (double)q.y;
+            D = __builtin_fma(df, df, D);
+            df = (double)p.z - (double)q.z;
+            D = __builtin_fma(df, df, D);
+            df = (double)p.w - (double)q.w;
+            D = __builtin_fma(df, df, D);
+        }
+    } else {
+        for (int32_t t = 0; t < d; ++t) {
+            const double df = (double)xi[t] - (double)xj[t];
+            D = __builtin_fma(df, df, D);
+        }
+    }
+    return (kind == kKindExponential) ? __builtin_sqrt(D) : D;
+}
+
+// Precision mode: the largest squared distance a pair may have and still
+// carry more than e^-Delta of its row's largest term, given dm >= the row's
+// smallest squared distance.  Gaussian (exponent gamma D): dm + Delta/gamma;
+// exponential (exponent gamma sqrt(D)): (sqrt(dm) + Delta/gamma)^2.
+__host__ __device__ inline double keep_dist2(int32_t kind, double dm, double margin_z, double gamma) {
+    if (kind == kKindExponential) {
+        const double r = __builtin_sqrt(dm) + margin_z / gamma;
+        return r * r;
+    }
+    return dm + margin_z / gamma;
+}
+
 }  // namespace fsg

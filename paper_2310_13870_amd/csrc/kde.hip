@@ -1,4 +1,5 @@
-// Segmented Gaussian KDE over tree bins on the FP64 matrix cores (hot-path
+// Segmented Gaussian (and exponential-kernel) KDE over tree bins on the FP64
+// matrix cores (hot-path
 // step "segmented KDE"; the two KDEs of Algorithm 1 and the degree KDE of
 // Algorithm 2, eq. (1) of Section 2.2 over index ranges).
 //
@@ -22,7 +23,9 @@ namespace fsg {
 
 // MULTI: items of many point sets in one launch; segment sg.job selects the
 // arguments of its point set from a.jobs.
-template <int D4, int RQ, bool MULTI>
+// KIND: the Gaussian kernel, or the exponential one (the same cross terms,
+// the square root of the distance in the exponent).
+template <int D4, int RQ, bool MULTI, int KIND = kKindGaussian>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 2 : 1))) void kde_bins_kernel(KdeArgs a) {
     // the table exponential where two waves share a SIMD (d <= 64), whose LDS
     // reads the other wave hides; the polynomial one at one wave per SIMD
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 
             int32_t sf = -1;
             if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -kScale * J.s * J.qnorm[p];
+            hq[qb] = (KIND == kKindExponential) ? J.qnorm[p] : -kScale * J.s * J.qnorm[p];
             load_row_part<D4>(qf[qb], J.Qp, p, grp);
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
@@ -112,7 +115,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D4 <= 16 ? 
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[kk], qf[qb][kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, kTab>(c, hq, xn, -kScale * J.s, two_s, jj, selfv, smin, smax, c0, c0 + 15, exp_tab, kv);
+            exact_values<RQ, kTab, false, KIND>(c, hq, xn, -kScale * J.s, two_s, jj, selfv, smin, smax, c0, c0 + 15,
+                                                exp_tab, kv);
             bins.add(kv, jj, c0 + 15);
             if (more) {
                 if (kPrefetch) {
@@ -137,10 +141,14 @@ static hipError_t launch_kde_t(const KdeArgs& a, int64_t max_items, int num_cus,
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    if (a.jobs)
+    if (a.kind == kKindExponential) {
+        if (a.jobs) return hipErrorInvalidValue;  // multi-set launches are Gaussian only
+        kde_bins_kernel<D4, RQ, false, kKindExponential><<<blocks, 256, 0, st>>>(a);
+    } else if (a.jobs) {
         kde_bins_kernel<D4, RQ, true><<<blocks, 256, 0, st>>>(a);
-    else
+    } else {
         kde_bins_kernel<D4, RQ, false><<<blocks, 256, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -161,6 +169,7 @@ int feature_steps(int d) {
 // d > 32, where 32 FP64 query rows let two waves share a SIMD (d <= 64) or
 // 64 would not fit the register file (d > 64).
 hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st, int waves_per_cu) {
+    if (a.kind == kKindLaplacian) return launch_kde_l1(a, max_items, num_cus, st);
     switch (a.D4) {
         case 1: return launch_kde_t<1, 4>(a, max_items, num_cus, waves_per_cu, st);
         case 2: return launch_kde_t<2, 4>(a, max_items, num_cus, waves_per_cu, st);

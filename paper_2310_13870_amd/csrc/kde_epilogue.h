@@ -379,7 +379,20 @@ struct BinAccumulator1 {
 // vector work does not hide the LDS latency (the exact recompute), and the
 // values are the same either way.  The self compare runs only when a query of
 // the block has its own index in [lo_col, hi_col].
-template <bool TAB, bool AHEAD>
+//
+// KIND = kKindExponential (the exponential kernel): hq is the raw |q|^2 and
+// the exponent is neg_s sqrt(max(|q|^2 + |x|^2 - 2 x.q, 0)) (two_s unused).
+template <int KIND>
+__device__ __forceinline__ double pair_exponent(double c, double hq, double xn, double neg_s, double two_s) {
+    if constexpr (KIND == kKindExponential) {
+        const double D = __builtin_fma(-2.0, c, hq + xn);
+        return neg_s * __builtin_sqrt(__builtin_fmax(D, 0.0));
+    } else {
+        return __builtin_fma(two_s, c, __builtin_fma(xn, neg_s, hq));
+    }
+}
+
+template <bool TAB, bool AHEAD, int KIND = kKindGaussian>
 __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq, const double (&xn)[4], double neg_s,
                                                    double two_s, const int32_t (&jj)[4], int32_t selfv, int32_t smin,
                                                    int32_t smax, int32_t lo_col, int32_t hi_col, const double* tab,
@@ -390,7 +403,7 @@ __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq
         int32_t mi[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            mi[i] = exp2_256_split(__builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq)), &r[i]);
+            mi[i] = exp2_256_split(pair_exponent<KIND>(c[i], hq, xn[i], neg_s, two_s), &r[i]);
             t[i] = tab[mi[i] & 255];
         }
 #pragma unroll
@@ -398,7 +411,7 @@ __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq
     } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double z = __builtin_fma(two_s, c[i], __builtin_fma(xn[i], neg_s, hq));
+            const double z = pair_exponent<KIND>(c[i], hq, xn[i], neg_s, two_s);
             kv[i] = TAB ? exp2_256_tab(z, tab) : exp2_fp64(z);
         }
     }
@@ -410,7 +423,7 @@ __device__ __forceinline__ void exact_values_block(const double4_t& c, double hq
 }
 
 // The FP64 epilogue of all query blocks against one 16-column block.
-template <int RQ, bool TAB, bool AHEAD = false>
+template <int RQ, bool TAB, bool AHEAD = false, int KIND = kKindGaussian>
 __device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const double (&hq)[RQ], const double (&xn)[4],
                                              double neg_s, double two_s, const int32_t (&jj)[4],
                                              const int32_t (&selfv)[RQ], const int32_t (&smin)[RQ],
@@ -418,8 +431,8 @@ __device__ __forceinline__ void exact_values(const double4_t (&c)[RQ], const dou
                                              const double* tab, double (&kv)[RQ][4]) {
 #pragma unroll
     for (int qb = 0; qb < RQ; ++qb)
-        exact_values_block<TAB, AHEAD>(c[qb], hq[qb], xn, neg_s, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col, hi_col,
-                                tab, kv[qb]);
+        exact_values_block<TAB, AHEAD, KIND>(c[qb], hq[qb], xn, neg_s, two_s, jj, selfv[qb], smin[qb], smax[qb], lo_col,
+                                             hi_col, tab, kv[qb]);
 }
 
 }  // namespace fsg

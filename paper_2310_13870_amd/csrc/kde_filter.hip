@@ -52,7 +52,7 @@ struct Gathered {
     int32_t first, last;  // smallest and largest column (uniform)
 };
 
-template <int D4, int RQ, bool MULTI>
+template <int D4, int RQ, bool MULTI, int KIND = kKindGaussian>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
     KdeArgs a, unsigned long long* __restrict__ next_item) {
     // queue length: fewer than 16 entries left over plus one batch of 256 columns
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             int32_t sf = -1;
             if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
-            hq[qb] = -s256 * J.qnorm[p];
+            hq[qb] = (KIND == kKindExponential) ? J.qnorm[p] : -s256 * J.qnorm[p];
             double qv[D4];
             load_row_part<D4>(qv, J.Qp, p, grp);
 #pragma unroll
@@ -202,7 +202,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
             }
             double kv[RQ][4];
-            exact_values<RQ, true, true>(c, hq, g.xn, -s256, two_s, g.jj, selfv, smin, smax, g.first, g.last, exp_tab, kv);
+            exact_values<RQ, true, true, KIND>(c, hq, g.xn, -s256, two_s, g.jj, selfv, smin, smax, g.first, g.last,
+                                               exp_tab, kv);
             bins.add(kv, g.jj, g.last);
         };
 
@@ -247,10 +248,15 @@ static hipError_t launch_exact_t(const KdeArgs& a, int64_t max_items, unsigned l
     // 32-entry items for d > 64 (exact_tile), whose FP64 query fragments
     // would not fit the LDS at 64
     constexpr int RQ = D4 >= 32 ? 2 : 4;
-    if (a.jobs)
+    if (a.kind == kKindExponential) {
+        if (a.jobs) return hipErrorInvalidValue;  // multi-set launches are Gaussian only
+        kde_exact_kept_kernel<D4, RQ, false, kKindExponential><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a,
+                                                                                                          next_item);
+    } else if (a.jobs) {
         kde_exact_kept_kernel<D4, RQ, true><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
-    else
+    } else {
         kde_exact_kept_kernel<D4, RQ, false><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a, next_item);
+    }
     return hipGetLastError();
 }
 

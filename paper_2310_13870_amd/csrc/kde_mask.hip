@@ -257,7 +257,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
 }
 
 // Minus the keep-threshold of every entry:
-//     theta_q = |q|^2/2 - dmin_q (1 + 1e-6)/2 - Delta/(2 gamma) - E,
+//     theta_q = |q|^2/2 - T_q/2 - E,  T_q = dmin_q (1 + 1e-6) + Delta/gamma
+// (Gaussian kernel; for the exponential kernel T_q = (sqrt(dmin_q (1 + 1e-6))
+// + Delta/gamma)^2, whose square root is the largest distance a kept pair
+// can have),
 //     E = eps (|q| xmax + xmax^2/2),
 // in FP64, then rounded down to FP32 (the test c~ - theta_q >= |x|^2/2 only
 // keeps more); entries past the last get -inf (never kept).
@@ -273,7 +276,11 @@ __global__ void mask_theta_kernel(MaskArgs m, float* __restrict__ out, int64_t n
     const double xmax = *m.xmax;
     const double nq = m.qnorm[p];
     const double err = m.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
-    const double th = 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - m.margin_z / (2.0 * m.gamma) - err;
+    // Gaussian: T = dmin (1 + 1e-6) + Delta/gamma; exponential: the squared
+    // distance whose square root is Delta/gamma beyond sqrt(dmin (1 + 1e-6))
+    const double th = (m.kind == kKindExponential)
+                          ? 0.5 * nq - 0.5 * keep_dist2(m.kind, m.dmin[p] * (1.0 + 1e-6), m.margin_z, m.gamma) - err
+                          : 0.5 * nq - 0.5 * m.dmin[p] * (1.0 + 1e-6) - m.margin_z / (2.0 * m.gamma) - err;
     float thf = (float)th;
     if ((double)thf > th) {  // step one FP32 ulp down
         int32_t bits = __float_as_int(thf);

@@ -6,9 +6,12 @@
 // inequality gives |q - x| >= |q - p_c| - r_c for every member x.  The keep
 // test of the scan can pass for a pair only if its squared distance is at
 // most
-//     T_q = dmin_q (1 + 1e-6) + Delta / gamma + 4 E_q + 2^-20 |theta_q|
-// (the threshold of the test, its error bound E_q counted on both sides of
-// the comparison, and the FP32 rounding of theta_q), so a (query tile, cell)
+//     T_q = K_q + 4 E_q + 2^-20 |theta_q|,  K_q = dmin_q (1 + 1e-6) + Delta / gamma
+// (the threshold of the test -- for the exponential kernel K_q =
+// (sqrt(dmin_q (1 + 1e-6)) + Delta / gamma)^2 --, its error bound E_q counted
+// on both sides of the comparison, and the FP32 rounding of theta_q; theta_q
+// differs from the test's by the rounding of the FP64 terms, which the
+// 2^-20 |theta_q| term covers), so a (query tile, cell)
 // pair with |q - p_c| > r_c + sqrt(T_q) for all queries of the tile cannot
 // keep any column: the scan skips it, and the kept set -- hence every mass --
 // is the same as with the full scan.  This is the first pruning step towards
@@ -155,7 +158,7 @@ hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const doub
 // ---------------------------------------------------------------------------
 // (1) Plan: bit c of surv[t] is set when some query of tile t may keep a
 // column of cell c.  One wave per tile, a lane per query entry; the pivot
-// coordinates are read with wave-uniform addresses.  The squared distance to
+// coordinates are shared through LDS.  The squared distance to
 // the pivot is bounded from below from FP32 norms and cross terms (four
 // partial sums each): their errors and the roundings that combine them stay
 // below (d + 32) 2^-24 (|q|^2 + |p|^2) (as in the pivot kernel), and the last
@@ -165,11 +168,17 @@ hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const doub
 // ---------------------------------------------------------------------------
 template <int DMAX>
 __global__ __launch_bounds__(256) void prune_plan_kernel(PruneArgs a) {
+    // pivots staged in LDS 32 at a time (one word of the cell set), zero
+    // padded to DMAX features so that the dot products need no guards
+    constexpr int CH = 32;
+    __shared__ float piv[CH][DMAX];
+    __shared__ float pn[CH], pr[CH];
+    __shared__ int32_t live[CH];
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));
-    if (t >= a.n_tiles) return;
+    const bool tile_ok = t < a.n_tiles;  // wave-uniform; every wave takes part in the staging
     const int64_t e = t * kTileQ + lane;
-    const bool valid = e < a.n;
+    const bool valid = tile_ok && e < a.n;
     const int32_t d = a.d;
     const int32_t p = valid ? a.order[e] : 0;
     float q[DMAX];
@@ -189,34 +198,44 @@ __global__ __launch_bounds__(256) void prune_plan_kernel(PruneArgs a) {
         const double nq = a.qnorm[p];
         const double dm = a.dmin[p] * (1.0 + 1e-6);
         const double err = a.eps * (__builtin_sqrt(nq) * xmax + 0.5 * xmax * xmax);
-        const double th = 0.5 * nq - 0.5 * dm - a.margin_z / (2.0 * a.gamma) - err;
-        double T = dm + a.margin_z / a.gamma + 4.0 * err + 0x1p-20 * __builtin_fabs(th);
+        const double Tk = keep_dist2(a.kind, dm, a.margin_z, a.gamma);
+        const double th = 0.5 * nq - 0.5 * Tk - err;
+        double T = Tk + 4.0 * err + 0x1p-20 * __builtin_fabs(th);
         T *= 1.0 + 0x1p-30;
         sT = float_up(__builtin_sqrt(T) * (1.0 + 0x1p-40));
     }
     const float sl = (float)(d + 40) * 0x1p-24f;
     const int32_t P = a.P;
-    uint32_t word = 0;
-    for (int32_t c = 0; c < P; ++c) {
-        const int32_t cs = a.cell_start[c], ce = a.cell_start[c + 1];
-        bool need = false;
-        if (ce > cs) {
-            const float* pc = a.X + (int64_t)a.cell_pivot[c] * d;
+    for (int32_t c0 = 0; c0 < P; c0 += CH) {
+        const int32_t nc = min(CH, P - c0);
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < CH * DMAX; k += 256) {
+            const int32_t cc = k / DMAX, kk = k - cc * DMAX;
+            piv[cc][kk] = (cc < nc && kk < d) ? a.X[(int64_t)a.cell_pivot[c0 + cc] * d + kk] : 0.0f;
+        }
+        if ((int32_t)threadIdx.x < CH) {
+            const int32_t c = c0 + threadIdx.x;
+            const bool ok = (int32_t)threadIdx.x < nc;
+            pn[threadIdx.x] = ok ? a.pnorm[c] : 0.0f;
+            pr[threadIdx.x] = ok ? a.prad[c] : 0.0f;
+            live[threadIdx.x] = ok && a.cell_start[c + 1] > a.cell_start[c];
+        }
+        __syncthreads();
+        if (!tile_ok) continue;
+        uint32_t word = 0;
+        for (int32_t cc = 0; cc < nc; ++cc) {
+            if (!live[cc]) continue;  // an empty cell (uniform)
             float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int k = 0; k < DMAX; ++k)
-                if (k < d) acc[k & 3] = __builtin_fmaf(q[k], pc[k], acc[k & 3]);
+            for (int k = 0; k < DMAX; ++k) acc[k & 3] = __builtin_fmaf(q[k], piv[cc][k], acc[k & 3]);
             const float dot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-            const float s = qn + a.pnorm[c];
+            const float s = qn + pn[cc];
             const float dlb = __builtin_fmaf(-sl, s, __builtin_fmaf(-2.0f, dot, s));
-            const float lim = a.prad[c] + sT;
-            need = valid && dlb <= lim * lim * (1.0f + 0x1p-20f);
+            const float lim = pr[cc] + sT;
+            const bool need = valid && dlb <= lim * lim * (1.0f + 0x1p-20f);
+            if (__ballot(need) != 0) word |= 1u << cc;
         }
-        if (__ballot(need) != 0) word |= 1u << (c & 31);
-        if ((c & 31) == 31 || c == P - 1) {
-            if (lane == 0) a.surv[t * a.words + (c >> 5)] = word;
-            word = 0;
-        }
+        if (lane == 0) a.surv[t * a.words + (c0 >> 5)] = word;
     }
 }
 

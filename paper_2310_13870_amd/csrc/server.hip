@@ -296,6 +296,7 @@ fsg_status fsg_server_submit_build(fsg_server* s, int64_t set_id, const float* X
     if (s && !s->ctx) return FSG_E_INVALID;  // its context was destroyed
     if (!s || !req_id) return FSG_E_INVALID;
     fsg_ctx* ctx = s->ctx;
+    if (ctx->kernel != FSG_GAUSSIAN) return set_error(ctx, FSG_E_UNSUPPORTED, "servers use the Gaussian kernel only");
     if (set_id < 0 || s->sets.count(set_id)) return set_error(ctx, FSG_E_INVALID, "set_id is negative or in use");
     if (!X_dev || n < 1 || n > 2147483647LL || d < 1) return set_error(ctx, FSG_E_INVALID, "bad point set");
     if (!(gamma > 0.0) || !(gamma < 1e308) || L < 1) return set_error(ctx, FSG_E_INVALID, "bad gamma or L");
