@@ -31,3 +31,30 @@ def test_gpu_graph_preserves_clusters(prec):
     W = dense_from_csr(n, rp, col, w)
     assert np.array_equal(W, W.T)
     say(f"{prec}: " + check_cluster_preserving(full_kernel(X, gamma), W, lab))
+
+
+@pytest.mark.parametrize("prec", ["plain_fp64", "bf16_split"])
+@pytest.mark.parametrize("shape", ["moons-n20k", "mixture-r8-n20k"])
+def test_gpu_graph_preserves_clusters_n20k(prec, shape):
+    """n = 20,000: two moons (the paper's synthetic shape) and an overlapping
+    five-component mixture in R^8; the full kernel graph's spectrum from a
+    dense matrix, the GPU graph's from its sparse CSR."""
+    from tests.cluster_common import (check_cluster_preserving_large, full_kernel_blocked, mixture_case,
+                                      moons_case, sparse_from_csr)
+    if shape.startswith("moons"):
+        X, lab, gamma, L = moons_case("moons-n20k", 62)
+    else:
+        X, lab, gamma, L = mixture_case(20_000, 8, 5, 73)
+    n = X.shape[0]
+    ctx = fsg.Context(0)
+    try:
+        pts = fsg.Points(ctx, to_dev(X), prec)
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 10)
+        rp, col, w = fsg.build_csr(ctx, pts, gamma, L, nbr, deg)
+        rp, col, w = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy().astype(np.float64)
+        pts.close()
+    finally:
+        ctx.close()
+    W = sparse_from_csr(n, rp, col, w)
+    assert (W != W.T).nnz == 0
+    say(f"{shape} {prec}: " + check_cluster_preserving_large(full_kernel_blocked(X, gamma), W, lab))

@@ -52,6 +52,26 @@ def subsample(n: int, m: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(n, size=min(m, n), replace=False)).astype(np.int32)
 
 
+def two_moons(n: int, noise: float, seed: int):
+    """Two interleaved half circles in R^2 (the synthetic shape of the
+    paper's experiments): n // 2 points at angle t ~ U[0, pi] on the outer
+    moon (cos t, sin t), the rest on the inner moon (1 - cos t, 1/2 - sin t),
+    plus isotropic Gaussian noise of std `noise`, rows in seeded random order.
+    Returns (X float32 [n, 2], moon label [n])."""
+    rng = np.random.default_rng(seed)
+    n_out = n // 2
+    t = rng.uniform(0.0, math.pi, size=n)
+    X = np.empty((n, 2), dtype=np.float64)
+    X[:n_out, 0] = np.cos(t[:n_out])
+    X[:n_out, 1] = np.sin(t[:n_out])
+    X[n_out:, 0] = 1.0 - np.cos(t[n_out:])
+    X[n_out:, 1] = 0.5 - np.sin(t[n_out:])
+    X += noise * rng.standard_normal(size=(n, 2))
+    lab = np.concatenate([np.zeros(n_out, dtype=np.int64), np.ones(n - n_out, dtype=np.int64)])
+    perm = rng.permutation(n)
+    return np.ascontiguousarray(X[perm], dtype=np.float32), lab[perm]
+
+
 def depth_of(n: int) -> int:
     """ceil(log2 n): the number of halvings from n points to one."""
     return 0 if n <= 1 else int(math.ceil(math.log2(n)))
