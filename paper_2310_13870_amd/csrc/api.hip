@@ -925,12 +925,20 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // device tables of a batched leaf stage: the jobs' leaf arguments and their
 // work-slot offsets
+// device tables of a batched leaf stage: per job its leaf arguments and its
+// grouping-key entry, the jobs' sample and node offsets, and the buffers of
+// the combined grouping (one sort of every job's samples by global node id)
 struct LeafTables {
     std::vector<fsg_job*> jobs;
-    void* dev = nullptr;   // LeafArgs[G], int64[G+1]
+    void* dev = nullptr;   // LeafArgs[G], LeafKeyJob[G], int64[G+1] sample offsets, int32[G+1] node offsets
     void* host = nullptr;  // pinned staging of the same layout
-    LeafArgs a0;           // launch arguments (tables bound)
-    int64_t slots = 0;
+    LeafArgs a0;           // launch arguments (tables bound; the grouping buffers are set per launch)
+    const LeafKeyJob* key_jobs = nullptr;
+    const int64_t* sample_off = nullptr;
+    const int32_t* node_off = nullptr;
+    int64_t samples = 0;   // all jobs' samples
+    int64_t nodes = 0;     // all jobs' leaf-level nodes
+    int64_t max_items = 0; // work items at most
 };
 
 static void free_leaf_tables(fsg_ctx* ctx, LeafTables* T) {
@@ -938,6 +946,22 @@ static void free_leaf_tables(fsg_ctx* ctx, LeafTables* T) {
     host_free(ctx, T->host);
     delete T;
 }
+
+// device tables of a batched root descent: every job's descent arguments and
+// entry offsets (job buffers only, so they are built once per job list)
+struct DescTables {
+    std::vector<fsg_job*> jobs;
+    void* dev = nullptr;   // DescArgs[G], int64[G+1]
+    void* host = nullptr;
+    DescArgs a0;
+};
+
+static void free_desc_tables(fsg_ctx* ctx, DescTables* T) {
+    dev_free(ctx, T->dev);
+    host_free(ctx, T->host);
+    delete T;
+}
+
 
 }  // namespace fsg
 
@@ -950,12 +974,6 @@ struct fsg_job {
     double* M = nullptr;       // root-pass bins [n][2^root_D]
     uint16_t* mask = nullptr;  // precision mode: keep masks of the root pass
     float* ntheta = nullptr;   // precision mode: keep-thresholds of the root pass
-    // leaf stage: samples grouped by node [ns], node starts [2^leaf_level + 1],
-    // work items [2 leaf_max_items] followed by their count
-    int32_t* leaf_sorted = nullptr;
-    int32_t* leaf_starts = nullptr;
-    int32_t* leaf_items = nullptr;
-    int64_t leaf_items_max = 0;
     std::vector<void*> owned;  // device blocks from the context's pool
 };
 
@@ -995,6 +1013,16 @@ static void batch_cache_drop(fsg_ctx* ctx, const fsg_job* j) {
             (void)hipStreamSynchronize(ctx->stream);
             free_leaf_tables(ctx, lc[i]);
             lc.erase(lc.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    auto& dc = ctx->desc_cache;
+    for (size_t i = 0; i < dc.size();) {
+        if (std::find(dc[i]->jobs.begin(), dc[i]->jobs.end(), j) != dc[i]->jobs.end()) {
+            (void)hipStreamSynchronize(ctx->stream);
+            free_desc_tables(ctx, dc[i]);
+            dc.erase(dc.begin() + i);
         } else {
             ++i;
         }
@@ -1240,14 +1268,26 @@ static fsg_status leaf_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, Leaf
             return FSG_OK;
         }
     const int32_t G = (int32_t)g.size();
-    const size_t o_off = align256(G * sizeof(LeafArgs));
-    const size_t bytes = align256(o_off + (G + 1) * sizeof(int64_t));
+    const size_t o_keyjobs = align256(G * sizeof(LeafArgs));
+    const size_t o_soff = align256(o_keyjobs + G * sizeof(LeafKeyJob));
+    const size_t o_noff = align256(o_soff + (G + 1) * sizeof(int64_t));
+    const size_t bytes = align256(o_noff + (G + 1) * sizeof(int32_t));
     LeafTables* T = new LeafTables();
     T->jobs = g;
     auto fail = [&](fsg_status s) {
         free_leaf_tables(ctx, T);
         return s;
     };
+    int64_t S = 0, N = 0;
+    for (const fsg_job* j : g) {
+        S += j->S.ns;
+        N += (int64_t)1 << j->S.plan.leaf_level;
+    }
+    if (S + 1 > 2147483647LL || N + 1 > 2147483647LL)
+        return fail(set_error(ctx, FSG_E_UNSUPPORTED, "a batched leaf stage holds more than 2^31 samples or nodes"));
+    T->samples = S;
+    T->nodes = N;
+    T->max_items = S / 64 + N + 1;
     if (hipMalloc(&T->dev, bytes) != hipSuccess || hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(set_error(ctx, FSG_E_NOMEM, "allocation of leaf tables failed"));
@@ -1255,20 +1295,27 @@ static fsg_status leaf_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, Leaf
     char* h = (char*)T->host;
     std::memset(h, 0, bytes);
     LeafArgs* hargs = (LeafArgs*)h;
-    int64_t* hoff = (int64_t*)(h + o_off);
-    int64_t total = 0;
+    LeafKeyJob* hkey = (LeafKeyJob*)(h + o_keyjobs);
+    int64_t* hsoff = (int64_t*)(h + o_soff);
+    int32_t* hnoff = (int32_t*)(h + o_noff);
+    int64_t soff = 0;
+    int32_t noff = 0;
     fsg_status st;
     for (int32_t i = 0; i < G; ++i) {
         const fsg_job* j = g[i];
         const int32_t* bnd = level_bounds(j->S.X, j->S.plan.leaf_level, &st);
         if (!bnd) return fail(st);
-        hargs[i] = leaf_args(j->S, bnd, j->leaf_sorted, j->leaf_starts, j->leaf_items,
-                             j->leaf_items + 2 * j->leaf_items_max);
-        hoff[i] = total;
-        total += j->leaf_items_max;
+        // (the combined grouping arrays are the launch's, in a0)
+        hargs[i] = leaf_args(j->S, bnd, nullptr, nullptr, nullptr, nullptr);
+        hkey[i].node = j->S.node;
+        hkey[i].nbr = j->S.nbr;
+        hsoff[i] = soff;
+        hnoff[i] = noff;
+        soff += j->S.ns;
+        noff += (int32_t)(1 << j->S.plan.leaf_level);
     }
-    hoff[G] = total;
-    T->slots = total;
+    hsoff[G] = soff;
+    hnoff[G] = noff;
     const hipError_t e = hipMemcpyAsync(T->dev, T->host, bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1276,40 +1323,111 @@ static fsg_status leaf_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, Leaf
     }
     T->a0 = hargs[0];
     T->a0.jobs = (const LeafArgs*)T->dev;
-    T->a0.job_slot_off = (const int64_t*)((char*)T->dev + o_off);
+    T->a0.job_node_off = (const int32_t*)((char*)T->dev + o_noff);
     T->a0.n_jobs = G;
+    T->key_jobs = (const LeafKeyJob*)((char*)T->dev + o_keyjobs);
+    T->sample_off = (const int64_t*)((char*)T->dev + o_soff);
+    T->node_off = (const int32_t*)((char*)T->dev + o_noff);
     ctx->leaf_cache.push_back(T);
     *out = T;
     return FSG_OK;
 }
 
-// Leaf stages of a group of jobs (one class of d) in one launch: each job's
-// samples are grouped by node into its own buffers and its work items listed,
-// then one kernel walks the items of all of them.  Per item the work is that
-// of the single-set leaf stage, so the results are the same bit for bit.
+// Leaf stages of a group of jobs (one class of d) in a few launches: one
+// sort groups every job's samples by global node id (job-major, stable, so
+// each node's samples keep the order the single-set sort gives them), one
+// pass lists the work items of all nodes, and one kernel walks them.  Per item
+// the work is that of the single-set leaf stage, so the results are the same
+// bit for bit.
 static fsg_status batch_leaf(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
     fsg_status st;
-    for (fsg_job* j : g) {
-        const Sampler& S = j->S;
-        const int lv = S.plan.leaf_level;
-        const int64_t n_nodes = (int64_t)1 << lv;
-        int32_t *sorted, *starts;
-        if ((st = group_by_node(ctx, S.node, S.ns, lv, &sorted, &starts, j->leaf_sorted, j->leaf_starts)) != FSG_OK)
-            return st;
-        if (!level_bounds(S.X, lv, &st)) return st;
-        int64_t* scratch;
-        if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (n_nodes + 1) + 1 + scan_partials(n_nodes)), &scratch)) !=
-            FSG_OK)
-            return st;
-        StageTimer t(ctx, "leaf");
-        FSG_HIP(ctx, launch_leaf_items(j->leaf_starts, n_nodes, scratch, j->leaf_items,
-                                       j->leaf_items + 2 * j->leaf_items_max, ctx->stream));
-    }
     LeafTables* T;
     if ((st = leaf_tables(ctx, g, &T)) != FSG_OK) return st;
+    SortBufs b = sort_bufs(ctx, T->samples, sizeof(uint32_t), &st);
+    if (st != FSG_OK) return st;
+    int64_t* scratch;
+    uint32_t* keys;
+    int32_t *vals, *starts, *items;
+    if ((st = ws(ctx, "leaf_scratch", (size_t)(2 * (T->nodes + 1) + 1 + scan_partials(T->nodes)), &scratch)) !=
+        FSG_OK)
+        return st;
+    if ((st = ws(ctx, "grp_keys", (size_t)T->samples, &keys)) != FSG_OK) return st;
+    if ((st = ws(ctx, "grp_vals", (size_t)T->samples, &vals)) != FSG_OK) return st;
+    if ((st = ws(ctx, "grp_starts", (size_t)T->nodes + 1, &starts)) != FSG_OK) return st;
+    if ((st = ws(ctx, "leaf_items", (size_t)(2 * T->max_items + 1), &items)) != FSG_OK) return st;
+    {
+        StageTimer t(ctx, "group");
+        FSG_HIP(ctx, launch_multi_node_keys(T->key_jobs, T->sample_off, T->node_off, (int32_t)g.size(), T->samples,
+                                            (uint32_t)T->nodes, keys, vals, ctx->stream));
+        FSG_HIP(ctx, radix_sort_u32(keys, vals, T->samples, bit_length((uint64_t)T->nodes), b, ctx->stream));
+        FSG_HIP(ctx, launch_node_starts(keys, T->samples, T->nodes, starts, ctx->stream));
+    }
     StageTimer t(ctx, "leaf");
-    FSG_HIP(ctx, launch_leaf(T->a0, T->slots, ctx->num_cus, ctx->stream));
-    for (fsg_job* j : g) FSG_HIP(ctx, launch_finish_inactive(j->S.node, j->S.ns, j->S.nbr, ctx->stream));
+    FSG_HIP(ctx, launch_leaf_items(starts, T->nodes, scratch, items, items + 2 * T->max_items, ctx->stream));
+    LeafArgs a0 = T->a0;
+    a0.sorted_samples = vals;
+    a0.node_start = starts;
+    a0.items = items;
+    a0.n_items = items + 2 * T->max_items;
+    FSG_HIP(ctx, launch_leaf(a0, T->max_items, ctx->num_cus, ctx->stream));
+    return FSG_OK;
+}
+
+// The descents over the root bins of several jobs in one launch (a block per
+// point, as for one job: the same results).
+static fsg_status batch_root_descend(fsg_ctx* ctx, const std::vector<fsg_job*>& g) {
+    if (g.size() == 1) return stage_root_descend(ctx, g[0]->S, g[0]->M);
+    DescTables* T = nullptr;
+    for (DescTables* c : ctx->desc_cache)
+        if (c->jobs == g) T = c;
+    if (!T) {
+        const int32_t G = (int32_t)g.size();
+        const size_t o_off = align256(G * sizeof(DescArgs));
+        const size_t bytes = align256(o_off + (G + 1) * sizeof(int64_t));
+        T = new DescTables();
+        T->jobs = g;
+        if (hipMalloc(&T->dev, bytes) != hipSuccess ||
+            hipHostMalloc(&T->host, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            free_desc_tables(ctx, T);
+            return set_error(ctx, FSG_E_NOMEM, "allocation of descent tables failed");
+        }
+        char* h = (char*)T->host;
+        std::memset(h, 0, bytes);
+        DescArgs* hargs = (DescArgs*)h;
+        int64_t* hoff = (int64_t*)(h + o_off);
+        int64_t total = 0;
+        size_t lds = 0;
+        for (int32_t i = 0; i < G; ++i) {
+            const fsg_job* j = g[i];
+            DescArgs da = desc_args(j->S, 0);
+            da.M = j->M;
+            da.n_entries = j->S.X->n;
+            da.entry_sample = nullptr;
+            da.deg = j->S.deg;
+            int32_t ng = 0;
+            lds = std::max(lds, desc_root_lds(da, &ng));
+            hargs[i] = da;
+            hoff[i] = total;
+            total += da.n_entries;
+        }
+        hoff[G] = total;
+        const hipError_t e = hipMemcpyAsync(T->dev, T->host, bytes, hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            free_desc_tables(ctx, T);
+            return set_error(ctx, FSG_E_DEVICE, std::string("descent tables: ") + hipGetErrorString(e));
+        }
+        T->a0 = hargs[0];
+        T->a0.n_entries = total;
+        T->a0.jobs = (const DescArgs*)T->dev;
+        T->a0.job_entry_off = (const int64_t*)((char*)T->dev + o_off);
+        T->a0.n_jobs = G;
+        T->a0.lds_bytes = lds;
+        ctx->desc_cache.push_back(T);
+    }
+    StageTimer t(ctx, "descend");
+    FSG_HIP(ctx, launch_descend_bins(T->a0, ctx->stream));
     return FSG_OK;
 }
 
@@ -1384,6 +1502,8 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
     ctx->batch_cache.clear();
     for (LeafTables* T : ctx->leaf_cache) free_leaf_tables(ctx, T);
     ctx->leaf_cache.clear();
+    for (DescTables* T : ctx->desc_cache) free_desc_tables(ctx, T);
+    ctx->desc_cache.clear();
     // live jobs are detached; their buffers are freed here
     for (fsg_job* j : ctx->jobs) {
         for (void* v : j->owned) {
@@ -1795,14 +1915,6 @@ fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int3
     if (!(j->S.deg = (double*)job_alloc(j, n * sizeof(double), &st))) return fail(st);
     if (j->S.n_uleaf > 0 && !(j->S.uleaf = (double*)job_alloc(j, ns * j->S.n_uleaf * sizeof(double), &st)))
         return fail(st);
-    {
-        const int lv = j->S.plan.leaf_level;
-        j->leaf_items_max = leaf_max_items(ns, lv);
-        if (!(j->leaf_sorted = (int32_t*)job_alloc(j, (size_t)ns * sizeof(int32_t), &st))) return fail(st);
-        if (!(j->leaf_starts = (int32_t*)job_alloc(j, (((size_t)1 << lv) + 1) * sizeof(int32_t), &st))) return fail(st);
-        if (!(j->leaf_items = (int32_t*)job_alloc(j, (size_t)(2 * j->leaf_items_max + 1) * sizeof(int32_t), &st)))
-            return fail(st);
-    }
     if (!j->S.plan.passes.empty()) {
         j->root_D = j->S.plan.passes[0].second;
         if (!(j->M = (double*)job_alloc(j, (size_t)(n << j->root_D) * sizeof(double), &st))) return fail(st);
@@ -1842,6 +1954,13 @@ fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, in
     }
     for (auto& kv : groups)
         if ((st = batch_root(ctx, kv.second)) != FSG_OK) return st;
+    // root descents of every job in its root stage: one launch
+    {
+        std::vector<fsg_job*> desc;
+        for (int32_t i = 0; i < n_jobs; ++i)
+            if (jobs[i]->stage == 0 && !jobs[i]->S.plan.passes.empty()) desc.push_back(jobs[i]);
+        if (!desc.empty() && (st = batch_root_descend(ctx, desc)) != FSG_OK) return st;
+    }
     // leaf stages: grouped by class of d, one launch per group
     std::map<int, std::vector<fsg_job*>> leaf_groups;
     for (int32_t i = 0; i < n_jobs; ++i) {
@@ -1849,7 +1968,7 @@ fsg_status fsg_batch_step(fsg_ctx* ctx, fsg_job* const* jobs, int32_t n_jobs, in
         if (j->stage >= j->n_stages) continue;
         const int P = (int)j->S.plan.passes.size();
         if (j->stage == 0 && P > 0) {
-            if ((st = stage_root_descend(ctx, j->S, j->M)) != FSG_OK) return st;
+            // (descended above)
         } else if (j->stage < P) {
             if ((st = stage_pass(ctx, j->S, (size_t)j->stage)) != FSG_OK) return st;
         } else {

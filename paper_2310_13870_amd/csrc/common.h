@@ -176,6 +176,7 @@ struct Arena;
 namespace fsg {
 struct BatchTables;  // device tables of a batched root pass (api.hip)
 struct LeafTables;   // device tables of a batched leaf stage (api.hip)
+struct DescTables;   // device tables of a batched root descent (api.hip)
 }
 struct fsg_server;
 
@@ -216,6 +217,7 @@ struct fsg_ctx {
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     std::vector<fsg::BatchTables*> batch_cache;
     std::vector<fsg::LeafTables*> leaf_cache;
+    std::vector<fsg::DescTables*> desc_cache;
     // live batch jobs; their buffers are freed and they are detached when the
     // context is destroyed
     std::set<fsg_job*> jobs;
@@ -417,8 +419,17 @@ struct DescArgs {
     // uleaf[sample * n_uleaf + k] = u(level = start_level + D + k)
     double* uleaf;
     int32_t n_uleaf;
+    // root passes of several point sets in one launch (jobs != NULL): entries
+    // [job_entry_off[k], job_entry_off[k+1]) are job k's, with the arguments
+    // jobs[k]; n_entries is the total and lds_bytes the largest job's LDS
+    const DescArgs* jobs;
+    const int64_t* job_entry_off;
+    int32_t n_jobs;
+    size_t lds_bytes;
 };
 hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st);
+// LDS bytes and Philox level groups of a root descent
+size_t desc_root_lds(const DescArgs& a, int32_t* n_groups);
 
 struct LeafArgs {
     const float* X;            // FP32 points
@@ -439,13 +450,27 @@ struct LeafArgs {
     float* margin;
     const double* uleaf;            // precomputed uniforms of the leaf levels (NULL: computed here)
     int32_t n_uleaf;
-    // several point sets in one launch (jobs != NULL): job k's items take the
-    // work slots [job_slot_off[k], job_slot_off[k+1]) (at most its item bound;
-    // slots past its *n_items are idle), its arguments jobs[k]
+    // several point sets in one launch (jobs != NULL): their samples were
+    // grouped by one sort over global node ids (job k's nodes are
+    // [job_node_off[k], job_node_off[k+1])); items and n_items are the
+    // combined work list (global node, global position), node_start the
+    // combined node starts (global positions) and sorted_samples the combined
+    // list of job-local sample ids; jobs[k] holds job k's other arguments
     const LeafArgs* jobs;
-    const int64_t* job_slot_off;
+    const int32_t* job_node_off;
     int32_t n_jobs;
 };
+// The grouping keys of several jobs' samples in one launch: sample s of job k
+// (global position sample_off[k] + s) gets key node_off[k] + node, or
+// inactive_key when it has no node (its neighbour is then set to -1), and the
+// value s.
+struct LeafKeyJob {
+    const int32_t* node;
+    int32_t* nbr;
+};
+hipError_t launch_multi_node_keys(const LeafKeyJob* jobs, const int64_t* sample_off, const int32_t* node_off,
+                                  int32_t n_jobs, int64_t total, uint32_t inactive_key, uint32_t* keys, int32_t* vals,
+                                  hipStream_t st);
 // max_items: the item bound of one set, or the slots of all jobs
 hipError_t launch_leaf(const LeafArgs& a, int64_t max_items, int num_cus, hipStream_t st);
 int leaf_class(int32_t d);  // the class of d a leaf launch is built for (2, 4, ..., 128)

@@ -34,19 +34,42 @@ __device__ __forceinline__ bool choose_left(double u, double mL, double mR, bool
 constexpr int kDescThreads = 256;
 constexpr int kDescChunk = 64;
 
-__global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a, int32_t n_groups) {
+// Philox level groups a root descent draws from (the levels it resolves and
+// the leaf levels whose uniforms it stores)
+__host__ __device__ inline int32_t desc_groups(const DescArgs& a) {
+    const int32_t last_level = a.start_level + a.D - 1 + (a.uleaf != nullptr ? a.n_uleaf : 0);
+    return (last_level >> 2) - (a.start_level >> 2) + 1;
+}
+
+// MULTI: the entries of several point sets' root passes (a0.jobs), one
+// block per entry as for one set.
+template <bool MULTI>
+__global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a0, int32_t n_groups0) {
     // LDS: the internal nodes of the sum tree, tree[k] for k in [1, 2^D)
     // (children 2k, 2k+1; the bins are the leaves 2^D + b and stay in global
     // memory), then the Philox blocks of up to 64 samples.
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
-    const int32_t nb = 1 << a.D;
-    double* tree = smem;
-    uint64_t* words = (uint64_t*)(smem + nb);  // [kDescChunk][n_groups][4]
-    const int32_t g0 = a.start_level >> 2;
-    // bins summed per thread in registers before the LDS levels
-    const int32_t per = (nb >= 8 * kDescThreads) ? 8 : ((nb >= 2 * kDescThreads) ? nb / kDescThreads : 1);
-    for (int64_t e = blockIdx.x; e < a.n_entries; e += gridDim.x) {
+    for (int64_t ge = blockIdx.x; ge < a0.n_entries; ge += gridDim.x) {
+        int64_t e = ge;
+        int32_t job = 0;
+        if (MULTI) {  // the point set owning entry ge (uniform binary search)
+            int32_t lo = 0, hi = a0.n_jobs;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (a0.job_entry_off[mid] <= ge) lo = mid; else hi = mid;
+            }
+            job = lo;
+            e = ge - a0.job_entry_off[job];
+        }
+        const DescArgs& a = MULTI ? a0.jobs[job] : a0;
+        const int32_t n_groups = MULTI ? desc_groups(a) : n_groups0;
+        const int32_t nb = 1 << a.D;
+        double* tree = smem;
+        uint64_t* words = (uint64_t*)(smem + nb);  // [kDescChunk][n_groups][4]
+        const int32_t g0 = a.start_level >> 2;
+        // bins summed per thread in registers before the LDS levels
+        const int32_t per = (nb >= 8 * kDescThreads) ? 8 : ((nb >= 2 * kDescThreads) ? nb / kDescThreads : 1);
         const double* M = a.M + e * nb;
         int32_t top;  // the LDS levels built below start at nodes [top, 2 top)
         if (per >= 2) {
@@ -165,19 +188,30 @@ __global__ __launch_bounds__(256) void descend_entries_kernel(DescArgs a) {
         for (int32_t q = 0; q < a.n_uleaf; ++q) a.uleaf[(int64_t)smp * a.n_uleaf + q] = uni.at(a.start_level + D + q);
 }
 
+// Philox blocks of at most min(L, kDescChunk) samples at a time: at L = 17
+// and D = 11 this keeps a block at 19 KB (8 blocks per CU)
+size_t desc_root_lds(const DescArgs& a, int32_t* n_groups) {
+    *n_groups = desc_groups(a);
+    const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
+    return sizeof(double) * ((size_t)1 << a.D) + sizeof(uint64_t) * 4 * chunk * (*n_groups);
+}
+
 hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
     if (a.n_entries < 1) return hipSuccess;
-    if (a.entry_sample == nullptr) {
-        if (a.D < 1 || a.D > 11) return hipErrorInvalidValue;  // the tree build assumes 2 <= 2^D <= 8 * 256
-        const int32_t last_level = a.start_level + a.D - 1 + (a.uleaf != nullptr ? a.n_uleaf : 0);
-        const int32_t n_groups = (last_level >> 2) - (a.start_level >> 2) + 1;
-        // Philox blocks of at most min(L, kDescChunk) samples at a time: at
-        // L = 17 and D = 11 this keeps a block at 19 KB (8 blocks per CU)
-        const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
-        const size_t lds = sizeof(double) * ((size_t)1 << a.D) + sizeof(uint64_t) * 4 * chunk * n_groups;
+    if (a.jobs != nullptr) {  // root passes of several sets (tables built by the caller)
+        if (a.lds_bytes == 0) return hipErrorInvalidValue;
         int64_t blocks = a.n_entries;
         if (blocks > (1 << 20)) blocks = 1 << 20;
-        descend_root_kernel<<<(unsigned)blocks, kDescThreads, lds, st>>>(a, n_groups);
+        descend_root_kernel<true><<<(unsigned)blocks, kDescThreads, a.lds_bytes, st>>>(a, 0);
+        return hipGetLastError();
+    }
+    if (a.entry_sample == nullptr) {
+        if (a.D < 1 || a.D > 11) return hipErrorInvalidValue;  // the tree build assumes 2 <= 2^D <= 8 * 256
+        int32_t n_groups = 0;
+        const size_t lds = desc_root_lds(a, &n_groups);
+        int64_t blocks = a.n_entries;
+        if (blocks > (1 << 20)) blocks = 1 << 20;
+        descend_root_kernel<false><<<(unsigned)blocks, kDescThreads, lds, st>>>(a, n_groups);
         return hipGetLastError();
     }
     const unsigned blocks = (unsigned)((a.n_entries + 255) / 256);
@@ -230,30 +264,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
     __shared__ double exp_tab[256];
     load_exp2_table(exp_tab);
     const int lane = threadIdx.x;
-    const int64_t n_slots = MULTI ? a0.job_slot_off[a0.n_jobs] : (int64_t)*a0.n_items;
-    for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
-        int64_t it = slot;
+    const int64_t n_items = (int64_t)*a0.n_items;
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        int32_t v = a0.items[2 * it];
+        const int32_t p0 = a0.items[2 * it + 1];
         int32_t job = 0;
-        if (MULTI) {  // the job owning the slot (binary search, uniform)
+        if (MULTI) {  // the job owning global node v (binary search, uniform)
             int32_t lo_j = 0, hi_j = a0.n_jobs;
             while (hi_j - lo_j > 1) {
                 const int32_t mid_j = (lo_j + hi_j) >> 1;
-                if (a0.job_slot_off[mid_j] <= slot) lo_j = mid_j; else hi_j = mid_j;
+                if (a0.job_node_off[mid_j] <= v) lo_j = mid_j; else hi_j = mid_j;
             }
             job = lo_j;
-            it = slot - a0.job_slot_off[job];
+            v -= a0.job_node_off[job];
         }
         const LeafArgs& a = MULTI ? a0.jobs[job] : a0;
-        if (MULTI && it >= (int64_t)*a.n_items) continue;  // an idle slot (uniform: no barrier is skipped alone)
         const double s256 = 256.0 * a.s, two_s = 2.0 * s256;
-        const int32_t v = a.items[2 * it], p0 = a.items[2 * it + 1];
-        const int32_t p1 = a.node_start[v + 1];
+        // the grouping of a multi-set launch is the launch's own (global
+        // positions, job-local sample ids)
+        const int32_t* nstart = MULTI ? a0.node_start + a0.job_node_off[job] : a.node_start;
+        const int32_t* sorted = MULTI ? a0.sorted_samples : a.sorted_samples;
+        const int32_t p1 = nstart[v + 1];
         const int32_t lo = a.bounds[v];
         const int32_t hi = min(a.bounds[v + 1], lo + kLeafMax);  // the planner keeps nodes within kLeafMax
         const int32_t cnt = hi - lo;
         const int32_t pos = p0 + lane;
         const bool active = pos < p1;
-        const int32_t smp = active ? a.sorted_samples[pos] : a.sorted_samples[p0];
+        const int32_t smp = active ? sorted[pos] : sorted[p0];
         const int32_t i = smp / a.L, l = smp - i * a.L;
         const float* xi = a.X + (int64_t)i * a.d;
         const int32_t self = i - lo;  // the sample's own point, if it lies in the node
@@ -510,6 +547,32 @@ hipError_t launch_leaf_items(const int32_t* node_start, int64_t n_nodes, int64_t
     if (e != hipSuccess) return e;
     leaf_item_fill_kernel<<<(unsigned)((n_nodes + 255) / 256 + 1), 256, 0, st>>>(node_start, offsets, n_nodes, total,
                                                                                items, n_items);
+    return hipGetLastError();
+}
+
+__global__ void multi_node_keys_kernel(const LeafKeyJob* __restrict__ jobs, const int64_t* __restrict__ sample_off,
+                                       const int32_t* __restrict__ node_off, int32_t n_jobs, int64_t total,
+                                       uint32_t inactive_key, uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (sample_off[mid] <= g) lo = mid; else hi = mid;
+    }
+    const int64_t s = g - sample_off[lo];
+    const int32_t v = jobs[lo].node[s];
+    if (v < 0) jobs[lo].nbr[s] = -1;  // no neighbour (an isolated point)
+    keys[g] = v < 0 ? inactive_key : (uint32_t)(node_off[lo] + v);
+    vals[g] = (int32_t)s;
+}
+
+hipError_t launch_multi_node_keys(const LeafKeyJob* jobs, const int64_t* sample_off, const int32_t* node_off,
+                                  int32_t n_jobs, int64_t total, uint32_t inactive_key, uint32_t* keys, int32_t* vals,
+                                  hipStream_t st) {
+    if (total == 0) return hipSuccess;
+    multi_node_keys_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(jobs, sample_off, node_off, n_jobs, total,
+                                                                          inactive_key, keys, vals);
     return hipGetLastError();
 }
 
