@@ -287,6 +287,15 @@ fsg_status fsg_ctx_set_autotune(fsg_ctx* ctx, int32_t enabled);
 fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int32_t* waves_per_cu,
                                int32_t* cols_per_item);
 
+/* The tuned shapes outlive the context in a small text file: save writes
+ * every tuned class with the device's architecture name and compute-unit
+ * count; load reads a file written on the same kind of device (other files
+ * load nothing) and *n_loaded (may be NULL) receives the classes taken over,
+ * which are then not tuned again.  FSG_E_INVALID if the file cannot be
+ * written, or read or parsed. */
+fsg_status fsg_ctx_save_tuning(fsg_ctx* ctx, const char* path);
+fsg_status fsg_ctx_load_tuning(fsg_ctx* ctx, const char* path, int32_t* n_loaded);
+
 /* ------------------------------------------------------------------------
  * HIP graphs of the context's stream: everything enqueued between
  * fsg_graph_begin and fsg_graph_end (which must not synchronise; e.g.

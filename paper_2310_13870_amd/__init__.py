@@ -67,6 +67,8 @@ _lib_fns = dict(
     fsg_job_outputs=_sig("fsg_job_outputs", ctypes.c_int, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)),
     fsg_job_destroy=_sig("fsg_job_destroy", None, _vp),
     fsg_ctx_set_autotune=_sig("fsg_ctx_set_autotune", ctypes.c_int, _vp, _i32),
+    fsg_ctx_save_tuning=_sig("fsg_ctx_save_tuning", ctypes.c_int, _vp, ctypes.c_char_p),
+    fsg_ctx_load_tuning=_sig("fsg_ctx_load_tuning", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_i32)),
     fsg_ctx_tuned_shape=_sig("fsg_ctx_tuned_shape", ctypes.c_int, _vp, _i32, ctypes.c_int, ctypes.POINTER(_i32),
                              ctypes.POINTER(_i32)),
     fsg_graph_begin=_sig("fsg_graph_begin", ctypes.c_int, _vp),
@@ -181,6 +183,15 @@ class Context:
         w, c = _i32(0), _i32(0)
         st = _lib.fsg_ctx_tuned_shape(self._h, D4, precision, ctypes.byref(w), ctypes.byref(c))
         return (w.value, c.value) if st == FSG_OK else None
+
+    def save_tuning(self, path: str):
+        self.check(_lib.fsg_ctx_save_tuning(self._h, os.fsencode(path)))
+
+    def load_tuning(self, path: str) -> int:
+        """Tuned shapes from a file written on the same kind of device; returns how many were taken over."""
+        n = _i32(0)
+        self.check(_lib.fsg_ctx_load_tuning(self._h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,6 +1,7 @@
 // C ABI of libfsg.so: argument checks, workspace, pass planning and the
 // orchestration of the kernels on the context's stream.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -1469,6 +1470,7 @@ fsg_status fsg_ctx_create(int device, void* hip_stream, uint64_t ws_budget_bytes
     c->stream = (hipStream_t)hip_stream;
     c->budget = ws_budget_bytes ? ws_budget_bytes : ((uint64_t)32 << 30);
     c->num_cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     c->noalloc_scratch = noalloc_scratch_setup(device);  // with `device` current
     if (hipHostMalloc((void**)&c->host_scratch, 64, hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -2039,6 +2041,51 @@ fsg_status fsg_ctx_tuned_shape(fsg_ctx* ctx, int32_t D4, fsg_precision prec, int
     if (it == ctx->tuned.end()) return set_error(ctx, FSG_E_INVALID, "no tuned shape for this class");
     *waves_per_cu = it->second.first;
     *cols_per_item = it->second.second;
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_save_tuning(fsg_ctx* ctx, const char* path) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!path) return set_error(ctx, FSG_E_INVALID, "NULL path");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_error(ctx, FSG_E_INVALID, std::string("cannot write ") + path);
+    std::fprintf(f, "fsg-tuning 1 %s %d\n", ctx->arch.c_str(), ctx->num_cus);
+    for (const auto& kv : ctx->tuned)
+        std::fprintf(f, "%d %d %d %d\n", kv.first.first, kv.first.second, kv.second.first, kv.second.second);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? FSG_OK : set_error(ctx, FSG_E_INVALID, std::string("cannot write ") + path);
+}
+
+fsg_status fsg_ctx_load_tuning(fsg_ctx* ctx, const char* path, int32_t* n_loaded) {
+    if (!ctx) return FSG_E_INVALID;
+    if (n_loaded) *n_loaded = 0;
+    if (!path) return set_error(ctx, FSG_E_INVALID, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_error(ctx, FSG_E_INVALID, std::string("cannot read ") + path);
+    char tag[32] = {0}, arch[128] = {0};
+    int version = 0, cus = 0;
+    if (std::fscanf(f, "%31s %d %127s %d", tag, &version, arch, &cus) != 4 || std::strcmp(tag, "fsg-tuning") != 0 ||
+        version != 1) {
+        std::fclose(f);
+        return set_error(ctx, FSG_E_INVALID, std::string("not a tuning file: ") + path);
+    }
+    int32_t loaded = 0;
+    if (ctx->arch == arch && ctx->num_cus == cus) {
+        int D4, prec, waves, cols;
+        while (std::fscanf(f, "%d %d %d %d", &D4, &prec, &waves, &cols) == 4) {
+            const bool sane = (D4 == 1 || D4 == 2 || D4 == 4 || D4 == 8 || D4 == 16 || D4 == 32) &&
+                              (prec == FSG_PLAIN_FP64 || prec == FSG_BF16_SPLIT) && waves >= 1 && waves <= 64 &&
+                              cols >= 0 && cols <= (1 << 24);
+            if (!sane) {
+                std::fclose(f);
+                return set_error(ctx, FSG_E_INVALID, std::string("bad entry in tuning file ") + path);
+            }
+            ctx->tuned[{D4, prec}] = {waves, cols};
+            ++loaded;
+        }
+    }
+    std::fclose(f);
+    if (n_loaded) *n_loaded = loaded;
     return FSG_OK;
 }
 

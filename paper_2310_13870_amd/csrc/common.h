@@ -185,6 +185,7 @@ struct fsg_ctx {
     hipStream_t stream = nullptr;
     uint64_t budget = 0;
     int num_cus = 256;
+    std::string arch;  // gcnArchName of the device
     std::string last_error;
     // workspace: named device buffers that grow on demand (never shrink)
     std::map<std::string, std::pair<void*, size_t>> bufs;

@@ -178,3 +178,48 @@ def test_graph_replay_after_workspace_growth(prec):
         finally:
             s.synchronize()
             ctx.close()
+
+
+def test_tuning_saved_and_loaded(tmp_path):
+    """Tuned launch shapes written by one context are taken over by another
+    on the same device (and not tuned again); results are unchanged."""
+    sets = SETS[2:6]
+    path = str(tmp_path / "tuning.txt")
+    ctx = fsg.Context(0)
+    try:
+        pts = _points(ctx, sets, "plain_fp64", 7900)
+        jobs = [fsg.Job(ctx, p, gamma, L, seed) for p, gamma, L, seed in pts]
+        fsg.batch_run(ctx, jobs)
+        a = [tuple(t.cpu() for t in j.result()) for j in jobs]
+        shape = ctx.tuned_shape(8)
+        assert shape is not None
+        ctx.save_tuning(path)
+        for j in jobs:
+            j.close()
+    finally:
+        ctx.close()
+    text = open(path).read()
+    say(f"tuning file: {text.strip()}")
+    assert text.startswith("fsg-tuning 1 gfx950")
+    ctx2 = fsg.Context(0)
+    try:
+        n = ctx2.load_tuning(path)
+        assert n >= 1 and ctx2.tuned_shape(8) == shape
+        pts2 = _points(ctx2, sets, "plain_fp64", 7900)
+        jobs2 = [fsg.Job(ctx2, p, gamma, L, seed) for p, gamma, L, seed in pts2]
+        fsg.batch_run(ctx2, jobs2)
+        for (n1, d1), j in zip(a, jobs2):
+            n2, d2 = j.result()
+            assert torch.equal(n1, n2.cpu()) and torch.equal(d1, d2.cpu())
+        assert ctx2.tuned_shape(8) == shape
+        bad = tmp_path / "bad.txt"
+        bad.write_text("not a tuning file\n")
+        with pytest.raises(fsg.FsgError):
+            ctx2.load_tuning(str(bad))
+        other = tmp_path / "other.txt"
+        other.write_text("fsg-tuning 1 gfx000 7\n8 0 4 1024\n")
+        assert ctx2.load_tuning(str(other)) == 0
+        for j in jobs2:
+            j.close()
+    finally:
+        ctx2.close()
