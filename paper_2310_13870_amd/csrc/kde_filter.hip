@@ -29,10 +29,11 @@
 
 namespace fsg {
 
-// exact-pass occupancy: two waves per SIMD where the FP64 query fragments of
-// 64-entry items leave room
+// exact-pass occupancy: two waves per SIMD (the query fragments are staged
+// in LDS in FP32 -- the points' own precision, so the copy is exact -- which
+// leaves room for two blocks of four waves per compute unit)
 template <int D4>
-constexpr int exact_waves() { return D4 <= 8 ? 2 : 1; }
+constexpr int exact_waves() { return 2; }
 
 // ---------------------------------------------------------------------------
 // Stage 2: exact recompute of the kept columns.  Work item = (query tile,
@@ -58,14 +59,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
     // queue length: fewer than 16 entries left over plus one batch of 256 columns
     constexpr int QN = 288;
     __shared__ int32_t queue_all[4][QN];
-    __shared__ double qf_all[4][RQ * D4 * 64];
+    __shared__ float qf_all[4][RQ * D4 * 64];
     __shared__ int32_t win_all[4][kBinWindow];
     __shared__ double exp_tab[256];
     load_exp2_table(exp_tab);
     const int lane = threadIdx.x & 63;
     int32_t* win = win_all[threadIdx.x >> 6];
     int32_t* queue = queue_all[threadIdx.x >> 6];
-    double* qf = qf_all[threadIdx.x >> 6];  // [qb][kk][lane]
+    float* qf = qf_all[threadIdx.x >> 6];  // [qb][kk][lane]
     const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int32_t n_items = *a.n_items;
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             double qv[D4];
             load_row_part<D4>(qv, J.Qp, p, grp);
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = qv[kk];
+            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = (float)qv[kk];  // exact
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             for (int qb = 0; qb < RQ; ++qb) {
                 double qv[D4];
 #pragma unroll
-                for (int kk = 0; kk < D4; ++kk) qv[kk] = qf[(qb * D4 + kk) * 64 + lane];
+                for (int kk = 0; kk < D4; ++kk) qv[kk] = (double)qf[(qb * D4 + kk) * 64 + lane];
                 c[qb] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int kk = 0; kk < D4; ++kk) c[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.xf[kk], qv[kk], c[qb], 0, 0, 0);
