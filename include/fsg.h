@@ -134,6 +134,20 @@ fsg_status fsg_ctx_filter_stats(fsg_ctx* ctx, int64_t* kept, int64_t* scanned);
  * FSG_E_INVALID for an unknown kind. */
 fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind);
 
+/* Error budget of the precision mode's KDE over all points (the root pass of
+ * fsg_sample_edges and fsg_degrees; batch jobs and servers always use 0).
+ * eps = 0 (default): pairs more than Delta = ln n + 25 below their row's
+ * largest exponent term are dropped, so that every degree loses less than
+ * e^-25 of itself and a sampled neighbour differs from the exact method's
+ * with probability below ceil(log2 n) e^-25.  0 < eps < 1: the paper's
+ * approximate-KDE regime (Theorem 1 asks for (1 +- eps)-accurate KDEs with
+ * eps <= 1/(6 log2 n)): Delta = ln(n-1) + ln(1/eps), so every degree is
+ * within [1 - eps, 1] of the exact one, the sampled neighbour's distribution
+ * is within total variation eps of the exact k/deg (Lemma 1's telescoping
+ * product holds for the kept kernel values), and fewer pairs are recomputed.
+ * FSG_E_INVALID outside [0, 1). */
+fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps);
+
 /* Tile pruning of the precision mode (default on): before the BF16 keep-mask
  * scan of a pass over all points, each 64-query tile is checked against the
  * cells of the 256 pivots (points grouped by nearest pivot, each with an upper

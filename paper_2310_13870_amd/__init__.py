@@ -43,6 +43,7 @@ _lib_fns = dict(
     fsg_ctx_set_levels_per_pass=_sig("fsg_ctx_set_levels_per_pass", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_pruning=_sig("fsg_ctx_set_pruning", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_kernel=_sig("fsg_ctx_set_kernel", ctypes.c_int, _vp, ctypes.c_int),
+    fsg_ctx_set_kde_error=_sig("fsg_ctx_set_kde_error", ctypes.c_int, _vp, _dbl),
     fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_stage_time=_sig("fsg_ctx_stage_time", ctypes.c_int, _vp, ctypes.c_char_p, ctypes.POINTER(_dbl),
                             ctypes.POINTER(_i64)),
@@ -145,6 +146,10 @@ class Context:
         if isinstance(kind, str):
             kind = KERNELS[kind]
         self.check(_lib.fsg_ctx_set_kernel(self._h, kind))
+
+    def set_kde_error(self, eps: float):
+        """Precision mode: the share of every degree the root KDE may drop (0: e^-25, the exact mode)."""
+        self.check(_lib.fsg_ctx_set_kde_error(self._h, float(eps)))
 
     def set_pruning(self, enabled: bool):
         """Precision mode: skip (query tile, cell) pairs that cannot keep a column (default on)."""

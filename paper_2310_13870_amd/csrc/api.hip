@@ -340,7 +340,16 @@ static int64_t mask_chunk_blocks(int64_t n_blocks, int64_t n_groups, int64_t n_w
 // Keep-mask arguments of a root pass over point set X (precision mode):
 // entries are the points in pivot order, so that each 64-query tile holds
 // points close together and keeps few columns.
-static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus, int32_t kind = FSG_GAUSSIAN) {
+// kde_error = 0: drop only pairs more than Delta = ln n + 25 below their
+// row's largest term (the exact mode); kde_error = eps > 0: Delta = ln(n-1) +
+// ln(1/eps), so that the dropped total is below eps of every degree.
+static double margin_for(int64_t n, double kde_error) {
+    if (kde_error > 0.0 && n >= 2) return std::log((double)(n - 1)) - std::log(kde_error);
+    return std::log((double)n) + kMarginExtra;
+}
+
+static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus, int32_t kind = FSG_GAUSSIAN,
+                               double kde_error = 0.0) {
     MaskArgs m;
     std::memset(&m, 0, sizeof(m));
     m.kind = kind;
@@ -356,7 +365,7 @@ static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus, i
     m.qnorm = X->norm;
     m.dmin = X->dmin;
     m.xmax = X->xmax;
-    m.margin_z = std::log((double)n) + kMarginExtra;
+    m.margin_z = margin_for(n, kde_error);
     m.eps = 1.0 / 1024.0;
     m.gamma = gamma;
     m.n_tiles = (n + kTileQ - 1) / kTileQ;
@@ -525,7 +534,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         // together and keep few columns; rows are written by point
         a.q_idx = X->order;
         a.out_rows = X->order;
-        MaskArgs m = root_mask_args(X, gamma, ctx->num_cus, ctx->kernel);
+        MaskArgs m = root_mask_args(X, gamma, ctx->num_cus, ctx->kernel, ctx->kde_error);
         float* ntheta;
         if ((st = ws(ctx, "mask_theta", (size_t)theta_entries(n), &ntheta)) != FSG_OK) return st;
         FSG_HIP(ctx, launch_mask_theta(m, ntheta, theta_entries(n), ctx->stream));
@@ -1538,6 +1547,13 @@ fsg_status fsg_ctx_sync(fsg_ctx* ctx) {
 }
 
 uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps) {
+    if (!ctx) return FSG_E_INVALID;
+    if (!(eps >= 0.0 && eps < 1.0)) return set_error(ctx, FSG_E_INVALID, "eps must be in [0, 1)");
+    ctx->kde_error = eps;
+    return FSG_OK;
+}
 
 fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind) {
     if (!ctx) return FSG_E_INVALID;

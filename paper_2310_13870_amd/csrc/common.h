@@ -202,6 +202,8 @@ struct fsg_ctx {
     bool pruning = true;
     // kernel of later calls (fsg_ctx_set_kernel)
     fsg_kernel kernel = FSG_GAUSSIAN;
+    // precision mode: the dropped share of every degree allowed (0: e^-25)
+    double kde_error = 0.0;
     // precision-mode statistics (device counters)
     int64_t* filter_counts = nullptr;  // [kept, scanned]
     // live point sets; detached (their ctx cleared) when the context is destroyed

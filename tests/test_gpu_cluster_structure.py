@@ -58,3 +58,24 @@ def test_gpu_graph_preserves_clusters_n20k(prec, shape):
     W = sparse_from_csr(n, rp, col, w)
     assert (W != W.T).nnz == 0
     say(f"{shape} {prec}: " + check_cluster_preserving_large(full_kernel_blocked(X, gamma), W, lab))
+
+
+def test_gpu_graph_preserves_clusters_eps_mode():
+    """The approximate-KDE regime (eps = 1/(6 ceil(log2 n)) of every degree may
+    be dropped) keeps the cluster structure: two moons, n = 20,000."""
+    import math
+    from tests.cluster_common import check_cluster_preserving_large, full_kernel_blocked, moons_case, sparse_from_csr
+    X, lab, gamma, L = moons_case("moons-n20k", 63)
+    n = X.shape[0]
+    ctx = fsg.Context(0)
+    try:
+        ctx.set_kde_error(1.0 / (6 * math.ceil(math.log2(n))))
+        pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 11)
+        rp, col, w = fsg.build_csr(ctx, pts, gamma, L, nbr, deg)
+        rp, col, w = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy().astype(np.float64)
+        pts.close()
+    finally:
+        ctx.close()
+    W = sparse_from_csr(n, rp, col, w)
+    say("eps mode: " + check_cluster_preserving_large(full_kernel_blocked(X, gamma), W, lab))

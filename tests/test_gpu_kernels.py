@@ -138,3 +138,41 @@ def test_unsupported_combinations_are_refused(ctx):
     fsg.Job(ctx, p, 0.1, 4, 1).close()
     p.close()
     pbf.close()
+
+
+@pytest.mark.parametrize("n,d,comps,spread", [(6000, 64, 20, 10.0), (5000, 16, 6, 3.0)])
+def test_precision_mode_eps_bounded_kde(ctx, n, d, comps, spread):
+    """The approximate-KDE regime of Theorem 1 (eps = 1/(6 ceil(log2 n))): the
+    root KDE may drop up to eps of every degree.  Degrees stay within
+    [1 - eps, 1] of the exact ones, a sampled neighbour differs from the
+    exact method's (same uniforms) with probability at most depth * eps, and
+    fewer pairs are recomputed than in the exact mode."""
+    X = workloads.mixture(n, d, comps, 900 + n, (-spread, spread), (0.5, 2.0))
+    gamma = 1.0 / (2.0 * (0.25 * math.sqrt(d)) ** 2)
+    depth = int(math.ceil(math.log2(n)))
+    eps = 1.0 / (6 * depth)
+    L = 12
+    pts = fsg.Points(ctx, to_dev(X), "bf16_split")
+    kept = {}
+    res = {}
+    for e in (0.0, eps):
+        ctx.set_kde_error(e)
+        ctx.reset_profiling()
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 23)
+        kept[e] = ctx.filter_stats()[0]
+        res[e] = (nbr.cpu().numpy(), deg.cpu().numpy())
+    ctx.set_kde_error(0.0)
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, gamma, L, 23)
+    deg = res[eps][1]
+    ratio = deg / rdeg
+    mism = float((res[eps][0] != rnbr).mean())
+    say(f"eps={eps:.4f}: kept {kept[eps]} vs exact mode {kept[0.0]}; degree ratio [{ratio.min():.6f}, "
+        f"{ratio.max():.6f}]; neighbour mismatch rate {mism:.2e} (bound {depth * eps:.3f})")
+    assert ratio.min() >= (1.0 - eps) * (1 - 1e-12) and ratio.max() <= 1.0 + 1e-12
+    assert mism <= depth * eps
+    assert kept[eps] <= kept[0.0]
+    # the exact mode still matches the oracle
+    assert np.max(np.abs(res[0.0][1] - rdeg) / rdeg) < 1e-9
+    with pytest.raises(fsg.FsgError):
+        ctx.set_kde_error(1.5)
+    pts.close()
