@@ -465,16 +465,24 @@ static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const Mask
     pa.words = (X->P + 31) / 32;
     pa.TP = TP;
     pa.n_groups = (m0.n_tiles + TP - 1) / TP;
-    pa.max_blocks = (int32_t)std::min<int64_t>(m0.blocks_per_chunk, 1 << 20);
+    // chunks of about 1.5 MB of data operands, so that the chunks an XCD
+    // scans at one time stay in its 4 MB L2
     const int64_t n_blocks_p = theta_entries(n) / 16;
-    const int64_t max_items = pa.n_groups * prune_max_items_per_group(pa.P, n_blocks_p, pa.max_blocks);
+    pa.n_blocks_p = n_blocks_p;
+    pa.chunk_blocks = (int32_t)std::max<int64_t>(32, std::min<int64_t>(1024, (1536 * 1024) / (1024 * m0.KB)));
+    pa.n_chunks = (n_blocks_p + pa.chunk_blocks - 1) / pa.chunk_blocks;
+    const int64_t pairs = pa.n_chunks * pa.n_groups;
+    const int64_t max_items = prune_max_items(pa.n_groups, pa.P, pa.n_chunks);
     int64_t* partials;
     uint16_t* maskp;
     if ((st = ws(ctx, "prune_surv", (size_t)(pa.n_tiles * pa.words), &pa.surv)) != FSG_OK) return st;
-    if ((st = ws(ctx, "prune_counts", (size_t)pa.n_groups + 1, &pa.counts)) != FSG_OK) return st;
-    if ((st = ws(ctx, "prune_offsets", (size_t)pa.n_groups + 1, &pa.offsets)) != FSG_OK) return st;
-    if ((st = ws(ctx, "prune_total", 1, &pa.total)) != FSG_OK) return st;
-    if ((st = ws(ctx, "prune_partials", (size_t)scan_partials(pa.n_groups + 1), &partials)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_counts", (size_t)pairs + 1, &pa.counts)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_offsets", (size_t)pairs + 1, &pa.offsets)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_bcounts", (size_t)pairs + 1, &pa.bcounts)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_boffsets", (size_t)pairs + 1, &pa.boffsets)) != FSG_OK) return st;
+    if ((st = ws(ctx, "prune_total", 2 + kXcds + 1, &pa.total)) != FSG_OK) return st;
+    pa.xseg = pa.total + 2;
+    if ((st = ws(ctx, "prune_partials", (size_t)scan_partials(pairs + 1), &partials)) != FSG_OK) return st;
     if ((st = ws(ctx, "prune_items", (size_t)(3 * max_items), &pa.items)) != FSG_OK) return st;
     if ((st = ws(ctx, "keep_mask_pivot", (size_t)(m0.n_tiles * n_blocks_p), &maskp)) != FSG_OK) return st;
     pa.scanned = m0.kept ? m0.kept + 1 : nullptr;
@@ -489,7 +497,7 @@ static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const Mask
     m.mask = maskp;
     m.n_blocks = n_blocks_p;
     m.list = pa.items;
-    m.n_list = pa.total;
+    m.xseg = pa.xseg;
     {
         StageTimer t(ctx, "kde_mask");
         FSG_HIP(ctx, launch_keep_mask(m, ctx->num_cus, ctx->stream));

@@ -117,10 +117,10 @@ struct MaskArgs {
     int32_t n_jobs;
     int64_t n_items_total;
     // pruned scan: work items {first tile, first block, end block} of the
-    // data in pivot order (Xb, xa, mask then refer to that order), their
-    // number on the device
+    // data in pivot order (Xb, xa, mask then refer to that order); XCD x takes
+    // items [xseg[x], xseg[x+1])
     const int32_t* list;
-    const int64_t* n_list;
+    const int64_t* xseg;
 };
 
 // Tile pruning ahead of the keep-mask scan (kde_prune.hip).
@@ -146,13 +146,21 @@ struct PruneArgs {
     uint32_t* surv;            // [n_tiles][words]: cells a tile may keep columns of
     int32_t TP;                // tiles per keep-mask work item
     int64_t n_groups;          // groups of TP tiles
-    int32_t max_blocks;        // blocks per work item at most
-    int64_t* counts;           // [n_groups + 1] items per group
-    int64_t* offsets;          // [n_groups + 1] exclusive scan of counts
-    int64_t* total;            // device scalar: the number of items
+    int64_t n_blocks_p;        // 16-column blocks of the data in pivot order
+    int32_t chunk_blocks;      // blocks per chunk (an item stays within one)
+    int64_t n_chunks;
+    int64_t* counts;           // [n_chunks n_groups + 1] items per (chunk, group)
+    int64_t* offsets;          // exclusive scan of counts
+    int64_t* bcounts;          // [n_chunks n_groups + 1] blocks per (chunk, group)
+    int64_t* boffsets;         // exclusive scan of bcounts
+    int64_t* total;            // device: [0] the number of items, [1] of blocks
     int32_t* items;            // [3 x items]
+    int64_t* xseg;             // [kXcds + 1] item segments of the XCDs
     int64_t* scanned;          // optional: adds the scanned (column, tile) pairs
 };
+// XCDs of the MI355X: workgroup b runs on XCD b % kXcds (round-robin
+// dispatch); the pruned scan gives each XCD its own segment of the items
+constexpr int kXcds = 8;
 
 constexpr int kThetaPad = 128;  // padding of MaskArgs::ntheta: a whole number of tile groups
 // 64-entry query tiles per keep-mask work item: two tiles use each loaded
@@ -385,7 +393,7 @@ hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const doub
                                 hipStream_t st);
 hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st);
 hipError_t launch_prune_items(const PruneArgs& a, int64_t* partials, hipStream_t st);
-int64_t prune_max_items_per_group(int32_t P, int64_t n_blocks_p, int32_t max_blocks);
+int64_t prune_max_items(int64_t n_groups, int32_t P, int64_t n_chunks);
 hipError_t launch_mask_to_index(const PruneArgs& a, const uint16_t* maskp, int64_t n_blocks_p, uint16_t* mask,
                                 int64_t n_blocks, hipStream_t st);
 int max_norm_parts(int64_t n);  // partial maxima launch_max_norm needs in `part`

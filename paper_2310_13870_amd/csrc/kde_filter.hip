@@ -56,7 +56,8 @@ struct Gathered {
 template <int D4, int RQ, bool MULTI, int KIND = kKindGaussian>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
     KdeArgs a, unsigned long long* __restrict__ next_item) {
-    // queue length: fewer than 16 entries left over plus one batch of 256 columns
+    // queue length: fewer than 16 entries left over plus the columns of the
+    // blocks one fill step takes (at least 17 blocks of 16 fit)
     constexpr int QN = 288;
     __shared__ int32_t queue_all[4][QN];
     __shared__ float qf_all[4][RQ * D4 * 64];
@@ -128,18 +129,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         // queue state (uniform): entries [head, tail) are pending
         int32_t head = 0, tail = 0;
         int64_t blk = blk0;  // next block whose mask is to be read
-        // masks of the next batch of 16 blocks: lane l holds block blk + l/4,
-        // loaded one batch ahead
+        // masks of a batch of 64 blocks (1024 columns): lane l holds block
+        // blk + l; the next batch is loaded while this one is taken
         auto load_masks = [&](int64_t b) -> uint32_t {
-            const int64_t mb = b + (lane >> 2);
+            const int64_t mb = b + lane;
             return (mb < blk1) ? (uint32_t)mrow[mb] : 0u;
         };
         uint32_t masks = load_masks(blk);
+        uint32_t masks_next = load_masks(blk + 64);
 
-        // append the kept columns of further batches of 16 blocks (in index
-        // order) until 16 are pending or the range ends.  Lane l takes columns
-        // 4(l%4) .. 4(l%4)+3 of block l/4; its entries go after those of the
-        // lanes below it, counted with one ballot per column position.
+        // append the kept columns of further blocks (in index order) until 16
+        // are pending or the range ends.  Lane l's columns go after those of
+        // the lanes below it: the exclusive prefix of the per-lane counts is
+        // formed bit by bit of the count (a ballot and a masked bit count per
+        // bit).  The blocks taken are the longest prefix of the batch whose
+        // columns fit the queue -- all 64 unless the masks are dense (at
+        // least 17 always fit: fewer than 16 entries are pending).
         auto fill = [&]() {
             while (tail - head < 16 && blk < blk1) {
                 if (head > 0) {  // move the fewer than 16 pending entries to the front
@@ -150,25 +155,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
                     head = 0;
                     tail = left;
                 }
-                const int32_t c0 = (int32_t)((blk + (lane >> 2)) << 4) + 4 * (lane & 3);
-                uint32_t bits = (masks >> (4 * (lane & 3))) & 15u;
-                const int32_t lo = min(max(col_begin - c0, 0), 4), hi = min(max(col_end - c0, 0), 4);
-                bits &= ((1u << hi) - 1u) & ~((1u << lo) - 1u);
-                blk += 16;
-                masks = load_masks(blk);
-                int32_t pos = tail, total = 0;
+                const int32_t c0 = (int32_t)((blk + lane) << 4);
+                const int32_t lo = min(max(col_begin - c0, 0), 16), hi = min(max(col_end - c0, 0), 16);
+                uint32_t bits = masks & ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                const int32_t cnt = __popc(bits);
+                int32_t excl = 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint64_t bk = __ballot((bits >> k) & 1u);
-                    pos += (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
-                    total += __popcll(bk);
+                for (int b = 0; b < 5; ++b) {
+                    const uint64_t bk = __ballot((cnt >> b) & 1);
+                    excl += (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u))
+                            << b;
                 }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if ((bits >> k) & 1u) queue[pos] = c0 + k;
-                    pos += (bits >> k) & 1u;
+                const int32_t incl = excl + cnt;
+                const int32_t nb = (int32_t)__popcll(__ballot(incl <= QN - tail));  // >= 17
+                if (lane < nb) {
+                    int32_t pos = tail + excl;
+                    while (bits) {
+                        queue[pos++] = c0 + (int32_t)__builtin_ctz(bits);
+                        bits &= bits - 1u;
+                    }
                 }
-                tail += uniform(total);
+                tail += uniform(__builtin_amdgcn_readlane(incl, nb - 1));
+                blk += nb;
+                if (nb == 64) {
+                    masks = masks_next;
+                    masks_next = load_masks(blk + 64);
+                } else {  // dense masks: reload from the first block not taken
+                    masks = load_masks(blk);
+                    masks_next = load_masks(blk + 64);
+                }
             }
             __builtin_amdgcn_wave_barrier();
         };

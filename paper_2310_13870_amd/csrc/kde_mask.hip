@@ -48,7 +48,9 @@ constexpr int kBufferFlags = 0x00020000;
 // Work items: MODE 0 = (tile group, chunk of blocks) of one point set; 1 =
 // the same over the point sets of a multi-set launch; 2 = a list of
 // {first tile, first block, end block} (the pruned scan over the data in
-// pivot order, whose number is read from the device).
+// pivot order), cut into one segment per XCD: the waves of the workgroups
+// an XCD runs (blockIdx % kXcds) take its segment, so that each L2 holds the
+// data chunks of its own segment only.
 template <int KB, int TP, int WAVES, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void kde_keep_mask_kernel(MaskArgs m0) {
     constexpr bool MULTI = MODE == 1;
@@ -60,13 +62,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     // ops per K step.
     constexpr int QB = 4 * TP;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
-    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    int64_t wave = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));  // wave-uniform
+    int64_t n_waves = (int64_t)gridDim.x * 4;
+    int64_t it0 = 0, n_items;
+    if constexpr (MODE == 2) {  // the grid is a multiple of kXcds workgroups
+        const int32_t x = (int32_t)(blockIdx.x % kXcds);
+        wave = (int64_t)(blockIdx.x / kXcds) * 4 + uniform((int32_t)(threadIdx.x >> 6));
+        n_waves = (int64_t)(gridDim.x / kXcds) * 4;
+        it0 = m0.xseg[x];
+        n_items = m0.xseg[x + 1];
+    } else {
+        n_items = MULTI ? m0.n_items_total : mask_items(m0);
+    }
     const int grp = lane >> 4;
     const int r = lane & 15;
-    const int64_t n_items = MULTI ? m0.n_items_total : (MODE == 2 ? *m0.n_list : mask_items(m0));
     int64_t kept = 0;
-    for (int64_t it = wave; it < n_items; it += n_waves) {
+    for (int64_t it = it0 + wave; it < n_items; it += n_waves) {
         int64_t local = it;
         int32_t job = 0;
         if (MULTI) {  // the point set owning item it (uniform binary search)
@@ -306,8 +317,10 @@ static hipError_t launch_mask_t(const MaskArgs& m, int num_cus, hipStream_t st) 
     if (n_items < waves) waves = n_items;
     if (waves < 1) waves = 1;
     if (m.list) {
-        waves = (int64_t)num_cus * 4 * WAVES;  // the item count is on the device
-        kde_keep_mask_kernel<KB, TP, WAVES, 2><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
+        // the item count is on the device: every wave slot of the chip, in a
+        // whole number of workgroups per XCD
+        const int64_t per_xcd = ((int64_t)num_cus * WAVES + kXcds - 1) / kXcds;
+        kde_keep_mask_kernel<KB, TP, WAVES, 2><<<(unsigned)(per_xcd * kXcds), 256, 0, st>>>(m);
     } else if (m.jobs) {
         kde_keep_mask_kernel<KB, TP, WAVES, 1><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(m);
     } else {

@@ -240,66 +240,118 @@ __global__ __launch_bounds__(256) void prune_plan_kernel(PruneArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// (2) Work items of the pruned scan: per group of TP tiles, the cells any of
-// its tiles may keep, in pivot order, as runs of 16-column blocks (cells
-// sharing or touching a block merge into one run), cut into items of at most
-// max_blocks blocks: {first tile, first block, end block}.  One thread per
-// group, run twice: to count the items, and to write them at the group's
-// offset.  The count pass also adds the scanned (column, tile) pairs to the
+// (2) Work items of the pruned scan, chunk-major: the data blocks (pivot
+// order) are cut into chunks of chunk_blocks blocks, and for every (chunk,
+// group of TP tiles) the cells the group may keep columns of are merged into
+// runs of blocks within the chunk (cells sharing or touching a block merge):
+// items {first tile, first block, end block}.  Items of one chunk are
+// consecutive, so waves that run together scan the same data -- the groups
+// of one cluster share its cells -- and the XCD split below keeps each L2 on
+// a few chunks at a time.  Counting and filling take one thread per (chunk,
+// group); the count pass also adds the scanned (column, tile) pairs to the
 // filter statistics.
 // ---------------------------------------------------------------------------
-__device__ int64_t group_items(const PruneArgs& a, int64_t g, int32_t* out) {
+__device__ __forceinline__ void group_cells(const PruneArgs& a, int64_t g, uint32_t (&w)[8], int64_t* tl) {
     const int64_t t0 = g * a.TP;
-    const int64_t tl = min((int64_t)a.TP, a.n_tiles - t0);
-    uint32_t w[8];
+    *tl = min((int64_t)a.TP, a.n_tiles - t0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         uint32_t v = 0;
         if (k < a.words)
-            for (int64_t t = t0; t < t0 + tl; ++t) v |= a.surv[t * a.words + k];
+            for (int64_t t = t0; t < t0 + *tl; ++t) v |= a.surv[t * a.words + k];
         w[k] = v;
     }
-    int64_t items = 0, blocks = 0;
+}
+
+// runs of blocks of group g's cells within block range [lo, hi), in order:
+// fn(b0, b1) for each
+template <typename F>
+__device__ __forceinline__ void group_runs(const PruneArgs& a, const uint32_t (&w)[8], int64_t lo, int64_t hi, F fn) {
+    // the first cell that ends after column 16 lo (cells are in pivot order)
+    int32_t c = 0, cb = a.P;
+    while (c < cb) {
+        const int32_t m = (c + cb) >> 1;
+        if ((int64_t)a.cell_start[m + 1] <= 16 * lo) c = m + 1; else cb = m;
+    }
     int64_t rb0 = -1, rb1 = -1;
-    auto emit = [&](int64_t b0, int64_t b1) {
-        for (int64_t s = b0; s < b1; s += a.max_blocks) {
-            if (out) {
-                out[3 * items] = (int32_t)t0;
-                out[3 * items + 1] = (int32_t)s;
-                out[3 * items + 2] = (int32_t)min(b1, s + a.max_blocks);
-            }
-            ++items;
-        }
-        blocks += b1 - b0;
-    };
-    for (int32_t c = 0; c < a.P; ++c) {
+    for (; c < a.P && (int64_t)a.cell_start[c] < 16 * hi; ++c) {
         if (!((w[c >> 5] >> (c & 31)) & 1u)) continue;
         const int32_t cs = a.cell_start[c], ce = a.cell_start[c + 1];
         if (ce <= cs) continue;
-        const int64_t b0 = cs >> 4, b1 = ((int64_t)ce + 15) >> 4;
+        const int64_t b0 = max((int64_t)(cs >> 4), lo), b1 = min(((int64_t)ce + 15) >> 4, hi);
+        if (b1 <= b0) continue;
         if (rb0 >= 0 && b0 <= rb1) {
             rb1 = max(rb1, b1);
         } else {
-            if (rb0 >= 0) emit(rb0, rb1);
+            if (rb0 >= 0) fn(rb0, rb1);
             rb0 = b0;
             rb1 = b1;
         }
     }
-    if (rb0 >= 0) emit(rb0, rb1);
-    if (!out && a.scanned) atomicAdd((unsigned long long*)a.scanned, (unsigned long long)(blocks * 16 * tl));
-    return items;
+    if (rb0 >= 0) fn(rb0, rb1);
 }
 
 __global__ void prune_count_kernel(PruneArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g > a.n_groups) return;
-    a.counts[g] = (g < a.n_groups) ? group_items(a, g, nullptr) : 0;
+    const int64_t kg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = a.n_chunks * a.n_groups;
+    int64_t items = 0, blocks = 0, tl = 0;
+    if (kg < total) {
+        const int64_t k = kg / a.n_groups, g = kg - k * a.n_groups;
+        uint32_t w[8];
+        group_cells(a, g, w, &tl);
+        const int64_t lo = k * a.chunk_blocks, hi = min(lo + a.chunk_blocks, a.n_blocks_p);
+        group_runs(a, w, lo, hi, [&](int64_t b0, int64_t b1) {
+            ++items;
+            blocks += b1 - b0;
+        });
+    }
+    if (kg <= total) {
+        a.counts[kg] = items;
+        a.bcounts[kg] = blocks;
+    }
+    // scanned (column, tile) pairs: one atomic per wave
+    unsigned long long sc = (unsigned long long)(blocks * 16 * tl);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sc += (unsigned long long)__shfl_xor((long long)sc, off);
+    if ((threadIdx.x & 63) == 0 && sc > 0 && a.scanned) atomicAdd((unsigned long long*)a.scanned, sc);
 }
 
 __global__ void prune_fill_kernel(PruneArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n_groups) return;
-    group_items(a, g, a.items + 3 * a.offsets[g]);
+    const int64_t kg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kg >= a.n_chunks * a.n_groups) return;
+    const int64_t k = kg / a.n_groups, g = kg - k * a.n_groups;
+    uint32_t w[8];
+    int64_t tl;
+    group_cells(a, g, w, &tl);
+    int32_t* out = a.items + 3 * a.offsets[kg];
+    const int64_t lo = k * a.chunk_blocks, hi = min(lo + a.chunk_blocks, a.n_blocks_p);
+    group_runs(a, w, lo, hi, [&](int64_t b0, int64_t b1) {
+        out[0] = (int32_t)(g * a.TP);
+        out[1] = (int32_t)b0;
+        out[2] = (int32_t)b1;
+        out += 3;
+    });
+}
+
+// XCD segments of the item list: segment x holds the items of the (chunk,
+// group) pairs whose blocks start in [x B / X, (x + 1) B / X), B the total
+// blocks, X = kXcds -- equal scan work per L2, consecutive chunks in each
+__global__ void prune_xcd_kernel(PruneArgs a) {
+    const int x = threadIdx.x;
+    if (x > kXcds) return;
+    const int64_t total = a.n_chunks * a.n_groups;
+    const int64_t B = a.boffsets[total];
+    if (x == 0 || x == kXcds) {
+        a.xseg[x] = (x == 0) ? 0 : a.offsets[total];
+        return;
+    }
+    const int64_t target = (B * x) / kXcds;
+    int64_t lo = 0, hi = total;  // the first pair whose block offset reaches target
+    while (lo < hi) {
+        const int64_t m = (lo + hi) >> 1;
+        if (a.boffsets[m] < target) lo = m + 1; else hi = m;
+    }
+    a.xseg[x] = a.offsets[lo];
 }
 
 hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st) {
@@ -317,23 +369,27 @@ hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// counts[n_groups + 1] -> offsets[n_groups + 1] (offsets[n_groups] = the item
-// total, also in *total), then the items
+// counts, bcounts [n_chunks n_groups + 1] -> offsets, boffsets (exclusive
+// scans; the last entry is the total), the items, then the XCD segments
 hipError_t launch_prune_items(const PruneArgs& a, int64_t* partials, hipStream_t st) {
-    const int64_t ng = a.n_groups;
-    prune_count_kernel<<<(unsigned)((ng + 1 + 255) / 256), 256, 0, st>>>(a);
+    const int64_t total = a.n_chunks * a.n_groups;
+    prune_count_kernel<<<(unsigned)((total + 1 + 255) / 256), 256, 0, st>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_exclusive_scan_i64(a.counts, a.offsets, ng + 1, a.total, partials, st);
+    e = launch_exclusive_scan_i64(a.counts, a.offsets, total + 1, a.total, partials, st);
     if (e != hipSuccess) return e;
-    prune_fill_kernel<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>(a);
+    e = launch_exclusive_scan_i64(a.bcounts, a.boffsets, total + 1, a.total + 1, partials, st);
+    if (e != hipSuccess) return e;
+    prune_fill_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prune_xcd_kernel<<<1, 64, 0, st>>>(a);
     return hipGetLastError();
 }
 
-// an upper bound on the items of one group (the allocation of a.items)
-int64_t prune_max_items_per_group(int32_t P, int64_t n_blocks_p, int32_t max_blocks) {
-    return (int64_t)P + n_blocks_p / max_blocks + 2;
-}
+// an upper bound on the items of a pruned scan: each (chunk, group) pair
+// splits its runs at most at the chunk's cell starts, so a group has at most
+// one item per surviving cell plus one per chunk
+int64_t prune_max_items(int64_t n_groups, int32_t P, int64_t n_chunks) { return n_groups * ((int64_t)P + n_chunks + 1); }
 
 // ---------------------------------------------------------------------------
 // (4) Keep bits back to index order.  One workgroup per tile: the bits of the
@@ -351,20 +407,26 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
     __shared__ uint32_t bits[kConvWindow / 32];
     const int64_t t = blockIdx.x;
     const int64_t g = t / a.TP;
-    const int64_t i0 = a.offsets[g], i1 = a.offsets[g + 1];
+    uint32_t w[8];
+    int64_t tl;
+    group_cells(a, g, w, &tl);
     const uint16_t* mrow = maskp + t * n_blocks_p;
     const int64_t n_cols = n_blocks * 16;
     for (int64_t w0 = 0; w0 < n_cols; w0 += kConvWindow) {
         for (int32_t k = threadIdx.x; k < (int32_t)(kConvWindow / 32); k += kConvThreads) bits[k] = 0u;
         __syncthreads();
-        for (int64_t it = i0; it < i1; ++it) {
-            const int32_t b0 = a.items[3 * it + 1], b1 = a.items[3 * it + 2];
-            for (int32_t b = b0 + (int32_t)threadIdx.x; b < b1; b += kConvThreads) {
+        // the group's scanned blocks are those of its cells: a wave per cell,
+        // its lanes over the cell's blocks (a block shared with a neighbour
+        // cell may be read twice; the bits it sets are the same)
+        for (int32_t c = (int32_t)(threadIdx.x >> 6); c < a.P; c += kConvThreads / 64) {
+            if (!((w[c >> 5] >> (c & 31)) & 1u)) continue;
+            const int64_t b1 = ((int64_t)a.cell_start[c + 1] + 15) >> 4;
+            for (int64_t b = (a.cell_start[c] >> 4) + (threadIdx.x & 63); b < b1; b += 64) {
                 uint32_t m = mrow[b];
                 while (m) {
-                    const int32_t c = __builtin_ctz(m);
+                    const int32_t k = __builtin_ctz(m);
                     m &= m - 1u;
-                    const int64_t j = (int64_t)a.order[16 * (int64_t)b + c] - w0;
+                    const int64_t j = (int64_t)a.order[16 * b + k] - w0;
                     if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
                 }
             }

@@ -25,13 +25,28 @@ __global__ void prep_fragments_kernel(const float* __restrict__ X, int64_t n, in
     Xp[idx] = (row < n && col < d) ? (double)X[row * d + col] : 0.0;
 }
 
-__global__ void prep_norms_kernel(const float* __restrict__ X, int64_t n, int32_t d, int64_t n_pad,
-                                  double* __restrict__ norm) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= n_pad) return;
+// Squared norms in FP64, each summed in coordinate order.  A block stages
+// the rows it owns through LDS with coalesced loads (a thread per row reading
+// its row directly would touch a different cache line per lane and load).
+constexpr int kNormStage = 16384;  // floats staged per block (64 KB)
+
+__global__ __launch_bounds__(256) void prep_norms_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                         int64_t n_pad, int32_t rows, double* __restrict__ norm) {
+    __shared__ float xs[kNormStage + 256];  // rows padded to d + 1 floats (no bank conflicts)
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int64_t r1 = min(r0 + rows, n);
+    const int64_t cnt = (r1 > r0) ? (r1 - r0) * d : 0;
+    const float* src = X + r0 * d;
+    for (int64_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+        const int64_t r = k / d, t = k - r * d;
+        xs[r * (d + 1) + t] = src[k];
+    }
+    __syncthreads();
+    const int64_t row = r0 + threadIdx.x;
+    if ((int32_t)threadIdx.x >= rows || row >= n_pad) return;
     double s = 0.0;
     if (row < n) {
-        const float* x = X + row * d;
+        const float* x = xs + threadIdx.x * (d + 1);
         for (int32_t t = 0; t < d; ++t) {
             const double v = (double)x[t];
             s = __builtin_fma(v, v, s);
@@ -46,7 +61,11 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t
     prep_fragments_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(X, n, d, D4, total, Xp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    prep_norms_kernel<<<(unsigned)((n_pad + 255) / 256), 256, 0, st>>>(X, n, d, n_pad, norm);
+    // rows per block: 256, fewer where 256 rows of d + 1 floats would not fit the stage
+    int32_t rows = kNormStage / (d + 1);
+    if (rows > 256) rows = 256;
+    if (rows < 1) return hipErrorInvalidValue;
+    prep_norms_kernel<<<(unsigned)((n_pad + rows - 1) / rows), 256, 0, st>>>(X, n, d, n_pad, rows, norm);
     return hipGetLastError();
 }
 
