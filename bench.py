@@ -510,7 +510,7 @@ def run_leg(ctx, w, Xd, prec, steps, warmup, args):
     ctx.set_profiling(False)
     kept, scanned = ctx.filter_stats()
     stages = {}
-    for name in ("prep", "prune", "kde_mask", "mask_convert", "kde_root", "kde_pass", "descend", "group", "leaf", "csr"):
+    for name in ("prep", "prune", "kde_mask", "mask_convert", "kde_root", "pass_mask", "kde_pass", "descend", "group", "leaf", "csr"):
         ms, cnt = ctx.stage_time(name)
         if cnt:
             stages[name] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / steps,

@@ -106,9 +106,11 @@ uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
  * launches of one stage since the last reset.  Stages: "prep", "prune" (the
  * precision mode's tile pruning plan), "kde_mask" (its BF16 keep-mask scan),
  * "mask_convert" (keep bits back to index order), "kde_root"
- * (the binned KDE over all points), "kde_pass" (binned KDE of later passes),
- * "descend" (descent over bins), "group" (sample sort by node), "leaf"
- * (leaf stage), "csr" (reweighting and CSR).  Unknown names report 0. */
+ * (the binned KDE over all points), "pass_mask" (the keep masks of a later
+ * pass in the exact precision mode, narrowed from the root pass's), "kde_pass"
+ * (binned KDE of later passes), "descend" (descent over bins), "group"
+ * (sample sort by node), "leaf" (leaf stage), "csr" (reweighting and CSR).
+ * Unknown names report 0. */
 fsg_status fsg_ctx_set_profiling(fsg_ctx* ctx, int enabled);
 fsg_status fsg_ctx_stage_time(fsg_ctx* ctx, const char* stage, double* ms, int64_t* launches);
 fsg_status fsg_ctx_reset_profiling(fsg_ctx* ctx);

@@ -508,7 +508,11 @@ static fsg_status pruned_keep_mask(fsg_ctx* ctx, const fsg_points* X, const Mask
 }
 
 // Binned KDE of all n points against the nodes of tree level D (one segment).
-static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M) {
+// In the precision mode the root pass's keep masks (index order, a row per
+// 64-entry tile of the pivot order) are returned through root_mask and
+// root_blocks when asked for: the later passes of the same build use them.
+static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, double* M,
+                            const uint16_t** root_mask = nullptr, int64_t* root_blocks = nullptr) {
     fsg_status st;
     if (X->prec == FSG_BF16_SPLIT && ctx->kernel == FSG_LAPLACIAN)
         return set_error(ctx, FSG_E_UNSUPPORTED, "the Laplacian kernel runs in the plain path only");
@@ -571,6 +575,8 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         a.mask = m.mask;
         a.n_blocks = m.n_blocks;
         FSG_HIP(ctx, launch_exact_kept(a, n_items, (unsigned long long*)next_item, ctx->num_cus, ctx->stream));
+        if (root_mask) *root_mask = m.mask;
+        if (root_blocks) *root_blocks = m.n_blocks;
         return FSG_OK;
     }
     {
@@ -595,8 +601,12 @@ static SortBufs sort_bufs(fsg_ctx* ctx, int64_t n, size_t key_bytes, fsg_status*
 // Orders the samples by their node at `level` (2^level nodes); inactive
 // samples last.  Returns sorted sample ids and node starts, in the given
 // buffers ([ns], [2^level + 1]) or else in the workspace.
+// With sub (the pivot positions of the points, n of them, L samples per
+// point) the samples of each node are further ordered by where their points
+// lie in the pivot order, to the precision the 24-bit key leaves.
 static fsg_status group_by_node(fsg_ctx* ctx, const int32_t* node, int64_t ns, int level, int32_t** sorted,
-                                int32_t** starts, int32_t* vals_out = nullptr, int32_t* starts_out = nullptr) {
+                                int32_t** starts, int32_t* vals_out = nullptr, int32_t* starts_out = nullptr,
+                                const int32_t* sub = nullptr, int64_t n = 0, int32_t L = 1) {
     fsg_status st;
     uint32_t* keys;
     int32_t* vals = vals_out;
@@ -607,10 +617,17 @@ static fsg_status group_by_node(fsg_ctx* ctx, const int32_t* node, int64_t ns, i
     if (!start && (st = ws(ctx, "grp_starts", (size_t)n_nodes + 1, &start)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, ns, sizeof(uint32_t), &st);
     if (st != FSG_OK) return st;
+    const int node_bits = bit_length((uint64_t)n_nodes);
+    const int pos_bits = bit_length((uint64_t)std::max<int64_t>(n - 1, 1));
+    const int sub_bits = sub ? std::min(pos_bits, std::max(0, 24 - node_bits)) : 0;
     StageTimer t(ctx, "group");
-    FSG_HIP(ctx, launch_node_keys(node, ns, (uint32_t)n_nodes, keys, vals, ctx->stream));
-    FSG_HIP(ctx, radix_sort_u32(keys, vals, ns, bit_length((uint64_t)n_nodes), b, ctx->stream));
-    FSG_HIP(ctx, launch_node_starts(keys, ns, n_nodes, start, ctx->stream));
+    if (sub_bits > 0)
+        FSG_HIP(ctx, launch_node_keys_sub(node, ns, L, sub, pos_bits - sub_bits, sub_bits, (uint32_t)n_nodes, keys,
+                                          vals, ctx->stream));
+    else
+        FSG_HIP(ctx, launch_node_keys(node, ns, (uint32_t)n_nodes, keys, vals, ctx->stream));
+    FSG_HIP(ctx, radix_sort_u32(keys, vals, ns, node_bits + sub_bits, b, ctx->stream));
+    FSG_HIP(ctx, launch_node_starts(keys, ns, n_nodes, start, ctx->stream, sub_bits));
     *sorted = vals;
     *starts = start;
     return FSG_OK;
@@ -650,8 +667,9 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if (pts_alloc(p, (size_t)P, &p->cell_pivot) != hipSuccess) return fail("cell table");
     if (pts_alloc(p, (size_t)P, &p->pnorm) != hipSuccess) return fail("cell table");
     if (pts_alloc(p, (size_t)P, &p->prad) != hipSuccess) return fail("cell table");
+    if (pts_alloc(p, (size_t)n, &p->inv) != hipSuccess) return fail("pivot positions");
     p->bytes += split_bytes + 2 * q_split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) +
-                p->n_pad * sizeof(float) + q_rows * sizeof(float) + (4 * (size_t)P + 1) * 4;
+                p->n_pad * sizeof(float) + q_rows * sizeof(float) + (4 * (size_t)P + 1) * 4 + n * sizeof(int32_t);
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
@@ -669,6 +687,7 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     // neighbouring cells of the pivot order are close together
     FSG_HIP(ctx, launch_pivot_chain(p->X, n, p->d, P, d16, rank, p->cell_pivot, label, ctx->stream));
     FSG_HIP(ctx, radix_sort_u32(label, p->order, n, 8, b, ctx->stream));
+    FSG_HIP(ctx, launch_inverse_order(p->order, n, p->inv, ctx->stream));
     FSG_HIP(ctx, launch_prep_query_split(p->X, p->order, n, p->d, KB, q_rows, p->Qb, ctx->stream));
     FSG_HIP(ctx, launch_max_norm(p->norm, n, part, p->xmax, ctx->stream));
     // the pruned scan: cells of the pivot order, data operands in that order
@@ -700,6 +719,10 @@ struct Sampler {
     double* deg = nullptr;     // [n] degrees (NULL: not wanted)
     int32_t* nbr = nullptr;    // [ns] result
     float* margin = nullptr;   // [ns] optional decision margins
+    // precision mode, exact KDE: the root pass's keep masks, which the later
+    // passes narrow their columns to (NULL: later passes scan every column)
+    const uint16_t* root_mask = nullptr;
+    int64_t root_blocks = 0;
 };
 
 static fsg_status sampler_plan(fsg_ctx* ctx, Sampler& S) {
@@ -746,9 +769,20 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     const int32_t nbins = 1 << D;
     const int64_t ns = S.ns;
     fsg_status st;
-    int32_t *sorted, *starts;
-    if ((st = group_by_node(ctx, S.node, ns, start, &sorted, &starts)) != FSG_OK) return st;
     const int64_t n_nodes = (int64_t)1 << start;
+    // precision mode with the root pass's masks: every item reads only the
+    // columns its samples' points kept at the root (W blocks per item at
+    // most: a node holds at most ceil(n / 2^start) points)
+    const int32_t tile_m = exact_tile(X->D4);
+    const int64_t max_items_m = ns / tile_m + n_nodes + 1;
+    const int64_t node_max = (X->n + n_nodes - 1) / n_nodes;
+    const int32_t W = (int32_t)((node_max + 15) / 16 + 2);
+    const bool masked = S.root_mask != nullptr && X->inv != nullptr &&
+                        (uint64_t)max_items_m * W * sizeof(uint16_t) <= ctx->budget / 8;
+    int32_t *sorted, *starts;
+    if ((st = group_by_node(ctx, S.node, ns, start, &sorted, &starts, nullptr, nullptr, masked ? X->inv : nullptr,
+                            X->n, S.L)) != FSG_OK)
+        return st;
     const int32_t* bnd = level_bounds(X, start + D, &st);
     if (!bnd) return st;
     int64_t* q_ptr;
@@ -758,7 +792,7 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     int32_t* n_items;
     int64_t* scratch;
     double* M;
-    const int32_t tile = kde_tile(X->D4);
+    const int32_t tile = masked ? tile_m : kde_tile(X->D4);
     const int64_t max_items = ns / tile + n_nodes + 1;
     if ((st = ws(ctx, "pass_qptr", (size_t)n_nodes + 1, &q_ptr)) != FSG_OK) return st;
     if ((st = ws(ctx, "pass_qidx", (size_t)ns, &q_idx)) != FSG_OK) return st;
@@ -783,7 +817,22 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     a.n_items = n_items;
     a.out = M;
     a.out_stride = nbins;
-    {
+    if (masked) {
+        uint16_t* pmask;
+        int64_t* next_item;
+        if ((st = ws(ctx, "pass_mask", (size_t)(max_items * W), &pmask)) != FSG_OK) return st;
+        if ((st = ws(ctx, "exact_next_item", 1, &next_item)) != FSG_OK) return st;
+        {
+            StageTimer t(ctx, "pass_mask");
+            FSG_HIP(ctx, launch_pass_mask(a, max_items, X->inv, S.root_mask, S.root_blocks, W, pmask, ctx->stream));
+        }
+        FSG_HIP(ctx, launch_fill_i64(next_item, 1, 0, ctx->stream));
+        a.mask = pmask;
+        a.n_blocks = W;
+        a.mask_by_item = 1;
+        StageTimer t(ctx, "kde_pass");
+        FSG_HIP(ctx, launch_exact_kept(a, max_items, (unsigned long long*)next_item, ctx->num_cus, ctx->stream));
+    } else {
         StageTimer t(ctx, "kde_pass");
         FSG_HIP(ctx, launch_kde(a, max_items, ctx->num_cus, ctx->stream));
     }
@@ -1779,7 +1828,11 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
         const int D = S.plan.passes[0].second;
         double* M;
         if ((st = ws(ctx, "pass_masses", (size_t)S.X->n << D, &M)) != FSG_OK) return st;
-        if ((st = root_bins(ctx, S.X, gamma, D, M)) != FSG_OK) return st;
+        // the later passes reuse the root pass's keep masks in the exact
+        // precision mode (with an eps bound every level is computed in full)
+        const bool reuse = S.X->prec == FSG_BF16_SPLIT && ctx->kde_error == 0.0;
+        if ((st = root_bins(ctx, S.X, gamma, D, M, reuse ? &S.root_mask : nullptr, &S.root_blocks)) != FSG_OK)
+            return st;
         if ((st = stage_root_descend(ctx, S, M)) != FSG_OK) return st;
     }
     for (size_t p = 1; p < S.plan.passes.size(); ++p)

@@ -81,6 +81,9 @@ struct KdeArgs {
     const KdeArgs* jobs;     // multi-set launch: per point set arguments (NULL: this one)
     const uint16_t* mask;    // precision mode: keep masks of this point set [tiles][n_blocks]
     int64_t n_blocks;        // precision mode: 16-column blocks per mask row
+    // precision mode, later passes: one mask row per work item, holding the
+    // blocks from the item's first column on (row `item`, entry b - first block)
+    int32_t mask_by_item;
 };
 
 // Filtered KDE (precision mode): BF16 split operands decide which pairs are
@@ -275,6 +278,7 @@ struct fsg_points {
     float* xap = nullptr;
     int32_t* cell_start = nullptr;
     int32_t* cell_pivot = nullptr;
+    int32_t* inv = nullptr;    // point -> its position in the pivot order
     float* pnorm = nullptr;
     float* prad = nullptr;
     int32_t P = 0;
@@ -391,6 +395,14 @@ hipError_t launch_pivot_chain(const float* X, int64_t n, int32_t d, int32_t P, u
 hipError_t launch_cell_geometry(const float* X, int32_t d, int32_t P, const double* dmin, const int32_t* order,
                                 const int32_t* cell_start, const int32_t* cell_pivot, float* pnorm, float* prad,
                                 hipStream_t st);
+// inv[order[e]] = e
+hipError_t launch_inverse_order(const int32_t* order, int64_t n, int32_t* inv, hipStream_t st);
+// keep masks of a later pass's work items (a.items, a.n_items; entries a.q_idx):
+// row it, entry k = the union over the item's entries of the root pass's mask
+// bits of block first + k (first = the item's first column / 16) in the row
+// of the entry's root tile (inv[point] / kTileQ); W entries per row
+hipError_t launch_pass_mask(const KdeArgs& a, int64_t max_items, const int32_t* inv, const uint16_t* root_mask,
+                            int64_t root_blocks, int32_t W, uint16_t* pmask, hipStream_t st);
 hipError_t launch_prune_plan(const PruneArgs& a, hipStream_t st);
 hipError_t launch_prune_items(const PruneArgs& a, int64_t* partials, hipStream_t st);
 int64_t prune_max_items(int64_t n_groups, int32_t P, int64_t n_chunks);
@@ -490,8 +502,15 @@ int leaf_class(int32_t d);  // the class of d a leaf launch is built for (2, 4, 
 hipError_t launch_init_samples(int64_t n_samples, int32_t* node, float* margin, hipStream_t st);
 hipError_t launch_node_keys(const int32_t* node, int64_t n_samples, uint32_t inactive_key, uint32_t* keys,
                             int32_t* vals, hipStream_t st);
+// start[v] = first position whose key >> key_shift is >= v
 hipError_t launch_node_starts(const uint32_t* sorted_keys, int64_t n_samples, int64_t n_nodes, int32_t* start,
-                              hipStream_t st);
+                              hipStream_t st, int32_t key_shift = 0);
+// keys node << sub_bits | (inv[s / L] >> sub_shift) (inactive: inactive_node <<
+// sub_bits): the samples of a node ordered by where their points lie in the
+// pivot order
+hipError_t launch_node_keys_sub(const int32_t* node, int64_t n_samples, int32_t L, const int32_t* inv,
+                                int32_t sub_shift, int32_t sub_bits, uint32_t inactive_node, uint32_t* keys,
+                                int32_t* vals, hipStream_t st);
 hipError_t launch_entry_points(const int32_t* sorted_samples, int64_t n, int32_t L, int32_t* q_idx,
                                hipStream_t st);
 hipError_t launch_leaf_items(const int32_t* node_start, int64_t n_nodes, int64_t* scratch, int32_t* items,

@@ -471,22 +471,42 @@ hipError_t launch_node_keys(const int32_t* node, int64_t n_samples, uint32_t ina
     return hipGetLastError();
 }
 
-// start[v] = first position whose key is >= v (v in [0, n_nodes]).
-__global__ void node_starts_kernel(const uint32_t* keys, int64_t n, int64_t n_nodes, int32_t* start) {
+__global__ void node_keys_sub_kernel(const int32_t* node, int64_t n_samples, int32_t L, const int32_t* inv,
+                                     int32_t sub_shift, int32_t sub_bits, uint32_t inactive_node, uint32_t* keys,
+                                     int32_t* vals) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_samples) return;
+    const int32_t v = node[s];
+    const uint32_t sub = (uint32_t)inv[s / L] >> sub_shift;
+    keys[s] = v < 0 ? (inactive_node << sub_bits) : (((uint32_t)v << sub_bits) | sub);
+    vals[s] = (int32_t)s;
+}
+
+hipError_t launch_node_keys_sub(const int32_t* node, int64_t n_samples, int32_t L, const int32_t* inv,
+                                int32_t sub_shift, int32_t sub_bits, uint32_t inactive_node, uint32_t* keys,
+                                int32_t* vals, hipStream_t st) {
+    if (L < 1 || sub_bits < 0 || sub_bits > 31) return hipErrorInvalidValue;
+    node_keys_sub_kernel<<<(unsigned)((n_samples + 255) / 256 + 1), 256, 0, st>>>(node, n_samples, L, inv, sub_shift,
+                                                                                 sub_bits, inactive_node, keys, vals);
+    return hipGetLastError();
+}
+
+// start[v] = first position whose key >> shift is >= v (v in [0, n_nodes]).
+__global__ void node_starts_kernel(const uint32_t* keys, int64_t n, int64_t n_nodes, int32_t shift, int32_t* start) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v > n_nodes) return;
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if ((int64_t)keys[mid] < v) lo = mid + 1; else hi = mid;
+        if ((int64_t)(keys[mid] >> shift) < v) lo = mid + 1; else hi = mid;
     }
     start[v] = (int32_t)lo;
 }
 
 hipError_t launch_node_starts(const uint32_t* sorted_keys, int64_t n_samples, int64_t n_nodes, int32_t* start,
-                              hipStream_t st) {
+                              hipStream_t st, int32_t key_shift) {
     node_starts_kernel<<<(unsigned)((n_nodes + 1 + 255) / 256 + 1), 256, 0, st>>>(sorted_keys, n_samples, n_nodes,
-                                                                                 start);
+                                                                                 key_shift, start);
     return hipGetLastError();
 }
 

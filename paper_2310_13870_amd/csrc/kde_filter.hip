@@ -123,8 +123,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         __builtin_amdgcn_wave_barrier();
         load_bin_window(win, bnd, w.b0, w.b1, lane);
         bins.init(bnd, win, w.b0, w.b1, col_begin, w.e0, w.ne, J.out_stride, J.out, J.out_rows, lane);
-        const uint16_t* mrow = J.mask + (w.e0 / kTileQ) * J.n_blocks;
-        const int64_t blk0 = col_begin >> 4, blk1 = (col_end + 15) >> 4;
+        const int64_t blk0 = col_begin >> 4;
+        const int64_t blk1 = J.mask_by_item ? min((int64_t)(col_end + 15) >> 4, blk0 + J.n_blocks) : (col_end + 15) >> 4;
+        const uint16_t* mrow =
+            J.mask_by_item ? J.mask + it * J.n_blocks - blk0 : J.mask + (w.e0 / kTileQ) * J.n_blocks;
 
         // queue state (uniform): entries [head, tail) are pending
         int32_t head = 0, tail = 0;
@@ -254,6 +256,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         bins.finish();
         it = n_waves + (int64_t)(uint32_t)uniform((int32_t)(uint32_t)__shfl(claim, 0));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Keep masks of a later pass.  A sample's pairs that the root pass dropped --
+// pairs more than Delta below the largest term of the sample's point's row --
+// stay dropped at every deeper level: their total over the whole row is below
+// e^-25 of the degree (n e^-Delta), so a walk that reaches a node through
+// them, or whose branch they would change, has probability below that bound
+// at each level.  The root pass's masks are per 64-entry tile of the pivot
+// order: a sample reads the row of its point's tile, a superset of the
+// point's own kept columns.  One wave per work item, a lane per block; the
+// union over the item's entries skips repeated tiles (the entries are sorted
+// by pivot position within their node).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pass_mask_kernel(KdeArgs a, const int32_t* __restrict__ inv,
+                                                        const uint16_t* __restrict__ root_mask, int64_t root_blocks,
+                                                        int32_t W, uint16_t* __restrict__ pmask) {
+    const int64_t it = (int64_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (it >= *a.n_items) return;
+    const WorkItem w = a.items[it];
+    const SegDesc sg = a.segs[w.seg];
+    const int32_t* bnd = a.bounds + sg.bound_off;
+    const int32_t col_end = uniform(min(max(bnd[w.b1], 0), (int32_t)a.n_data));
+    const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
+    const int64_t wb = col_begin >> 4;
+    const int32_t nblk = (int32_t)(((col_end + 15) >> 4) - wb);
+    for (int32_t k0 = 0; k0 < W; k0 += 64) {
+        const int32_t k = k0 + lane;
+        uint32_t acc = 0;
+        int32_t prev = -1;
+        for (int32_t t = 0; t < w.ne; ++t) {
+            const int32_t rt = uniform(inv[a.q_idx[w.e0 + t]] / kTileQ);
+            if (rt == prev) continue;
+            prev = rt;
+            if (k < nblk && k < W) acc |= root_mask[(int64_t)rt * root_blocks + wb + k];
+        }
+        if (k < W) pmask[it * W + k] = (uint16_t)acc;
+    }
+}
+
+hipError_t launch_pass_mask(const KdeArgs& a, int64_t max_items, const int32_t* inv, const uint16_t* root_mask,
+                            int64_t root_blocks, int32_t W, uint16_t* pmask, hipStream_t st) {
+    if (max_items <= 0) return hipSuccess;
+    if (W < 1) return hipErrorInvalidValue;
+    pass_mask_kernel<<<(unsigned)((max_items + 3) / 4), 256, 0, st>>>(a, inv, root_mask, root_blocks, W, pmask);
+    return hipGetLastError();
 }
 
 template <int D4>

@@ -274,4 +274,15 @@ hipError_t launch_max_norm(const double* norm, int64_t n, double* part, double* 
     return hipGetLastError();
 }
 
+__global__ void inverse_order_kernel(const int32_t* __restrict__ order, int64_t n, int32_t* __restrict__ inv) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) inv[order[e]] = (int32_t)e;
+}
+
+hipError_t launch_inverse_order(const int32_t* order, int64_t n, int32_t* inv, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    inverse_order_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(order, n, inv);
+    return hipGetLastError();
+}
+
 }  // namespace fsg

@@ -324,6 +324,47 @@ def test_bf16_split_matches_plain_and_prunes(ctx):
     assert 0 < kept < scanned  # how much is pruned depends on how separated the clusters are
 
 
+@pytest.mark.parametrize("n,d,L,cap,comps", [(5000, 8, 6, 1, 4), (5000, 8, 6, 2, 4), (9001, 64, 5, 3, 12),
+                                             (6000, 100, 4, 2, 8), (4500, 128, 4, 3, 6), (3000, 16, 7, 5, 1)])
+def test_bf16_split_later_passes_use_root_masks(ctx, n, d, L, cap, comps):
+    """Later passes of the exact precision mode read only the columns the root
+    pass kept for their samples' points (the pairs dropped at the root total
+    below e^-25 of every degree, so a branch they could change is taken with
+    probability below that bound per level): neighbours match the oracle
+    outside the decision band and match the plain path, degrees to 1e-9."""
+    rng = np.random.default_rng(n + d + cap)
+    centres = rng.uniform(-10.0, 10.0, size=(comps, d))
+    X = (centres[rng.integers(0, comps, size=n)] + rng.normal(0.0, 1.0, size=(n, d))).astype(np.float32)
+    gamma = 1.0 / (2.0 * 0.25 * d)
+    seed = 77 + n
+    try:
+        ctx.set_levels_per_pass(cap)
+        pbf = fsg.Points(ctx, to_dev(X), "bf16_split")
+        p32 = fsg.Points(ctx, to_dev(X))
+        ctx.set_profiling(True)
+        ctx.reset_profiling()
+        nbr, deg, _ = fsg.sample_edges(ctx, pbf, gamma, L, seed)
+        ms, launches = ctx.stage_time("pass_mask")
+        ctx.set_profiling(False)
+        a = fsg.sample_edges(ctx, p32, gamma, L, seed)
+    finally:
+        ctx.set_levels_per_pass(0)
+    say(f"later passes bf16 n={n} d={d} cap={cap}: pass_mask launches {launches}")
+    assert launches >= 1
+    nbr, deg = nbr.cpu().numpy(), deg.cpu().numpy()
+    rnbr, rdeg, rmargin = oracle.sample_rows(X, gamma, L, seed)
+    rel = np.abs(deg - rdeg) / np.maximum(rdeg, 1e-300)
+    assert rel.max() < 1e-9, f"degree max rel err {rel.max()}"
+    mism, exempt, non_exempt = compare_neighbours(nbr, rnbr, rmargin)
+    say(f"  vs oracle: mismatches {mism} (band-exempt {exempt}, non-exempt {non_exempt})")
+    assert non_exempt == 0
+    m2, e2, ne2 = compare_neighbours(nbr, a[0].cpu().numpy(), rmargin)
+    say(f"  vs plain: mismatches {m2} (band-exempt {e2})")
+    assert ne2 == 0
+    pbf.close()
+    p32.close()
+
+
 @pytest.mark.parametrize("n,d,L,spread,comps", [(1, 3, 2, 10.0, 1), (100, 8, 5, 10.0, 3), (255, 2, 6, 20.0, 4),
                                                 (4097, 16, 8, 12.0, 10), (20_001, 64, 6, 10.0, 30),
                                                 (6000, 100, 6, 10.0, 12), (9000, 128, 5, 10.0, 16),
