@@ -873,6 +873,11 @@ static LeafArgs leaf_args(const Sampler& S, const int32_t* bnd, const int32_t* s
     la.margin = S.margin;
     la.uleaf = S.plan.passes.empty() ? nullptr : S.uleaf;
     la.n_uleaf = S.plan.passes.empty() ? 0 : S.n_uleaf;
+    if (S.root_mask != nullptr && X->inv != nullptr) {
+        la.root_mask = S.root_mask;
+        la.root_blocks = S.root_blocks;
+        la.inv = X->inv;
+    }
     return la;
 }
 
@@ -884,7 +889,12 @@ static fsg_status stage_leaf(fsg_ctx* ctx, const Sampler& S) {
     const int64_t ns = S.ns;
     fsg_status st;
     int32_t *sorted, *starts;
-    if ((st = group_by_node(ctx, S.node, ns, S.plan.leaf_level, &sorted, &starts)) != FSG_OK) return st;
+    // with the root pass's masks, a node's samples are ordered by pivot
+    // position, so that an item's samples share few root tiles
+    const bool masked = S.root_mask != nullptr && X->inv != nullptr;
+    if ((st = group_by_node(ctx, S.node, ns, S.plan.leaf_level, &sorted, &starts, nullptr, nullptr,
+                            masked ? X->inv : nullptr, X->n, S.L)) != FSG_OK)
+        return st;
     const int64_t n_nodes = (int64_t)1 << S.plan.leaf_level;
     const int32_t* bnd = level_bounds(X, S.plan.leaf_level, &st);
     if (!bnd) return st;

@@ -473,6 +473,12 @@ struct LeafArgs {
     float* margin;
     const double* uleaf;            // precomputed uniforms of the leaf levels (NULL: computed here)
     int32_t n_uleaf;
+    // precision mode, exact KDE: the root pass's keep masks (index order, a
+    // row of root_blocks 16-column blocks per 64-entry tile of the pivot
+    // order) and the points' pivot positions; NULL: every point is evaluated
+    const uint16_t* root_mask;
+    int64_t root_blocks;
+    const int32_t* inv;
     // several point sets in one launch (jobs != NULL): their samples were
     // grouped by one sort over global node ids (job k's nodes are
     // [job_node_off[k], job_node_off[k+1])); items and n_items are the

@@ -246,6 +246,157 @@ __device__ __forceinline__ double leaf_exponent(double sum, double hq, double xn
     return __builtin_fma(two_s, sum, hq - s256 * xn);
 }
 
+// Sparse leaf path (precision mode, exact KDE, with the root pass's keep
+// masks): a sample's pairs that the root pass dropped total below e^-25 of
+// its degree, so they change its walk with probability below that bound
+// (the same reading as the later passes).  The item evaluates only the node's
+// points kept at the root for some of its samples (the union of their tiles'
+// mask bits), at most kLeafSparse of them, with the cross terms in the same
+// order as the full path (features 0 .. d-1, one fused multiply-add each), so
+// a kept point's value is the full path's.  Returns false, having written
+// nothing, when the union holds more points (or none), or when some sample
+// would see a zero total (the walk reached the node through pairs its own
+// tile dropped): the caller then runs the full path for the item.
+constexpr int kLeafSparse = 16;
+
+template <int DMAX, int KIND>
+__device__ __forceinline__ bool leaf_sparse(const LeafArgs& a, int32_t lo, int32_t cnt, bool active, int32_t smp,
+                                            int32_t i, int32_t l, int32_t self, double qn, double hq, double s256,
+                                            double two_s, const double* exp_tab, float* xsp, double* xnsp,
+                                            int32_t* idxp) {
+    const int lane = threadIdx.x;
+    // (1) the keep bits of the node's points, bit j for point lo + j: this
+    // sample's tile row, the blocks of the node concatenated, then ORed over
+    // the item's samples
+    const int64_t b0 = lo >> 4;
+    const int32_t sh = lo & 15;
+    const int32_t nblk = (sh + cnt + 15) >> 4;  // at most 5 (cnt <= 64)
+    uint64_t w0 = 0, w1 = 0;
+    if (active) {
+        const uint16_t* row = a.root_mask + (int64_t)(a.inv[i] / kTileQ) * a.root_blocks + b0;
+        uint64_t m[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) m[b] = (b < nblk) ? row[b] : 0u;
+        w0 = m[0] | (m[1] << 16) | (m[2] << 32) | (m[3] << 48);
+        w1 = m[4];
+    }
+    uint64_t kb = (sh == 0) ? w0 : ((w0 >> sh) | (w1 << (64 - sh)));
+    if (cnt < 64) kb &= (1ull << cnt) - 1ull;
+    uint32_t klo = (uint32_t)kb, khi = (uint32_t)(kb >> 32);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        klo |= (uint32_t)__shfl_xor((int)klo, off);
+        khi |= (uint32_t)__shfl_xor((int)khi, off);
+    }
+    const uint64_t keep = ((uint64_t)(uint32_t)uniform((int32_t)khi) << 32) | (uint32_t)uniform((int32_t)klo);
+    const int32_t nk = __popcll(keep);
+    if (nk == 0 || nk > kLeafSparse) return false;
+    // (2) the kept points in index order, their rows feature-major in LDS
+    // (16 per feature, zeros past nk) and their squared norms
+    if ((keep >> lane) & 1ull) idxp[__popcll(keep & ((1ull << lane) - 1ull))] = lane;
+    __syncthreads();
+    int32_t jk[kLeafSparse];
+#pragma unroll
+    for (int k = 0; k < kLeafSparse; ++k) jk[k] = (k < nk) ? uniform(idxp[k]) : 0;
+    {
+        // every load issued before the first store (DMAX / 4 per lane)
+        // (lane l stages point l % 16 at features l / 16 + 4 r)
+        constexpr int kPer = (DMAX * kLeafSparse + 63) / 64;
+        const int32_t myk = lane & (kLeafSparse - 1);
+        const float* src = a.X + (int64_t)(lo + ((myk < nk) ? idxp[myk] : 0)) * a.d;
+        float v[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int32_t t = (lane >> 4) + 4 * r;
+            v[r] = (t < a.d && myk < nk) ? src[t] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) xsp[lane + 64 * r] = v[r];
+    }
+    if (lane < kLeafSparse) xnsp[lane] = (lane < nk) ? a.norm[lo + idxp[lane]] : 0.0;
+    // the sample's row in registers (vector loads where rows are 16-byte aligned)
+    const float* xi = a.X + (int64_t)i * a.d;
+    float q[DMAX];
+    if ((a.d & 3) == 0 && ((uintptr_t)a.X & 15) == 0) {
+#pragma unroll
+        for (int t = 0; t < DMAX; t += 4) {
+            float4 w = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (t < a.d) w = *(const float4*)(xi + t);
+            q[t] = w.x;
+            q[t + 1] = w.y;
+            q[t + 2] = w.z;
+            q[t + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? xi[t] : 0.0f;
+    }
+    __syncthreads();
+    // (3) cross terms, then values (0 for the sample's own point)
+    double kv[kLeafSparse];
+#pragma unroll
+    for (int k = 0; k < kLeafSparse; ++k) kv[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t) {
+        if (t >= a.d) continue;  // uniform; q stays in registers (static indices)
+        const double qt = (double)q[t];
+        const float4* row = (const float4*)(xsp + t * kLeafSparse);
+#pragma unroll
+        for (int k4 = 0; k4 < kLeafSparse / 4; ++k4) {
+            if (4 * k4 < nk) {
+                const float4 v = row[k4];
+                kv[4 * k4 + 0] = __builtin_fma(qt, (double)v.x, kv[4 * k4 + 0]);
+                kv[4 * k4 + 1] = __builtin_fma(qt, (double)v.y, kv[4 * k4 + 1]);
+                kv[4 * k4 + 2] = __builtin_fma(qt, (double)v.z, kv[4 * k4 + 2]);
+                kv[4 * k4 + 3] = __builtin_fma(qt, (double)v.w, kv[4 * k4 + 3]);
+            }
+        }
+    }
+    double total = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLeafSparse; ++k) {
+        if (k < nk) {
+            const double v = exp2_256_tab(leaf_exponent<KIND>(kv[k], hq, xnsp[k], s256, two_s, qn), exp_tab);
+            kv[k] = (jk[k] != self) ? v : 0.0;
+            total += kv[k];
+        } else {
+            kv[k] = 0.0;
+        }
+    }
+    if (__ballot(active && !(total > 0.0)) != 0) {
+        __syncthreads();  // the full path restages the LDS
+        return false;
+    }
+    // (4) the walk over the node's levels, as in the full path
+    if (active) {
+        SampleUniforms uni;
+        uni.init(a.seed, (uint64_t)i, (uint64_t)l);
+        const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
+        float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+        int32_t na = 0, nbd = cnt, level = a.level;
+        while (nbd - na > 1) {
+            const int32_t mid = tree_split(na, nbd);
+            double mL = 0.0, mR = 0.0;
+#pragma unroll
+            for (int k = 0; k < kLeafSparse; ++k) {
+                if (k < nk) {
+                    const bool in_node = (jk[k] >= na) && (jk[k] < nbd);
+                    const bool left = jk[k] < mid;
+                    mL += (in_node && left) ? kv[k] : 0.0;
+                    mR += (in_node && !left) ? kv[k] : 0.0;
+                }
+            }
+            const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
+            const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
+            if (go_left) nbd = mid; else na = mid;
+            ++level;
+        }
+        a.nbr[smp] = lo + na;
+        if (a.margin != nullptr) a.margin[smp] = mg;
+    }
+    return true;
+}
+
 // KIND: the Gaussian kernel (cross terms, the norm expansion), the exponential
 // one (the same, then the square root) or the Laplacian one (the L1 distance
 // from coordinate differences, summed in coordinate order).
@@ -259,9 +410,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
     // 2^(z/256) from the table.
     constexpr bool kWide = DMAX > 32;
     typedef typename std::conditional<kWide, float, double>::type stage_t;
-    __shared__ stage_t xs[kWide ? DMAX * kLeafMax : (kLeafMax + 3) * DMAX];
+    __shared__ __attribute__((aligned(16))) stage_t xs[kWide ? DMAX * kLeafMax : (kLeafMax + 3) * DMAX];
     __shared__ double xns[kLeafMax];  // |x|^2 of the node's points, 0 past the last
     __shared__ double exp_tab[256];
+    __shared__ int32_t idxp[kLeafSparse];  // the sparse path's kept points
     load_exp2_table(exp_tab);
     const int lane = threadIdx.x;
     const int64_t n_items = (int64_t)*a0.n_items;
@@ -296,6 +448,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
         const int32_t self = i - lo;  // the sample's own point, if it lies in the node
         const double qn = a.norm[i];
         const double hq = -s256 * qn;
+        if constexpr (!MULTI && KIND != kKindLaplacian) {
+            if (a.root_mask != nullptr && leaf_sparse<DMAX, KIND>(a, lo, cnt, active, smp, i, l, self, qn, hq, s256,
+                                                                  two_s, exp_tab, (float*)xs, xns, idxp)) {
+                __syncthreads();  // xs is reused by the next item
+                continue;
+            }
+        }
         xns[lane] = (lane < cnt) ? a.norm[lo + lane] : 0.0;
         double kv[kLeafMax];
         if constexpr (kWide) {
