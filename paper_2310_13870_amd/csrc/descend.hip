@@ -259,6 +259,74 @@ __device__ __forceinline__ double leaf_exponent(double sum, double hq, double xn
 // tile dropped): the caller then runs the full path for the item.
 constexpr int kLeafSparse = 16;
 
+// The cross terms, values and walk of the sparse path for NG groups of four
+// kept points (nk <= 4 NG; the padding columns are zero and their values are
+// set to 0): whole groups are updated at once, so the sums stay in place.
+template <int NG, int DMAX, int KIND>
+__device__ __forceinline__ bool leaf_sparse_tail(const LeafArgs& a, const float (&q)[DMAX], const float* xsp,
+                                                 const double* xnsp, const int32_t (&jk)[kLeafSparse], int32_t nk,
+                                                 int32_t lo, int32_t cnt, bool active, int32_t smp, int32_t i,
+                                                 int32_t l, int32_t self, double qn, double hq, double s256,
+                                                 double two_s, const double* exp_tab) {
+    constexpr int K = 4 * NG;
+    double kv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) kv[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t) {
+        if (t < a.d) {  // uniform
+            const double qt = (double)q[t];
+            const float4* row = (const float4*)(xsp + t * kLeafSparse);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const float4 v = row[g];
+                kv[4 * g + 0] = __builtin_fma(qt, (double)v.x, kv[4 * g + 0]);
+                kv[4 * g + 1] = __builtin_fma(qt, (double)v.y, kv[4 * g + 1]);
+                kv[4 * g + 2] = __builtin_fma(qt, (double)v.z, kv[4 * g + 2]);
+                kv[4 * g + 3] = __builtin_fma(qt, (double)v.w, kv[4 * g + 3]);
+            }
+        }
+    }
+    // values, 0 for the sample's own point and the padding
+    double total = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v = exp2_256_tab(leaf_exponent<KIND>(kv[k], hq, xnsp[k], s256, two_s, qn), exp_tab);
+        kv[k] = (k < nk && jk[k] != self) ? v : 0.0;
+        total += kv[k];
+    }
+    if (__ballot(active && !(total > 0.0)) != 0) {
+        __syncthreads();  // the full path restages the LDS
+        return false;
+    }
+    // the walk over the node's levels, as in the full path
+    if (active) {
+        SampleUniforms uni;
+        uni.init(a.seed, (uint64_t)i, (uint64_t)l);
+        const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
+        float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+        int32_t na = 0, nbd = cnt, level = a.level;
+        while (nbd - na > 1) {
+            const int32_t mid = tree_split(na, nbd);
+            double mL = 0.0, mR = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool in_node = (jk[k] >= na) && (jk[k] < nbd);
+                const bool left = jk[k] < mid;
+                mL += (in_node && left) ? kv[k] : 0.0;
+                mR += (in_node && !left) ? kv[k] : 0.0;
+            }
+            const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
+            const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
+            if (go_left) nbd = mid; else na = mid;
+            ++level;
+        }
+        a.nbr[smp] = lo + na;
+        if (a.margin != nullptr) a.margin[smp] = mg;
+    }
+    return true;
+}
+
 template <int DMAX, int KIND>
 __device__ __forceinline__ bool leaf_sparse(const LeafArgs& a, int32_t lo, int32_t cnt, bool active, int32_t smp,
                                             int32_t i, int32_t l, int32_t self, double qn, double hq, double s256,
@@ -332,69 +400,16 @@ __device__ __forceinline__ bool leaf_sparse(const LeafArgs& a, int32_t lo, int32
         for (int t = 0; t < DMAX; ++t) q[t] = (t < a.d) ? xi[t] : 0.0f;
     }
     __syncthreads();
-    // (3) cross terms, then values (0 for the sample's own point)
-    double kv[kLeafSparse];
-#pragma unroll
-    for (int k = 0; k < kLeafSparse; ++k) kv[k] = 0.0;
-#pragma unroll
-    for (int t = 0; t < DMAX; ++t) {
-        if (t >= a.d) continue;  // uniform; q stays in registers (static indices)
-        const double qt = (double)q[t];
-        const float4* row = (const float4*)(xsp + t * kLeafSparse);
-#pragma unroll
-        for (int k4 = 0; k4 < kLeafSparse / 4; ++k4) {
-            if (4 * k4 < nk) {
-                const float4 v = row[k4];
-                kv[4 * k4 + 0] = __builtin_fma(qt, (double)v.x, kv[4 * k4 + 0]);
-                kv[4 * k4 + 1] = __builtin_fma(qt, (double)v.y, kv[4 * k4 + 1]);
-                kv[4 * k4 + 2] = __builtin_fma(qt, (double)v.z, kv[4 * k4 + 2]);
-                kv[4 * k4 + 3] = __builtin_fma(qt, (double)v.w, kv[4 * k4 + 3]);
-            }
-        }
+    switch ((nk + 3) >> 2) {
+        case 1: return leaf_sparse_tail<1, DMAX, KIND>(a, q, xsp, xnsp, jk, nk, lo, cnt, active, smp, i, l, self, qn,
+                                                       hq, s256, two_s, exp_tab);
+        case 2: return leaf_sparse_tail<2, DMAX, KIND>(a, q, xsp, xnsp, jk, nk, lo, cnt, active, smp, i, l, self, qn,
+                                                       hq, s256, two_s, exp_tab);
+        case 3: return leaf_sparse_tail<3, DMAX, KIND>(a, q, xsp, xnsp, jk, nk, lo, cnt, active, smp, i, l, self, qn,
+                                                       hq, s256, two_s, exp_tab);
+        default: return leaf_sparse_tail<4, DMAX, KIND>(a, q, xsp, xnsp, jk, nk, lo, cnt, active, smp, i, l, self,
+                                                        qn, hq, s256, two_s, exp_tab);
     }
-    double total = 0.0;
-#pragma unroll
-    for (int k = 0; k < kLeafSparse; ++k) {
-        if (k < nk) {
-            const double v = exp2_256_tab(leaf_exponent<KIND>(kv[k], hq, xnsp[k], s256, two_s, qn), exp_tab);
-            kv[k] = (jk[k] != self) ? v : 0.0;
-            total += kv[k];
-        } else {
-            kv[k] = 0.0;
-        }
-    }
-    if (__ballot(active && !(total > 0.0)) != 0) {
-        __syncthreads();  // the full path restages the LDS
-        return false;
-    }
-    // (4) the walk over the node's levels, as in the full path
-    if (active) {
-        SampleUniforms uni;
-        uni.init(a.seed, (uint64_t)i, (uint64_t)l);
-        const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
-        float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
-        int32_t na = 0, nbd = cnt, level = a.level;
-        while (nbd - na > 1) {
-            const int32_t mid = tree_split(na, nbd);
-            double mL = 0.0, mR = 0.0;
-#pragma unroll
-            for (int k = 0; k < kLeafSparse; ++k) {
-                if (k < nk) {
-                    const bool in_node = (jk[k] >= na) && (jk[k] < nbd);
-                    const bool left = jk[k] < mid;
-                    mL += (in_node && left) ? kv[k] : 0.0;
-                    mR += (in_node && !left) ? kv[k] : 0.0;
-                }
-            }
-            const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
-            const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
-            if (go_left) nbd = mid; else na = mid;
-            ++level;
-        }
-        a.nbr[smp] = lo + na;
-        if (a.margin != nullptr) a.margin[smp] = mg;
-    }
-    return true;
 }
 
 // KIND: the Gaussian kernel (cross terms, the norm expansion), the exponential
