@@ -953,6 +953,7 @@ fsg_status csr_rows_async(fsg_ctx* ctx, const fsg_points* X, double gamma, int32
     a.col = col_dev;
     a.w = w_dev;
     a.cap = cap;
+    a.row_order = X->order;  // the pivot order in the precision mode
     StageTimer t(ctx, "csr");
     FSG_HIP(ctx, launch_csr_rows(a, nbr_dev, L, cnt, fillc, off, off_part, uniq, uniq_part, n_long_dev, ctx->stream));
     return FSG_OK;

@@ -579,6 +579,9 @@ struct CsrRowArgs {
     int32_t* col;
     float* w;
     int64_t cap;
+    // rows filled in this order (NULL: index order); the pivot order keeps a
+    // cluster's rows, whose neighbours are mostly in the same cluster, together
+    const int32_t* row_order;
 };
 bool job_finished(const fsg_job* j);
 void server_detach(fsg_server* s);  // release everything a server holds on its context

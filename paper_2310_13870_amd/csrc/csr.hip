@@ -197,10 +197,16 @@ __global__ __launch_bounds__(256) void csr_row_sort_kernel(const uint32_t* __res
 // Columns and weights of row i from its sorted unique entries; the kernel
 // value uses the difference form in FP64 summed in feature order, so both
 // directions of an edge get bit-identical weights.
+// With a row order, XCD x (workgroups b with b % kXcds == x; the grid is a
+// multiple of kXcds) takes the x-th eighth of the order, four rows per
+// workgroup, so that each L2 holds the rows of the clusters it works on.
 __global__ __launch_bounds__(256) void csr_row_fill_kernel(CsrRowArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-    if (row >= a.n) return;
+    const int64_t per_xcd = gridDim.x / kXcds;
+    const int64_t lb = a.row_order ? (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds : blockIdx.x;
+    const int64_t r = lb * 4 + (int64_t)__builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    if (r >= a.n) return;
+    const int64_t row = a.row_order ? a.row_order[r] : r;
     const int64_t rp = a.row_ptr[row];
     const int64_t cnt = a.row_ptr[row + 1] - rp;
     const int32_t* seg = a.ent + (int64_t)a.L * row + a.in_off[row];
@@ -237,7 +243,8 @@ hipError_t launch_csr_rows(const CsrRowArgs& a, const int32_t* nbr, int32_t L, u
     csr_row_sort_kernel<<<row_blocks, 256, 0, st>>>(off, L, a.ent, uniq, n, n_long);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_exclusive_scan_i64(uniq, a.row_ptr, n, a.row_ptr + n, uniq_partials, st)) != hipSuccess) return e;
-    csr_row_fill_kernel<<<row_blocks, 256, 0, st>>>(a);
+    const unsigned fill_blocks = a.row_order ? (row_blocks + kXcds - 1) / kXcds * kXcds : row_blocks;
+    csr_row_fill_kernel<<<fill_blocks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

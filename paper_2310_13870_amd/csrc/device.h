@@ -173,18 +173,31 @@ __device__ __forceinline__ double kernel_distance(int32_t kind, const float* xi,
         return D;
     }
     if (vec) {
+        // eight 16-byte pieces of each row are loaded before any is used (the
+        // sums still run in feature order)
         const float4* vi = (const float4*)xi;
         const float4* vj = (const float4*)xj;
-        for (int32_t t4 = 0; t4 < (d >> 2); ++t4) {
-            const float4 p = vi[t4], q = vj[t4];
-            double df = (double)p.x - (double)q.x;
-            D = __builtin_fma(df, df, D);
-            df = (double)p.y - (double)q.y;
-            D = __builtin_fma(df, df, D);
-            df = (double)p.z - (double)q.z;
-            D = __builtin_fma(df, df, D);
-            df = (double)p.w - (double)q.w;
-            D = __builtin_fma(df, df, D);
+        const int32_t n4 = d >> 2;
+        for (int32_t c = 0; c < n4; c += 8) {
+            float4 p[8], q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                p[u] = (c + u < n4) ? vi[c + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                q[u] = (c + u < n4) ? vj[c + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (c + u < n4) {
+                    double df = (double)p[u].x - (double)q[u].x;
+                    D = __builtin_fma(df, df, D);
+                    df = (double)p[u].y - (double)q[u].y;
+                    D = __builtin_fma(df, df, D);
+                    df = (double)p[u].z - (double)q[u].z;
+                    D = __builtin_fma(df, df, D);
+                    df = (double)p[u].w - (double)q[u].w;
+                    D = __builtin_fma(df, df, D);
+                }
+            }
         }
     } else {
         for (int32_t t = 0; t < d; ++t) {
