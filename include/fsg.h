@@ -107,7 +107,7 @@ uint64_t fsg_ctx_workspace_bytes(const fsg_ctx* ctx);
  * precision mode's tile pruning plan), "kde_mask" (its BF16 keep-mask scan),
  * "mask_convert" (keep bits back to index order), "kde_root"
  * (the binned KDE over all points), "pass_mask" (the keep masks of a later
- * pass in the exact precision mode, narrowed from the root pass's), "kde_pass"
+ * pass in the precision mode, narrowed from the root pass's), "kde_pass"
  * (binned KDE of later passes), "descend" (descent over bins), "group"
  * (sample sort by node), "leaf" (leaf stage), "csr" (reweighting and CSR).
  * Unknown names report 0. */
@@ -144,10 +144,13 @@ fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind);
  * with probability below ceil(log2 n) e^-25.  0 < eps < 1: the paper's
  * approximate-KDE regime (Theorem 1 asks for (1 +- eps)-accurate KDEs with
  * eps <= 1/(6 log2 n)): Delta = ln(n-1) + ln(1/eps), so every degree is
- * within [1 - eps, 1] of the exact one, the sampled neighbour's distribution
- * is within total variation eps of the exact k/deg (Lemma 1's telescoping
- * product holds for the kept kernel values), and fewer pairs are recomputed.
- * FSG_E_INVALID outside [0, 1). */
+ * within [1 - eps, 1] of the exact one and fewer pairs are recomputed.  In
+ * both cases every level of fsg_sample_edges evaluates only pairs the root
+ * pass kept (a superset of each point's own), so each level's branch
+ * probabilities differ from the exact ones by at most the dropped mass over
+ * the degree: the sampled neighbour's distribution is within total variation
+ * ceil(log2 n) e^-25 (eps = 0) or ceil(log2 n) eps (at most 1/6 for the
+ * paper's eps) of the exact k/deg.  FSG_E_INVALID outside [0, 1). */
 fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps);
 
 /* Tile pruning of the precision mode (default on): before the BF16 keep-mask

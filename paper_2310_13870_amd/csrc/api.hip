@@ -1839,9 +1839,10 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
         const int D = S.plan.passes[0].second;
         double* M;
         if ((st = ws(ctx, "pass_masses", (size_t)S.X->n << D, &M)) != FSG_OK) return st;
-        // the later passes reuse the root pass's keep masks in the exact
-        // precision mode (with an eps bound every level is computed in full)
-        const bool reuse = S.X->prec == FSG_BF16_SPLIT && ctx->kde_error == 0.0;
+        // the later passes and the leaf stage read only the columns the root
+        // pass kept (exact mode: the dropped pairs total below e^-25 of each
+        // degree; with an eps bound, below eps of it)
+        const bool reuse = S.X->prec == FSG_BF16_SPLIT;
         if ((st = root_bins(ctx, S.X, gamma, D, M, reuse ? &S.root_mask : nullptr, &S.root_blocks)) != FSG_OK)
             return st;
         if ((st = stage_root_descend(ctx, S, M)) != FSG_OK) return st;
