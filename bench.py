@@ -693,7 +693,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": d, "L": L, "sigma": w.sigma, "gamma": w.gamma,
                    "components": w.n_comp, "precision": precs[0],
-                   "precision_detail": PRECISION_NOTE[precs[0]], "tile_pruning": not args.no_pruning},
+                   "precision_detail": PRECISION_NOTE[precs[0]], "tile_pruning": (not args.no_pruning) and n >= (1 << 18)},
         "kernel_evals_per_s": head["kde"]["kernel_evals_per_s"],
         "pairs_scanned_per_s": head["kde"]["pairs_scanned_per_s"],
         "pairs_resolved_per_s": head["kde"]["pairs_resolved_per_s"],

@@ -153,7 +153,7 @@ fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind);
  * paper's eps) of the exact k/deg.  FSG_E_INVALID outside [0, 1). */
 fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps);
 
-/* Tile pruning of the precision mode (default on): before the BF16 keep-mask
+/* Tile pruning of the precision mode: before the BF16 keep-mask
  * scan of a pass over all points, each 64-query tile is checked against the
  * cells of the 256 pivots (points grouped by nearest pivot, each with an upper
  * bound on its radius); by the triangle inequality a (tile, cell) pair whose
@@ -162,7 +162,10 @@ fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps);
  * cannot keep a column and is not scanned.  The kept set, and so every
  * result, is the same with and without it; on well-separated clusters the
  * scan shrinks to the tiles' own clusters (Section 1 and Theorem 1 rely on a
- * KDE that is fast on such data).  Off: every pair is scanned. */
+ * KDE that is fast on such data).  enabled > 0: on; 0: off, every pair is
+ * scanned; < 0 (default): on for point sets of at least 2^18 points, where
+ * the scan it saves outweighs the plan and the conversion of the keep bits
+ * back to index order. */
 fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled);
 
 /* Cap the number of tree levels one binned KDE pass resolves (0 restores the

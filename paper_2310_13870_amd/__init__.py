@@ -151,9 +151,10 @@ class Context:
         """Precision mode: the share of every degree the root KDE may drop (0: e^-25, the exact mode)."""
         self.check(_lib.fsg_ctx_set_kde_error(self._h, float(eps)))
 
-    def set_pruning(self, enabled: bool):
-        """Precision mode: skip (query tile, cell) pairs that cannot keep a column (default on)."""
-        self.check(_lib.fsg_ctx_set_pruning(self._h, 1 if enabled else 0))
+    def set_pruning(self, enabled):
+        """Precision mode: skip (query tile, cell) pairs that cannot keep a column.
+        True: on; False: off; None (default): on for sets of at least 2^18 points."""
+        self.check(_lib.fsg_ctx_set_pruning(self._h, -1 if enabled is None else (1 if enabled else 0)))
 
     def set_profiling(self, enabled: bool):
         self.check(_lib.fsg_ctx_set_profiling(self._h, 1 if enabled else 0))

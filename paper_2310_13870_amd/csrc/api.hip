@@ -560,7 +560,8 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
             FSG_HIP(ctx, launch_fill_i64(ctx->filter_counts, 2, 0, ctx->stream));
         }
         m.kept = ctx->filter_counts;
-        if (ctx->pruning && X->Xbp) {
+        const bool prune = ctx->pruning > 0 || (ctx->pruning < 0 && n >= kPruneMinPoints);
+        if (prune && X->Xbp) {
             if ((st = pruned_keep_mask(ctx, X, m)) != FSG_OK) return st;
         } else {
             // pairs examined: every data column once per 64-query tile
@@ -1633,7 +1634,7 @@ fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind) {
 
 fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled) {
     if (!ctx) return FSG_E_INVALID;
-    ctx->pruning = enabled != 0;
+    ctx->pruning = enabled < 0 ? -1 : (enabled > 0 ? 1 : 0);
     return FSG_OK;
 }
 

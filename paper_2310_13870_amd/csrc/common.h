@@ -24,6 +24,9 @@ namespace fsg {
 // contiguous bytes.
 // ---------------------------------------------------------------------------
 constexpr int kLeafMax = 64;     // largest node the leaf stage resolves
+// smallest point set the tile pruning runs on by default: below it the
+// plan and the conversion back to index order cost more than the scan saves
+constexpr int64_t kPruneMinPoints = (int64_t)1 << 18;
 constexpr int kTileQ = 64;       // query entries per wave in the KDE kernel
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -210,7 +213,7 @@ struct fsg_ctx {
     // cap on the tree levels one binned pass resolves (0: automatic)
     int max_levels_per_pass = 0;
     // precision mode: skip (query tile, cell) pairs that cannot keep a column
-    bool pruning = true;
+    int32_t pruning = -1;        // tile pruning: -1 by size (n >= kPruneMinPoints), 0 off, 1 on
     // kernel of later calls (fsg_ctx_set_kernel)
     fsg_kernel kernel = FSG_GAUSSIAN;
     // precision mode: the dropped share of every degree allowed (0: e^-25)

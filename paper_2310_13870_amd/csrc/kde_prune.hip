@@ -65,9 +65,29 @@ __global__ __launch_bounds__(256) void pivot_dist_kernel(const float* __restrict
 // one wave: lane l holds candidates l, l + 64, l + 128, l + 192
 __global__ __launch_bounds__(64) void pivot_chain_kernel(const uint16_t* __restrict__ D16, int32_t P, int64_t n,
                                                          int32_t* __restrict__ rank, int32_t* __restrict__ cell_pivot) {
-    __shared__ uint16_t dl[kMaxPivots * kMaxPivots];
+    __shared__ __attribute__((aligned(16))) uint16_t dl[kMaxPivots * kMaxPivots];
     const int lane = threadIdx.x;
-    for (int32_t k = lane; k < P * P; k += 64) dl[k] = D16[k];
+    {
+        // 16 bytes per lane and load, eight loads in flight (D16 is 256-byte
+        // aligned workspace)
+        const int32_t nv = (P * P) / 8;
+        const uint4* src = (const uint4*)D16;
+        uint4* dst = (uint4*)dl;
+        for (int32_t k0 = 0; k0 < nv; k0 += 64 * 8) {
+            uint4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = k0 + 64 * u + lane;
+                v[u] = (k < nv) ? src[k] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = k0 + 64 * u + lane;
+                if (k < nv) dst[k] = v[u];
+            }
+        }
+        for (int32_t k = 8 * nv + lane; k < P * P; k += 64) dl[k] = D16[k];
+    }
     __syncthreads();
     uint32_t visited = (lane == 0) ? 1u : 0u;
     int32_t cur = 0;
@@ -413,7 +433,8 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
     const uint16_t* mrow = maskp + t * n_blocks_p;
     const int64_t n_cols = n_blocks * 16;
     for (int64_t w0 = 0; w0 < n_cols; w0 += kConvWindow) {
-        for (int32_t k = threadIdx.x; k < (int32_t)(kConvWindow / 32); k += kConvThreads) bits[k] = 0u;
+        const int32_t wwords = (int32_t)((min(kConvWindow, n_cols - w0) + 31) / 32);
+        for (int32_t k = threadIdx.x; k < wwords; k += kConvThreads) bits[k] = 0u;
         __syncthreads();
         // the group's scanned blocks are those of its cells: a wave per cell,
         // its lanes over the cell's blocks (a block shared with a neighbour
@@ -437,7 +458,13 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
         const int64_t kb0 = w0 / 16;
         const int64_t kbn = min(kConvWindow / 16, n_blocks - kb0);
         uint16_t* out = mask + t * n_blocks + kb0;
-        for (int64_t k = threadIdx.x; k < kbn; k += kConvThreads)
+        int64_t k4 = 0;  // blocks written four at a time (8-byte stores) where aligned
+        if (((t * n_blocks + kb0) & 3) == 0) {
+            k4 = kbn & ~(int64_t)3;
+            uint2* o2 = (uint2*)out;
+            for (int64_t k = threadIdx.x; k < k4 / 4; k += kConvThreads) o2[k] = make_uint2(bits[2 * k], bits[2 * k + 1]);
+        }
+        for (int64_t k = k4 + threadIdx.x; k < kbn; k += kConvThreads)
             out[k] = (uint16_t)(bits[k >> 1] >> (16 * (k & 1)));
         __syncthreads();
     }

@@ -104,7 +104,7 @@ def test_exponential_precision_mode_against_oracle(ctx, n, d, comps):
         ctx.reset_profiling()
         nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 17)
         out[prune] = (nbr.cpu().numpy(), deg.cpu().numpy(), ctx.filter_stats())
-    ctx.set_pruning(True)
+    ctx.set_pruning(None)
     assert np.array_equal(out[True][0], out[False][0]) and np.array_equal(out[True][1], out[False][1])
     say(f"exponential bf16 n={n} d={d}: kept/scanned pruned {out[True][2]}, full {out[False][2]}")
     nbr, deg, _ = out[True]

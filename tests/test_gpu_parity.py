@@ -384,7 +384,7 @@ def test_pruned_scan_keeps_the_same_set(ctx, n, d, L, spread, comps):
         nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 4242)
         kept, scanned = ctx.filter_stats()
         res[prune] = (nbr.cpu().numpy(), deg.cpu().numpy(), kept, scanned)
-    ctx.set_pruning(True)
+    ctx.set_pruning(None)
     (n0, d0, k0, s0), (n1, d1, k1, s1) = res[False], res[True]
     say(f"n={n} d={d}: kept {k0} / {k1}, scanned {s0} (full) / {s1} (pruned)")
     assert k0 == k1, "the pruned scan keeps a different number of (column, tile) pairs"
@@ -406,7 +406,11 @@ def test_pruned_scan_against_oracle_full_rows(ctx):
     gamma = 1.0 / 18.0
     pts = fsg.Points(ctx, to_dev(X), "bf16_split")
     ctx.reset_profiling()
-    nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 99)
+    try:
+        ctx.set_pruning(True)  # below the size where it is on by default
+        nbr, deg, _ = fsg.sample_edges(ctx, pts, gamma, L, 99)
+    finally:
+        ctx.set_pruning(None)
     kept, scanned = ctx.filter_stats()
     say(f"pruned: scanned {scanned} of {((n + 63) // 64) * n} column-tile pairs, kept {kept}")
     assert scanned < 0.4 * ((n + 63) // 64) * n
