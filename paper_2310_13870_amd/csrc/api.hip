@@ -665,7 +665,8 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if (pts_alloc(p, q_split_bytes, &qb) != hipSuccess) return fail("split operands");
     p->Qb = qb;
     if (pts_alloc(p, (size_t)n, &p->dmin) != hipSuccess) return fail("distance bounds");
-    if (pts_alloc(p, (size_t)n, &p->order) != hipSuccess) return fail("pivot order");
+    // the pivot order padded to whole 16-point blocks (read a block at a time)
+    if (pts_alloc(p, (size_t)((n + 15) & ~(int64_t)15), &p->order) != hipSuccess) return fail("pivot order");
     if (pts_alloc(p, 1, &p->xmax) != hipSuccess) return fail("norm bound");
     if (pts_alloc(p, (size_t)p->n_pad, &p->xa) != hipSuccess) return fail("norm terms");
     const int32_t P = (int32_t)(n < 256 ? n : 256);

@@ -283,15 +283,33 @@ __global__ __launch_bounds__(256) void pass_mask_kernel(KdeArgs a, const int32_t
     const int32_t col_begin = uniform(min(max(bnd[w.b0], 0), col_end));
     const int64_t wb = col_begin >> 4;
     const int32_t nblk = (int32_t)(((col_end + 15) >> 4) - wb);
+    // lane t: the root tile of entry t; the first entry of each run of equal
+    // tiles marks it (entries are sorted by pivot position)
+    const int32_t rt_l = (lane < w.ne) ? inv[a.q_idx[w.e0 + lane]] / kTileQ : -1;
+    const int32_t rt_prev = __shfl_up(rt_l, 1);
+    const uint64_t first = __ballot(lane < w.ne && (lane == 0 || rt_l != rt_prev));
     for (int32_t k0 = 0; k0 < W; k0 += 64) {
         const int32_t k = k0 + lane;
+        const bool in = k < nblk && k < W;
         uint32_t acc = 0;
-        int32_t prev = -1;
-        for (int32_t t = 0; t < w.ne; ++t) {
-            const int32_t rt = uniform(inv[a.q_idx[w.e0 + t]] / kTileQ);
-            if (rt == prev) continue;
-            prev = rt;
-            if (k < nblk && k < W) acc |= root_mask[(int64_t)rt * root_blocks + wb + k];
+        // eight distinct tiles at a time, their loads in flight together
+        uint64_t m = first;
+        while (m) {
+            int32_t rts[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                rts[u] = -1;
+                if (m) {
+                    const int32_t src = (int32_t)__builtin_ctzll(m);
+                    m &= m - 1ull;
+                    rts[u] = __builtin_amdgcn_readlane(rt_l, src);
+                }
+            }
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (in && rts[u] >= 0) ? root_mask[(int64_t)rts[u] * root_blocks + wb + k] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc |= v[u];
         }
         if (k < W) pmask[it * W + k] = (uint16_t)acc;
     }

@@ -416,7 +416,8 @@ int64_t prune_max_items(int64_t n_groups, int32_t P, int64_t n_chunks) { return 
 // tile's scanned blocks (pivot order, position e = point order[e]) are set in
 // a bitmap of columns in LDS, a window of 2^20 columns at a time, which is
 // then written out whole, so that every block of the tile's index-order row is
-// written (blocks without kept columns get 0).
+// written (blocks without kept columns get 0).  A block's 16 point indices are
+// loaded together (four 16-byte loads) before its bits are walked.
 // ---------------------------------------------------------------------------
 constexpr int kConvThreads = 512;
 constexpr int64_t kConvWindow = (int64_t)1 << 20;  // columns per LDS window (128 KB)
@@ -443,18 +444,28 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
             if (!((w[c >> 5] >> (c & 31)) & 1u)) continue;
             const int64_t b1 = ((int64_t)a.cell_start[c + 1] + 15) >> 4;
             for (int64_t b = (a.cell_start[c] >> 4) + (threadIdx.x & 63); b < b1; b += 64) {
-                uint32_t m = mrow[b];
-                while (m) {
-                    const int32_t k = __builtin_ctz(m);
-                    m &= m - 1u;
-                    const int64_t j = (int64_t)a.order[16 * b + k] - w0;
-                    if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
+                const uint32_t m = mrow[b];
+                if (m == 0u) continue;
+                // positions 16 b .. 16 b + 15 exist: the order array is padded
+                // to whole blocks (the padding's bits are never set)
+                const int4* ob = (const int4*)(a.order + 16 * b);
+                int4 o[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] = ob[q];
+                const int32_t pts[16] = {o[0].x, o[0].y, o[0].z, o[0].w, o[1].x, o[1].y, o[1].z, o[1].w,
+                                         o[2].x, o[2].y, o[2].z, o[2].w, o[3].x, o[3].y, o[3].z, o[3].w};
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if ((m >> k) & 1u) {
+                        const int64_t j = (int64_t)pts[k] - w0;
+                        if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
+                    }
                 }
             }
         }
         __syncthreads();
-        // write the window's blocks of the tile's row: block k of the window
-        // is half k % 2 of word k / 2
+        // the window's blocks of the tile's row: block k of the window is half
+        // k % 2 of word k / 2
         const int64_t kb0 = w0 / 16;
         const int64_t kbn = min(kConvWindow / 16, n_blocks - kb0);
         uint16_t* out = mask + t * n_blocks + kb0;
@@ -462,7 +473,8 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
         if (((t * n_blocks + kb0) & 3) == 0) {
             k4 = kbn & ~(int64_t)3;
             uint2* o2 = (uint2*)out;
-            for (int64_t k = threadIdx.x; k < k4 / 4; k += kConvThreads) o2[k] = make_uint2(bits[2 * k], bits[2 * k + 1]);
+            for (int64_t k = threadIdx.x; k < k4 / 4; k += kConvThreads)
+                o2[k] = make_uint2(bits[2 * k], bits[2 * k + 1]);
         }
         for (int64_t k = k4 + threadIdx.x; k < kbn; k += kConvThreads)
             out[k] = (uint16_t)(bits[k >> 1] >> (16 * (k & 1)));
