@@ -725,9 +725,7 @@ struct Sampler {
     uint64_t seed = 0;
     Plan plan;
     int64_t ns = 0;
-    int32_t n_uleaf = 0;
     int32_t* node = nullptr;   // [ns] current node of every sample
-    double* uleaf = nullptr;   // [ns][n_uleaf] uniforms of the leaf levels (or NULL)
     double* deg = nullptr;     // [n] degrees (NULL: not wanted)
     int32_t* nbr = nullptr;    // [ns] result
     float* margin = nullptr;   // [ns] optional decision margins
@@ -741,7 +739,6 @@ static fsg_status sampler_plan(fsg_ctx* ctx, Sampler& S) {
     S.ns = S.X->n * (int64_t)S.L;
     if (S.ns > 2147483647LL) return set_error(ctx, FSG_E_UNSUPPORTED, "n*L must be < 2^31");
     S.plan = make_plan(S.X->n, S.L, ctx->budget, ctx->max_levels_per_pass, S.X->prec);
-    S.n_uleaf = (!S.plan.passes.empty()) ? tree_depth(S.X->n) - S.plan.leaf_level : 0;
     return FSG_OK;
 }
 
@@ -754,10 +751,6 @@ static DescArgs desc_args(const Sampler& S, size_t p) {
     da.seed = S.seed;
     da.node = S.node;
     da.margin = S.margin;
-    if (p + 1 == S.plan.passes.size() && S.uleaf != nullptr && S.n_uleaf > 0) {
-        da.uleaf = S.uleaf;
-        da.n_uleaf = S.n_uleaf;
-    }
     return da;
 }
 
@@ -883,8 +876,6 @@ static LeafArgs leaf_args(const Sampler& S, const int32_t* bnd, const int32_t* s
     la.n_items = n_items;
     la.nbr = S.nbr;
     la.margin = S.margin;
-    la.uleaf = S.plan.passes.empty() ? nullptr : S.uleaf;
-    la.n_uleaf = S.plan.passes.empty() ? 0 : S.n_uleaf;
     if (S.root_mask != nullptr && X->inv != nullptr) {
         la.root_mask = S.root_mask;
         la.root_blocks = S.root_blocks;
@@ -1844,7 +1835,6 @@ fsg_status fsg_sample_edges(fsg_ctx* ctx, const fsg_points* Xc, double gamma, in
     S.margin = margin_dev;
     fsg_status st;
     if ((st = sampler_plan(ctx, S)) != FSG_OK) return st;
-    if (S.n_uleaf > 0 && (st = ws(ctx, "smp_uleaf", (size_t)S.ns * S.n_uleaf, &S.uleaf)) != FSG_OK) return st;
     if ((st = ws(ctx, "smp_node", (size_t)S.ns, &S.node)) != FSG_OK) return st;
     FSG_HIP(ctx, launch_init_samples(S.ns, S.node, margin_dev, ctx->stream));
     if (!S.plan.passes.empty()) {
@@ -1974,8 +1964,7 @@ void build_bytes_estimate(const fsg_ctx* ctx, int64_t n, int32_t d, int32_t L, f
            (2 * (uint64_t)leaf_max_items((int64_t)ns, plan.leaf_level) + 1) * 4;
     if (!plan.passes.empty()) {
         const int D = plan.passes[0].second;
-        const uint64_t n_uleaf = (uint64_t)(tree_depth(n) - plan.leaf_level);
-        job += ns * n_uleaf * 8 + ((uint64_t)n << D) * 8;
+        job += ((uint64_t)n << D) * 8;
         if (prec == FSG_BF16_SPLIT)  // keep masks and thresholds
             job += (uint64_t)((n + kTileQ - 1) / kTileQ) * (n_pad / 16) * 2 +
                    ((uint64_t)n + kThetaPad - 1) / kThetaPad * kThetaPad * 4;
@@ -2016,8 +2005,6 @@ fsg_status fsg_job_create(fsg_ctx* ctx, const fsg_points* Xc, double gamma, int3
     if (!(j->S.node = (int32_t*)job_alloc(j, ns * sizeof(int32_t), &st))) return fail(st);
     if (!(j->S.nbr = (int32_t*)job_alloc(j, ns * sizeof(int32_t), &st))) return fail(st);
     if (!(j->S.deg = (double*)job_alloc(j, n * sizeof(double), &st))) return fail(st);
-    if (j->S.n_uleaf > 0 && !(j->S.uleaf = (double*)job_alloc(j, ns * j->S.n_uleaf * sizeof(double), &st)))
-        return fail(st);
     if (!j->S.plan.passes.empty()) {
         j->root_D = j->S.plan.passes[0].second;
         if (!(j->M = (double*)job_alloc(j, (size_t)(n << j->root_D) * sizeof(double), &st))) return fail(st);

@@ -441,10 +441,6 @@ struct DescArgs {
     int32_t* node;             // sample -> node index at the current level (in/out)
     float* margin;             // sample -> running min margin (in/out), may be NULL
     double* deg;               // root pass: point -> degree, may be NULL
-    // uniforms of the levels after this pass, for the leaf stage (may be NULL):
-    // uleaf[sample * n_uleaf + k] = u(level = start_level + D + k)
-    double* uleaf;
-    int32_t n_uleaf;
     // root passes of several point sets in one launch (jobs != NULL): entries
     // [job_entry_off[k], job_entry_off[k+1]) are job k's, with the arguments
     // jobs[k]; n_entries is the total and lds_bytes the largest job's LDS
@@ -474,8 +470,6 @@ struct LeafArgs {
     const int32_t* n_items;
     int32_t* nbr;
     float* margin;
-    const double* uleaf;            // precomputed uniforms of the leaf levels (NULL: computed here)
-    int32_t n_uleaf;
     // precision mode, exact KDE: the root pass's keep masks (index order, a
     // row of root_blocks 16-column blocks per 64-entry tile of the pivot
     // order) and the points' pivot positions; NULL: every point is evaluated

@@ -34,10 +34,9 @@ __device__ __forceinline__ bool choose_left(double u, double mL, double mR, bool
 constexpr int kDescThreads = 256;
 constexpr int kDescChunk = 64;
 
-// Philox level groups a root descent draws from (the levels it resolves and
-// the leaf levels whose uniforms it stores)
+// Philox level groups a root descent draws from (the levels it resolves)
 __host__ __device__ inline int32_t desc_groups(const DescArgs& a) {
-    const int32_t last_level = a.start_level + a.D - 1 + (a.uleaf != nullptr ? a.n_uleaf : 0);
+    const int32_t last_level = a.start_level + a.D - 1;
     return (last_level >> 2) - (a.start_level >> 2) + 1;
 }
 
@@ -137,12 +136,6 @@ __global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a0,
                     }
                     a.node[smp] = m;
                     if (a.margin != nullptr) a.margin[smp] = mg;
-                    if (a.uleaf != nullptr) {
-                        for (int32_t q = 0; q < a.n_uleaf; ++q) {
-                            const int32_t level = a.start_level + a.D + q;
-                            a.uleaf[smp * a.n_uleaf + q] = word_to_uniform(wk[((level >> 2) - g0) * 4 + (level & 3)]);
-                        }
-                    }
                 }
             }
             __syncthreads();
@@ -184,8 +177,6 @@ __global__ __launch_bounds__(256) void descend_entries_kernel(DescArgs a) {
     }
     a.node[smp] = (v << D) + m;
     if (a.margin != nullptr) a.margin[smp] = mg;
-    if (a.uleaf != nullptr)
-        for (int32_t q = 0; q < a.n_uleaf; ++q) a.uleaf[(int64_t)smp * a.n_uleaf + q] = uni.at(a.start_level + D + q);
 }
 
 // Philox blocks of at most min(L, kDescChunk) samples at a time: at L = 17
@@ -303,7 +294,6 @@ __device__ __forceinline__ bool leaf_sparse_tail(const LeafArgs& a, const float 
     if (active) {
         SampleUniforms uni;
         uni.init(a.seed, (uint64_t)i, (uint64_t)l);
-        const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
         float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
         int32_t na = 0, nbd = cnt, level = a.level;
         while (nbd - na > 1) {
@@ -316,7 +306,7 @@ __device__ __forceinline__ bool leaf_sparse_tail(const LeafArgs& a, const float 
                 mL += (in_node && left) ? kv[k] : 0.0;
                 mR += (in_node && !left) ? kv[k] : 0.0;
             }
-            const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
+            const double u = uni.at(level);
             const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
             if (go_left) nbd = mid; else na = mid;
             ++level;
@@ -553,8 +543,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
             } else {
                 SampleUniforms uni;
                 uni.init(a.seed, (uint64_t)i, (uint64_t)l);
-                const double* ul = (a.uleaf != nullptr) ? a.uleaf + (int64_t)smp * a.n_uleaf : nullptr;
-                float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+                        float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
                 int32_t na = 0, nbd = cnt, level = a.level;
                 while (nbd - na > 1) {
                     const int32_t mid = tree_split(na, nbd);
@@ -566,7 +555,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void le
                         mL += (in_node && left) ? kv[j] : 0.0;
                         mR += (in_node && !left) ? kv[j] : 0.0;
                     }
-                    const double u = (ul != nullptr) ? ul[level - a.level] : uni.at(level);
+                    const double u = uni.at(level);
                     const bool go_left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
                     if (go_left) nbd = mid; else na = mid;
                     ++level;
