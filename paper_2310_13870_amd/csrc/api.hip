@@ -1571,7 +1571,7 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
     for (fsg_points* p : ctx->points) {
         for (void* v : {(void*)p->Xp, (void*)p->norm, (void*)p->Xb, (void*)p->Qb, (void*)p->dmin, (void*)p->order,
                         (void*)p->xmax, (void*)p->xa, (void*)p->Xbp, (void*)p->xap, (void*)p->cell_start,
-                        (void*)p->cell_pivot, (void*)p->pnorm, (void*)p->prad})
+                        (void*)p->cell_pivot, (void*)p->pnorm, (void*)p->prad, (void*)p->inv})
             if (v) ctx->pool_size.erase(v);
         for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
         p->ctx = nullptr;
@@ -1772,6 +1772,7 @@ void fsg_points_destroy(fsg_points* p) {
     pts_free(p, p->cell_pivot);
     pts_free(p, p->pnorm);
     pts_free(p, p->prad);
+    pts_free(p, p->inv);
     for (auto& kv : p->levels) pts_free(p, kv.second);
     delete p;
 }
