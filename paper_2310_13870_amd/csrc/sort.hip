@@ -141,17 +141,26 @@ __device__ __forceinline__ uint64_t peers_of(uint32_t digit, bool active) {
     return peers;
 }
 
+// The tile is first ordered by digit in LDS (stable), then written out in
+// that order: the keys of one digit leave a tile as one contiguous run, so
+// the global writes are whole runs instead of 4-byte scatters.
 template <typename K>
 __global__ __launch_bounds__(256) void radix_scatter_kernel(const K* __restrict__ keys, const int32_t* __restrict__ vals,
                                                           K* __restrict__ keys_out, int32_t* __restrict__ vals_out,
                                                           int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                           int64_t nb) {
     __shared__ uint32_t wcount[4][256];
-    __shared__ uint32_t wbase[4][256];
+    __shared__ uint32_t wbase[4][256];   // tile-local position of each wave's next key of a digit
+    __shared__ uint32_t dstart[256];     // tile-local start of each digit
+    __shared__ uint32_t gstart[256];     // global start of each digit's run of this tile
+    __shared__ K lk[kSortTile];
+    __shared__ int32_t lv[kSortTile];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int k = threadIdx.x; k < 4 * 256; k += kSortThreads) (&wcount[0][0])[k] = 0;
     __syncthreads();
-    const int64_t wstart = (int64_t)blockIdx.x * kSortTile + (int64_t)wv * kWaveKeys;
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int32_t tile_n = (int32_t)min((int64_t)kSortTile, n - tile0);
+    const int64_t wstart = tile0 + (int64_t)wv * kWaveKeys;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // pass 1: per-wave digit counts
     for (int c = 0; c < kWaveKeys; c += 64) {
@@ -162,16 +171,31 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const K* __restrict_
         if (active && (63 - __clzll(peers)) == lane) wcount[wv][digit] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // bases: global digit offset of this block plus the counts of earlier waves
-    for (int dg = threadIdx.x; dg < 256; dg += kSortThreads) {
-        uint32_t run = offs[(int64_t)dg * nb + blockIdx.x];
+    // tile-local digit starts (exclusive scan over the digits of the tile's
+    // counts), then each wave's base within its digit
+    {
+        const int dg = threadIdx.x;  // 256 threads, one per digit
+        const uint32_t tot = wcount[0][dg] + wcount[1][dg] + wcount[2][dg] + wcount[3][dg];
+        dstart[dg] = tot;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t v = (dg >= off) ? dstart[dg - off] : 0u;
+            __syncthreads();
+            dstart[dg] += v;
+            __syncthreads();
+        }
+        const uint32_t ex = dstart[dg] - tot;
+        __syncthreads();
+        dstart[dg] = ex;
+        uint32_t run = ex;
         for (int w = 0; w < 4; ++w) {
             wbase[w][dg] = run;
             run += wcount[w][dg];
         }
+        gstart[dg] = offs[(int64_t)dg * nb + blockIdx.x];
     }
     __syncthreads();
-    // pass 2: stable scatter
+    // pass 2: stable placement in LDS
     for (int c = 0; c < kWaveKeys; c += 64) {
         const int64_t idx = wstart + c + lane;
         const bool active = idx < n;
@@ -185,12 +209,21 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const K* __restrict_
         const uint64_t peers = peers_of(digit, active);
         if (active) {
             const uint32_t pos = wbase[wv][digit] + (uint32_t)__popcll(peers & below);
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+            lk[pos] = key;
+            lv[pos] = val;
         }
         __builtin_amdgcn_wave_barrier();
         if (active && (63 - __clzll(peers)) == lane) wbase[wv][digit] += (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // runs out in tile order
+    for (int32_t p = threadIdx.x; p < tile_n; p += kSortThreads) {
+        const K key = lk[p];
+        const uint32_t digit = (uint32_t)(key >> shift) & 255u;
+        const uint32_t g = gstart[digit] + ((uint32_t)p - dstart[digit]);
+        keys_out[g] = key;
+        vals_out[g] = lv[p];
     }
 }
 
