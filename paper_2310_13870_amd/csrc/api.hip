@@ -297,6 +297,12 @@ static KdeArgs kde_args(const fsg_points* Q, const fsg_points* X, double gamma, 
     a.n_query = Q->n;
     a.n_data = X->n;
     a.s = gamma * 1.442695040888963407359924681001892137;
+    if (kind == FSG_GAUSSIAN && Q->Xs && X->Xs) {
+        a.Qs = Q->Xs;
+        a.qe = Q->xe;
+        a.Xs = X->Xs;
+        a.xe = X->xe;
+    }
     return a;
 }
 
@@ -530,7 +536,8 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if (!bnd) return st;
     const int64_t n = X->n;
     const int32_t nbins = 1 << D;
-    const int32_t tile = (X->prec == FSG_BF16_SPLIT) ? exact_tile(X->D4) : kde_tile(X->D4);
+    const int32_t tile = (X->prec == FSG_BF16_SPLIT) ? exact_tile(X->D4, X->Xs && ctx->kernel == FSG_GAUSSIAN)
+                                                     : kde_tile(X->D4);
     const int64_t tiles = (n + tile - 1) / tile;
     const int32_t bpc = root_bins_per_item(ctx, tiles, nbins);
     const int64_t n_items = tiles * ((nbins + bpc - 1) / bpc);
@@ -682,6 +689,13 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if (pts_alloc(p, (size_t)n, &p->inv) != hipSuccess) return fail("pivot positions");
     p->bytes += split_bytes + 2 * q_split_bytes + n * (sizeof(double) + sizeof(int32_t)) + sizeof(double) +
                 p->n_pad * sizeof(float) + q_rows * sizeof(float) + (4 * (size_t)P + 1) * 4 + n * sizeof(int32_t);
+    // the exact recompute's integer slices (32 < d <= 64)
+    const bool sliced = p->D4 == 16;
+    if (sliced) {
+        if (pts_alloc(p, (size_t)p->n_pad * kSliceRow, &p->Xs) != hipSuccess) return fail("integer slices");
+        if (pts_alloc(p, (size_t)p->n_pad, &p->xe) != hipSuccess) return fail("integer slices");
+        p->bytes += (size_t)p->n_pad * (kSliceRow + sizeof(int32_t));
+    }
     fsg_status st;
     if ((st = ws(ctx, "pivot_labels", (size_t)n, &label)) != FSG_OK) return st;
     SortBufs b = sort_bufs(ctx, n, sizeof(uint32_t), &st);
@@ -694,6 +708,7 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if ((st = ws(ctx, "pivot_rank", (size_t)P, &rank)) != FSG_OK) return st;
     StageTimer t(ctx, "prep");
     FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->xa, ctx->stream));
+    if (sliced) FSG_HIP(ctx, launch_prep_slices(p->X, n, p->d, p->n_pad, p->Xs, p->xe, ctx->stream));
     FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
     // cells labelled along a nearest-neighbour chain of the pivots, so that
     // neighbouring cells of the pivot order are close together
@@ -778,7 +793,9 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     // precision mode with the root pass's masks: every item reads only the
     // columns its samples' points kept at the root (W blocks per item at
     // most: a node holds at most ceil(n / 2^start) points)
-    const int32_t tile_m = exact_tile(X->D4);
+    // later passes recompute in FP64 (64-query items): their items hold few
+    // kept columns each, where the integer slices' 32-query items cost more
+    const int32_t tile_m = exact_tile(X->D4, false);
     const int64_t max_items_m = ns / tile_m + n_nodes + 1;
     const int64_t node_max = (X->n + n_nodes - 1) / n_nodes;
     const int32_t W = (int32_t)((node_max + 15) / 16 + 2);
@@ -813,6 +830,8 @@ static fsg_status stage_pass(fsg_ctx* ctx, const Sampler& S, size_t p) {
     FSG_HIP(ctx, launch_build_items(q_ptr, n_nodes, nbins, nbins, tile, scratch, items, n_items, max_items,
                                     ctx->stream));
     KdeArgs a = kde_args(X, X, S.gamma, S.kind);
+    a.Qs = a.Xs = nullptr;
+    a.qe = a.xe = nullptr;
     a.q_idx = q_idx;
     a.self_idx = q_idx;
     a.self_mode = SELF_ARRAY;
@@ -1174,12 +1193,20 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
     int64_t* hmoff = (int64_t*)(h + o_moff);
     int64_t total = 0, mtotal = 0;
     fsg_status st;
+    // one exact-recompute variant per launch: the integer slices only where
+    // every set of the launch has them
+    bool all_sliced = bf16;
+    for (int32_t i = 0; i < G; ++i) all_sliced = all_sliced && g[i]->S.X->Xs != nullptr;
     for (int32_t i = 0; i < G; ++i) {
         fsg_job* j = g[i];
         if ((st = job_root_args(ctx, j, &hargs[i], &hmargs[i])) != FSG_OK) return fail(st);
+        if (!all_sliced) {
+            hargs[i].Qs = hargs[i].Xs = nullptr;
+            hargs[i].qe = hargs[i].xe = nullptr;
+        }
         const int64_t n = j->S.X->n;
         const int32_t nbins = 1 << j->root_D;
-        const int32_t tile = bf16 ? exact_tile(j->S.X->D4) : kde_tile(j->S.X->D4);
+        const int32_t tile = bf16 ? exact_tile(j->S.X->D4, all_sliced) : kde_tile(j->S.X->D4);
         const int64_t n_tiles = (n + tile - 1) / tile;
         int64_t bpc;
         if (bf16) {
@@ -1571,7 +1598,8 @@ void fsg_ctx_destroy(fsg_ctx* ctx) {
     for (fsg_points* p : ctx->points) {
         for (void* v : {(void*)p->Xp, (void*)p->norm, (void*)p->Xb, (void*)p->Qb, (void*)p->dmin, (void*)p->order,
                         (void*)p->xmax, (void*)p->xa, (void*)p->Xbp, (void*)p->xap, (void*)p->cell_start,
-                        (void*)p->cell_pivot, (void*)p->pnorm, (void*)p->prad, (void*)p->inv})
+                        (void*)p->cell_pivot, (void*)p->pnorm, (void*)p->prad, (void*)p->inv, (void*)p->Xs,
+                        (void*)p->xe})
             if (v) ctx->pool_size.erase(v);
         for (auto& kv : p->levels) ctx->pool_size.erase(kv.second);
         p->ctx = nullptr;
@@ -1773,6 +1801,8 @@ void fsg_points_destroy(fsg_points* p) {
     pts_free(p, p->pnorm);
     pts_free(p, p->prad);
     pts_free(p, p->inv);
+    pts_free(p, p->Xs);
+    pts_free(p, p->xe);
     for (auto& kv : p->levels) pts_free(p, kv.second);
     delete p;
 }

@@ -30,6 +30,23 @@ constexpr int64_t kPruneMinPoints = (int64_t)1 << 18;
 constexpr int kTileQ = 64;       // query entries per wave in the KDE kernel
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef int32_t int4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Integer slices of the points (precision mode, 32 < d <= 64): point p's row
+// scaled by 2^-e_p (e_p chosen so that every |x_k| 2^-e_p < 0.498) and
+// rounded to a multiple of 2^-56 is written as kSlices signed base-256 digits
+// per coordinate,
+//   x_k 2^-e_p = sum_{a=1..kSlices} c_{a,k} 2^-8a + r_k,  c in [-128, 127], |r_k| <= 2^-57,
+// (balanced digits, taken from the least significant up; every FP32
+// coordinate at least 2^-30 times its row's largest is exact).  Slice a of point
+// p is 64 bytes at Xs[p * kSliceRow + 64 a] (coordinates zero-padded to 64),
+// e_p is xe[p].  v_mfma_i32_16x16x64_i8: lane l supplies 16 bytes of row l%16
+// of A and of column l%16 of B (the same 16 of the 64 K positions, at byte
+// 16 (l/16) of the slice) and receives C[4 (l/16) + i][l%16] in element i.
+// ---------------------------------------------------------------------------
+constexpr int kSlices = 7;
+constexpr int kSliceRow = 64 * kSlices;
 
 // One unit of KDE work for one wave: up to 16*RQ query entries of one
 // segment against the bins [b0, b1) of that segment.
@@ -87,6 +104,12 @@ struct KdeArgs {
     // precision mode, later passes: one mask row per work item, holding the
     // blocks from the item's first column on (row `item`, entry b - first block)
     int32_t mask_by_item;
+    // precision mode, 32 < d <= 64, Gaussian kernel: integer slices of the
+    // query and data points (NULL: the cross terms are recomputed in FP64)
+    const int8_t* Qs;
+    const int32_t* qe;
+    const int8_t* Xs;
+    const int32_t* xe;
 };
 
 // Filtered KDE (precision mode): BF16 split operands decide which pairs are
@@ -282,6 +305,8 @@ struct fsg_points {
     int32_t* cell_start = nullptr;
     int32_t* cell_pivot = nullptr;
     int32_t* inv = nullptr;    // point -> its position in the pivot order
+    int8_t* Xs = nullptr;      // integer slices [n_pad][kSliceRow] (32 < d <= 64)
+    int32_t* xe = nullptr;     // their row exponents [n_pad]
     float* pnorm = nullptr;
     float* prad = nullptr;
     int32_t P = 0;
@@ -361,6 +386,8 @@ int feature_steps(int d);
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip sources).
 // ---------------------------------------------------------------------------
+hipError_t launch_prep_slices(const float* X, int64_t n, int32_t d, int64_t n_pad, int8_t* Xs, int32_t* xe,
+                              hipStream_t st);
 hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t n_pad, double* Xp, double* norm,
                        hipStream_t st);
 hipError_t launch_level_bounds(int64_t n, int level, int32_t* out, hipStream_t st);
@@ -370,7 +397,9 @@ hipError_t launch_kde(const KdeArgs& a, int64_t max_items, int num_cus, hipStrea
 // the Laplacian kernel's binned KDE on the vector units (kde_l1.hip)
 hipError_t launch_kde_l1(const KdeArgs& a, int64_t max_items, int num_cus, hipStream_t st);
 int kde_tile(int D4);  // query entries per work item of the plain kernel
-int exact_tile(int D4);  // query entries per work item of the exact recompute (precision mode)
+// query entries per work item of the exact recompute (precision mode; sliced:
+// the integer-slice variant runs)
+int exact_tile(int D4, bool sliced);
 hipError_t launch_batch_items(const BatchItemDesc* jd, int32_t n_jobs, int64_t total, WorkItem* items,
                               int32_t* n_items, hipStream_t st);
 hipError_t launch_keep_mask(const MaskArgs& m, int num_cus, hipStream_t st);

@@ -53,14 +53,46 @@ struct Gathered {
     int32_t first, last;  // smallest and largest column (uniform)
 };
 
-template <int D4, int RQ, bool MULTI, int KIND = kKindGaussian>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void kde_exact_kept_kernel(
-    KdeArgs a, unsigned long long* __restrict__ next_item) {
+// The integer-slice variant (32 < d <= 64, Gaussian kernel): the cross term
+// of a pair is 2^(e_q + e_x) sum_{a+b <= kSlices+1} 2^-8(a+b) (q_a . x_b) over
+// the slices (layout in common.h), each slice product an exact integer on
+// v_mfma_i32_16x16x64_i8 (|q_a . x_b| <= 64 * 2^14 = 2^20; a group of equal
+// a+b holds at most 7 of them, so the int32 accumulators cannot overflow and
+// two neighbouring groups join exactly in 32 bits).  The joined groups are
+// summed in FP64 (three roundings).  Against the exact product, the dropped
+// slice pairs (a+b > kSlices+1: at most 6.02 d 2^-58) and the digits past the
+// last slice (d 2^-57) add at most 8.1 d 2^(e_q + e_x - 58) <= 4.1 d 2^-53 |q| |x|
+// (2^e <= 4.02 max|x_k|), the order of the rounding of a d-term FP64
+// accumulation; the FP64 recompute's bin sums then follow unchanged.  Items
+// of 32 queries; their slices are staged in LDS.
+struct GatheredS {
+    int4_t xs[kSlices];  // this lane's 16 bytes of every slice of its column (A row lane % 16)
+    double xn[4];        // |x|^2 of the lane's four result columns (padding: jj = INT32_MAX)
+    int32_t jj[4];
+    int32_t xe[4];       // their row exponents
+    int32_t first, last;
+};
+
+template <int D4, bool SLICED>
+struct GatherSel {
+    using type = Gathered<D4>;
+};
+template <int D4>
+struct GatherSel<D4, true> {
+    using type = GatheredS;
+};
+
+template <int D4, int RQ, bool MULTI, int KIND = kKindGaussian, bool SLICED = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves<D4>()))) void
+kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
+    static_assert(!SLICED || (D4 == 16 && RQ == 2 && KIND == kKindGaussian && kSlices == 7),
+                  "integer slices: 32 < d <= 64, 32-query items, Gaussian kernel");
     // queue length: fewer than 16 entries left over plus the columns of the
     // blocks one fill step takes (at least 17 blocks of 16 fit)
     constexpr int QN = 288;
     __shared__ int32_t queue_all[4][QN];
-    __shared__ float qf_all[4][RQ * D4 * 64];
+    // per wave: the FP32 query fragments, or the query slices ([qb][slice][lane] x 16 bytes)
+    __shared__ float qf_all[4][SLICED ? RQ * kSlices * 64 * 4 : RQ * D4 * 64];
     __shared__ int32_t win_all[4][kBinWindow];
     __shared__ double exp_tab[256];
     load_exp2_table(exp_tab);
@@ -89,6 +121,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         const double two_s = 2.0 * s256;
         double hq[RQ];
         int32_t selfv[RQ], smin[RQ], smax[RQ];
+        double two_sq[RQ];  // 2 s 256 2^(e_q - 24): the slice sums' scale on the query side
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int qb = 0; qb < RQ; ++qb) {
@@ -101,10 +134,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             if (ok) sf = (J.self_mode == SELF_POINT) ? p : ((J.self_mode == SELF_ARRAY) ? J.self_idx[e] : -1);
             selfv[qb] = sf;
             hq[qb] = (KIND == kKindExponential) ? J.qnorm[p] : -s256 * J.qnorm[p];
-            double qv[D4];
-            load_row_part<D4>(qv, J.Qp, p, grp);
+            if constexpr (SLICED) {
+                const int8_t* qrow = J.Qs + (int64_t)p * kSliceRow + 16 * grp;
+                int4_t* qs = (int4_t*)qf;
 #pragma unroll
-            for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = (float)qv[kk];  // exact
+                for (int sa = 0; sa < kSlices; ++sa) qs[(qb * kSlices + sa) * 64 + lane] = *(const int4_t*)(qrow + 64 * sa);
+                two_sq[qb] = __builtin_ldexp(two_s, J.qe[p] - 24);
+            } else {
+                double qv[D4];
+                load_row_part<D4>(qv, J.Qp, p, grp);
+#pragma unroll
+                for (int kk = 0; kk < D4; ++kk) qf[(qb * D4 + kk) * 64 + lane] = (float)qv[kk];  // exact
+            }
             int32_t mn = sf >= 0 ? sf : INT32_MAX, mx = sf;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
@@ -208,6 +249,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
             }
         };
 
+        // the same for the slices: A row r holds queue entry r (the i32
+        // result element i of lane group g is row 4g + i)
+        auto prepare_s = [&](GatheredS& g, int32_t pos, int32_t cnt) {
+            const int32_t gl = queue[pos + ((r < cnt) ? r : 0)];
+            const int8_t* xrow = J.Xs + (int64_t)gl * kSliceRow + 16 * grp;
+#pragma unroll
+            for (int sb = 0; sb < kSlices; ++sb) g.xs[sb] = *(const int4_t*)(xrow + 64 * sb);
+            g.first = uniform(queue[pos]);
+            g.last = uniform(queue[pos + cnt - 1]);
+            // padding positions read the last column; their |x|^2 becomes +inf
+            // only where it is used, so that no wait for these loads comes
+            // before the next block's products
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t idx = 4 * grp + i;
+                const int32_t col = queue[pos + min(idx, cnt - 1)];
+                g.jj[i] = (idx < cnt) ? col : INT32_MAX;
+                g.xn[i] = J.xnorm[col];
+                g.xe[i] = J.xe[col];
+            }
+        };
+
+        // the 28 slice products of query block qb, the query slices read from
+        // LDS one at a time: consecutive products go to different accumulators
+        auto slice_products = [&](int4_t (&ac)[kSlices], int qb, const GatheredS& g) {
+            const int4_t* qs = (const int4_t*)qf + qb * kSlices * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < kSlices; ++k) ac[k] = int4_t{0, 0, 0, 0};
+            int4_t q[kSlices];
+#pragma unroll
+            for (int sa = 0; sa < kSlices; ++sa) q[sa] = qs[sa * 64];
+#pragma unroll
+            for (int sa = 0; sa < kSlices; ++sa) {
+#pragma unroll
+                for (int sb = 0; sa + sb < kSlices; ++sb)
+                    ac[sa + sb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(g.xs[sb], q[sa], ac[sa + sb], 0, 0, 0);
+            }
+        };
+        // the kernel values of one query block from its slice sums (no
+        // self-pair test; that follows for the whole block)
+        auto slice_values = [&](const int4_t (&ac)[kSlices], int qb, const GatheredS& g, const double (&xn)[4],
+                                double (&kvq)[4]) {
+            double rr[4], t[4];
+            int32_t mi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // groups 2k and 2k+1 joined exactly in 32 bits (|group| < 7 2^20);
+                // group 2k+1 has weight 2^-8(2k+3), the last group 2^-64
+                int32_t pr[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    pr[k] = (int32_t)(((uint32_t)ac[2 * k][i] << 8) + (uint32_t)ac[2 * k + 1][i]);
+                double v = __builtin_fma((double)pr[1], 0x1p-16, (double)pr[0]);
+                v = __builtin_fma((double)pr[2], 0x1p-32, v);
+                v = __builtin_fma((double)ac[6][i], 0x1p-40, v);
+                v = __builtin_ldexp(v, g.xe[i]);
+                mi[i] = exp2_256_split(pair_exponent<KIND>(v, hq[qb], xn[i], -s256, two_sq[qb]), &rr[i]);
+                t[i] = exp_tab[mi[i] & 255];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) kvq[i] = exp2_256_join(t[i], rr[i], mi[i]);
+        };
+
+        auto compute_s = [&](const GatheredS& g) {
+            double kv[RQ][4];
+            double xn[4];  // padding columns: |x|^2 = +inf gives exponent -inf and value 0
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xn[i] = (g.jj[i] == INT32_MAX) ? __builtin_inf() : g.xn[i];
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb) {
+                int4_t acc[kSlices];
+                slice_products(acc, qb, g);
+                slice_values(acc, qb, g, xn, kv[qb]);
+            }
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb) {
+                if (smax[qb] >= g.first && smin[qb] <= g.last &&
+                    __ballot(selfv[qb] >= g.first && selfv[qb] <= g.last) != 0) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (g.jj[i] == selfv[qb]) kv[qb][i] = 0.0;
+                }
+            }
+            bins.add(kv, g.jj, g.last);
+        };
+
         auto compute = [&](const Gathered<D4>& g) {
             // padding columns: |x|^2 = +inf gives exponent -inf and value 0
             double4_t c[RQ];
@@ -230,26 +357,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(exact_waves
         if (tail > head) {
             // two operand buffers in turn: the next block gathers while this
             // one computes
-            Gathered<D4> g0, g1;
+            typename GatherSel<D4, SLICED>::type g0, g1;
+            auto prep_any = [&](typename GatherSel<D4, SLICED>::type& g, int32_t pos, int32_t cnt) {
+                if constexpr (SLICED)
+                    prepare_s(g, pos, cnt);
+                else
+                    prepare(g, pos, cnt);
+            };
+            auto compute_any = [&](const typename GatherSel<D4, SLICED>::type& g) {
+                if constexpr (SLICED)
+                    compute_s(g);
+                else
+                    compute(g);
+            };
             int32_t n0 = min(16, tail - head);
-            prepare(g0, head, n0);
+            prep_any(g0, head, n0);
             head += n0;
             while (true) {
                 fill();
                 const int32_t n1 = min(16, tail - head);
                 if (n1 > 0) {
-                    prepare(g1, head, n1);
+                    prep_any(g1, head, n1);
                     head += n1;
                 }
-                compute(g0);
+                compute_any(g0);
                 if (n1 == 0) break;
                 fill();
                 const int32_t n2 = min(16, tail - head);
                 if (n2 > 0) {
-                    prepare(g0, head, n2);
+                    prep_any(g0, head, n2);
                     head += n2;
                 }
-                compute(g1);
+                compute_any(g1);
                 if (n2 == 0) break;
             }
         }
@@ -326,6 +465,19 @@ hipError_t launch_pass_mask(const KdeArgs& a, int64_t max_items, const int32_t* 
 template <int D4>
 static hipError_t launch_exact_t(const KdeArgs& a, int64_t max_items, unsigned long long* next_item, int num_cus,
                                  hipStream_t st) {
+    if constexpr (D4 == 16) {
+        if (a.Xs && a.Qs && a.kind == kKindGaussian) {
+            int64_t waves = (int64_t)num_cus * 8;
+            if (max_items < waves) waves = max_items;
+            if (waves < 1) waves = 1;
+            const unsigned blocks = (unsigned)((waves + 3) / 4);
+            if (a.jobs)
+                kde_exact_kept_kernel<16, 2, true, kKindGaussian, true><<<blocks, 256, 0, st>>>(a, next_item);
+            else
+                kde_exact_kept_kernel<16, 2, false, kKindGaussian, true><<<blocks, 256, 0, st>>>(a, next_item);
+            return hipGetLastError();
+        }
+    }
     int64_t waves = (int64_t)num_cus * 8;
     if (max_items < waves) waves = max_items;
     if (waves < 1) waves = 1;
@@ -357,6 +509,6 @@ hipError_t launch_exact_kept(const KdeArgs& a, int64_t max_items, unsigned long 
     }
 }
 
-int exact_tile(int D4) { return D4 >= 32 ? 32 : 64; }
+int exact_tile(int D4, bool sliced) { return (D4 >= 32 || sliced) ? 32 : 64; }
 
 }  // namespace fsg

@@ -1,5 +1,6 @@
-// Hot-path step "prep": FP64 matrix-core operand rows, squared norms,
-// and the node boundaries of one level of the index-order partition tree.
+// Hot-path step "prep": FP64 matrix-core operand rows, squared norms, the
+// integer slices of the precision mode's exact recompute, and the node
+// boundaries of one level of the index-order partition tree.
 #include "common.h"
 #include "device.h"
 
@@ -66,6 +67,44 @@ hipError_t launch_prep(const float* X, int64_t n, int32_t d, int32_t D4, int64_t
     if (rows > 256) rows = 256;
     if (rows < 1) return hipErrorInvalidValue;
     prep_norms_kernel<<<(unsigned)((n_pad + rows - 1) / rows), 256, 0, st>>>(X, n, d, n_pad, rows, norm);
+    return hipGetLastError();
+}
+
+// Integer slices (layout in common.h): one wave per point, a lane per
+// coordinate.  The scaled coordinate times 2^56 is an integer below 2^55 in
+// magnitude (exact in FP64 up to the rounding of coordinates below 2^-56 of
+// the scale); its digits come off the low end in 64-bit integers.
+__global__ __launch_bounds__(256) void prep_slices_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                          int64_t n_pad, int8_t* __restrict__ Xs,
+                                                          int32_t* __restrict__ xe) {
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= n_pad) return;
+    const float x = (p < n && lane < d) ? X[p * d + lane] : 0.0f;
+    float m = __builtin_fabsf(x);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off));
+    int e = 0;
+    if (m > 0.0f) {
+        // m = f 2^e with f in [0.5, 1): m 2^-(e+1) < 0.498 unless f >= 0.996
+        const float f = __builtin_frexpf(m, &e);
+        e += (f >= 0.996f) ? 2 : 1;
+    }
+    int64_t v = (int64_t)__builtin_rint(__builtin_ldexp((double)x, 56 - e));
+    int8_t* row = Xs + p * kSliceRow;
+#pragma unroll
+    for (int a = kSlices - 1; a >= 0; --a) {
+        const int64_t c = ((v + 128) & 255) - 128;
+        v = (v - c) >> 8;
+        row[64 * a + lane] = (int8_t)c;
+    }
+    if (lane == 0) xe[p] = e;
+}
+
+hipError_t launch_prep_slices(const float* X, int64_t n, int32_t d, int64_t n_pad, int8_t* Xs, int32_t* xe,
+                              hipStream_t st) {
+    if (d > 64) return hipErrorInvalidValue;
+    prep_slices_kernel<<<(unsigned)((n_pad + 3) / 4), 256, 0, st>>>(X, n, d, n_pad, Xs, xe);
     return hipGetLastError();
 }
 
