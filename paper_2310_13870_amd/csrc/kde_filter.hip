@@ -312,17 +312,43 @@ kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
             for (int i = 0; i < 4; ++i) kvq[i] = exp2_256_join(t[i], rr[i], mi[i]);
         };
 
+        auto slice_values2 = [&](const int4_t (&ac)[RQ][kSlices], const GatheredS& g, const double (&xn)[4],
+                                 double (&kvq)[RQ][4]) {
+            double rr[RQ][4], t[RQ][4];
+            int32_t mi[RQ][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int qb = 0; qb < RQ; ++qb) {
+                    int32_t pr[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        pr[k] = (int32_t)(((uint32_t)ac[qb][2 * k][i] << 8) + (uint32_t)ac[qb][2 * k + 1][i]);
+                    double v = __builtin_fma((double)pr[1], 0x1p-16, (double)pr[0]);
+                    v = __builtin_fma((double)pr[2], 0x1p-32, v);
+                    v = __builtin_fma((double)ac[qb][6][i], 0x1p-40, v);
+                    v = __builtin_ldexp(v, g.xe[i]);
+                    mi[qb][i] = exp2_256_split(pair_exponent<KIND>(v, hq[qb], xn[i], -s256, two_sq[qb]), &rr[qb][i]);
+                    t[qb][i] = exp_tab[mi[qb][i] & 255];
+                }
+            }
+#pragma unroll
+            for (int qb = 0; qb < RQ; ++qb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) kvq[qb][i] = exp2_256_join(t[qb][i], rr[qb][i], mi[qb][i]);
+        };
+
         auto compute_s = [&](const GatheredS& g) {
             double kv[RQ][4];
             double xn[4];  // padding columns: |x|^2 = +inf gives exponent -inf and value 0
 #pragma unroll
             for (int i = 0; i < 4; ++i) xn[i] = (g.jj[i] == INT32_MAX) ? __builtin_inf() : g.xn[i];
+            // both query blocks' products first, then their values together
+            // (eight independent chains per lane)
+            int4_t acc[RQ][kSlices];
 #pragma unroll
-            for (int qb = 0; qb < RQ; ++qb) {
-                int4_t acc[kSlices];
-                slice_products(acc, qb, g);
-                slice_values(acc, qb, g, xn, kv[qb]);
-            }
+            for (int qb = 0; qb < RQ; ++qb) slice_products(acc[qb], qb, g);
+            slice_values2(acc, g, xn, kv);
 #pragma unroll
             for (int qb = 0; qb < RQ; ++qb) {
                 if (smax[qb] >= g.first && smin[qb] <= g.last &&
