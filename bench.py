@@ -30,10 +30,14 @@ if ROOT not in sys.path:
 
 PRECISION_NOTE = {
     "plain_fp64": "plain: fp32 points, every pair on the fp64 matrix cores, fp64 exp",
-    "bf16_split": "bf16 hi/lo split filter on bf16 matrix cores (fp32 accumulate), kept pairs exact in fp64",
+    "bf16_split": ("bf16 hi/lo split filter on bf16 matrix cores (fp32 accumulate); kept pairs recomputed to fp64 "
+                   "accuracy (32 < d <= 64, root pass: cross terms from int8 base-256 slices on int8 matrix cores, "
+                   "exact int32 slice products joined in fp64; otherwise fp64 matrix cores), fp64 exp and bins"),
 }
 METRIC = "kernel evals/s + sampled edges/s, BF16-split vs FP32 plain; p50/p99 latency"
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+INT8_MFMA_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak
+SLICE_PAIRS = 28  # int8 slice products per cross term of the sliced recompute (seven slices, a + b <= 8)
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
@@ -537,13 +541,24 @@ def run_leg(ctx, w, Xd, prec, steps, warmup, args):
         flops = 2.0 * d * evaluated
         achieved = flops / (kde["ms_per_launch"] * 1e-3) / 1e12
         kname = "kde_bins" if prec == "plain_fp64" else "kde_exact_kept"
+        sliced = prec != "plain_fp64" and 32 < d <= 64
         label = ("binned KDE over all point pairs (FP64 matrix cores)" if prec == "plain_fp64"
+                 else "recompute of the kept pairs to FP64 accuracy: cross terms from int8 slice products "
+                      "(int8 matrix cores), FP64 exponent and bins" if sliced
                  else "exact FP64 recompute of the kept pairs (FP64 matrix cores)")
         roofline = {"bound": "mfma", "kernel": label, "kernel_symbol": kname + "_kernel",
                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic_from_profile(kname, w.name),
                     "ms_per_launch": kde["ms_per_launch"], "algorithmic_flops_per_launch": flops,
-                    "flops_basis": "2d FP64 flops (cross term) per evaluated pair"}
+                    "flops_basis": "2d flops (cross term, delivered to FP64 accuracy) per evaluated pair, "
+                                   "against the FP64 matrix peak"}
+        if sliced:
+            # what the int8 matrix cores execute: SLICE_PAIRS products of 64-long
+            # slices per pair (coordinates padded to 64)
+            issued = 2.0 * 64 * SLICE_PAIRS * evaluated / (kde["ms_per_launch"] * 1e-3) / 1e12
+            roofline["executed_as"] = {"unit": "TOP/s", "int8_issued": issued, "peak": INT8_MFMA_PEAK_TOPS,
+                                       "frac": issued / INT8_MFMA_PEAK_TOPS,
+                                       "basis": f"{SLICE_PAIRS} int8 slice products x 2 x 64 ops per evaluated pair"}
     if mask:
         # algorithmic: the 2d flops of one cross term per scanned pair; issued:
         # the split contraction over K = 3d (hi.hi + hi.lo + lo.hi)

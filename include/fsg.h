@@ -168,6 +168,18 @@ fsg_status fsg_ctx_set_kde_error(fsg_ctx* ctx, double eps);
  * back to index order. */
 fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled);
 
+/* Integer slices in the precision mode's exact recompute (32 < d <= 64,
+ * Gaussian kernel, root pass): each point's coordinates, scaled by a power
+ * of two per point, are cut into seven signed base-256 digits, the cross term
+ * of a kept pair is the sum of the 28 most significant digit-slice products
+ * (exact in int32 on the int8 matrix cores) joined in FP64, with error at
+ * most 4.1 d 2^-53 |q| |x| -- the order of a d-term FP64 accumulation -- and
+ * the exponent and bin sums follow in FP64 as before.  enabled != 0 (default
+ * < 0): used where it applies; 0: the cross terms are recomputed on the FP64
+ * matrix cores.  The kept set does not depend on it; masses differ within
+ * the two recomputes' error bounds. */
+fsg_status fsg_ctx_set_exact_slices(fsg_ctx* ctx, int32_t enabled);
+
 /* Cap the number of tree levels one binned KDE pass resolves (0 restores the
  * automatic choice, which is bounded by the workspace budget).  Results do not
  * depend on it; smaller caps trade more passes for less workspace. */

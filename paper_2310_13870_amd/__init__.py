@@ -42,6 +42,7 @@ _lib_fns = dict(
     fsg_ctx_workspace_bytes=_sig("fsg_ctx_workspace_bytes", _u64, _vp),
     fsg_ctx_set_levels_per_pass=_sig("fsg_ctx_set_levels_per_pass", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_pruning=_sig("fsg_ctx_set_pruning", ctypes.c_int, _vp, _i32),
+    fsg_ctx_set_exact_slices=_sig("fsg_ctx_set_exact_slices", ctypes.c_int, _vp, _i32),
     fsg_ctx_set_kernel=_sig("fsg_ctx_set_kernel", ctypes.c_int, _vp, ctypes.c_int),
     fsg_ctx_set_kde_error=_sig("fsg_ctx_set_kde_error", ctypes.c_int, _vp, _dbl),
     fsg_ctx_set_profiling=_sig("fsg_ctx_set_profiling", ctypes.c_int, _vp, ctypes.c_int),
@@ -155,6 +156,11 @@ class Context:
         """Precision mode: skip (query tile, cell) pairs that cannot keep a column.
         True: on; False: off; None (default): on for sets of at least 2^18 points."""
         self.check(_lib.fsg_ctx_set_pruning(self._h, -1 if enabled is None else (1 if enabled else 0)))
+
+    def set_exact_slices(self, enabled):
+        """Precision mode, 32 < d <= 64, Gaussian kernel: recompute kept pairs' cross terms from
+        int8 slice products (True or None, the default) or on the FP64 matrix cores (False)."""
+        self.check(_lib.fsg_ctx_set_exact_slices(self._h, -1 if enabled is None else (1 if enabled else 0)))
 
     def set_profiling(self, enabled: bool):
         self.check(_lib.fsg_ctx_set_profiling(self._h, 1 if enabled else 0))

@@ -536,8 +536,8 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     if (!bnd) return st;
     const int64_t n = X->n;
     const int32_t nbins = 1 << D;
-    const int32_t tile = (X->prec == FSG_BF16_SPLIT) ? exact_tile(X->D4, X->Xs && ctx->kernel == FSG_GAUSSIAN)
-                                                     : kde_tile(X->D4);
+    const bool sliced = ctx->slices != 0 && X->Xs && ctx->kernel == FSG_GAUSSIAN;
+    const int32_t tile = (X->prec == FSG_BF16_SPLIT) ? exact_tile(X->D4, sliced) : kde_tile(X->D4);
     const int64_t tiles = (n + tile - 1) / tile;
     const int32_t bpc = root_bins_per_item(ctx, tiles, nbins);
     const int64_t n_items = tiles * ((nbins + bpc - 1) / bpc);
@@ -550,6 +550,10 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
     FSG_HIP(ctx, launch_uniform_segs(segs, 1, 0, nbins, ctx->stream));
     FSG_HIP(ctx, launch_regular_items(n, nbins, bpc, tile, items, n_items_dev, ctx->stream));
     KdeArgs a = kde_args(X, X, gamma, ctx->kernel);
+    if (!sliced) {
+        a.Qs = a.Xs = nullptr;
+        a.qe = a.xe = nullptr;
+    }
     a.q_idx = nullptr;
     a.self_mode = SELF_POINT;
     a.bounds = bnd;
@@ -1001,6 +1005,7 @@ struct BatchTables {
     std::vector<fsg_job*> jobs;
     int waves_per_cu = 8;
     int cols = 2048;
+    int32_t slices = -1;        // the context's integer-slice setting the tables were built with
     void* dev = nullptr;        // one block: KdeArgs[G] SegDesc[G] BatchItemDesc[G+1] MaskArgs[G] int64[G+1] counter
     void* host = nullptr;       // pinned staging of the same layout
     size_t bytes = 0;
@@ -1157,7 +1162,7 @@ static fsg_status job_root_args(fsg_ctx* ctx, fsg_job* j, KdeArgs* a, MaskArgs* 
 static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int waves_per_cu, int cols,
                                BatchTables** out) {
     for (BatchTables* T : ctx->batch_cache)
-        if (T->jobs == g && T->waves_per_cu == waves_per_cu && T->cols == cols) {
+        if (T->jobs == g && T->waves_per_cu == waves_per_cu && T->cols == cols && T->slices == ctx->slices) {
             *out = T;
             return FSG_OK;
         }
@@ -1174,6 +1179,7 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
     T->jobs = g;
     T->waves_per_cu = waves_per_cu;
     T->cols = cols;
+    T->slices = ctx->slices;
     T->bytes = bytes;
     auto fail = [&](fsg_status s) {
         free_tables(ctx, T);
@@ -1195,7 +1201,7 @@ static fsg_status batch_tables(fsg_ctx* ctx, const std::vector<fsg_job*>& g, int
     fsg_status st;
     // one exact-recompute variant per launch: the integer slices only where
     // every set of the launch has them
-    bool all_sliced = bf16;
+    bool all_sliced = bf16 && ctx->slices != 0;
     for (int32_t i = 0; i < G; ++i) all_sliced = all_sliced && g[i]->S.X->Xs != nullptr;
     for (int32_t i = 0; i < G; ++i) {
         fsg_job* j = g[i];
@@ -1665,6 +1671,12 @@ fsg_status fsg_ctx_set_kernel(fsg_ctx* ctx, fsg_kernel kind) {
 fsg_status fsg_ctx_set_pruning(fsg_ctx* ctx, int32_t enabled) {
     if (!ctx) return FSG_E_INVALID;
     ctx->pruning = enabled < 0 ? -1 : (enabled > 0 ? 1 : 0);
+    return FSG_OK;
+}
+
+fsg_status fsg_ctx_set_exact_slices(fsg_ctx* ctx, int32_t enabled) {
+    if (!ctx) return FSG_E_INVALID;
+    ctx->slices = enabled < 0 ? -1 : (enabled > 0 ? 1 : 0);
     return FSG_OK;
 }
 

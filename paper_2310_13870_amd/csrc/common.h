@@ -237,6 +237,7 @@ struct fsg_ctx {
     int max_levels_per_pass = 0;
     // precision mode: skip (query tile, cell) pairs that cannot keep a column
     int32_t pruning = -1;        // tile pruning: -1 by size (n >= kPruneMinPoints), 0 off, 1 on
+    int32_t slices = -1;         // integer-slice recompute: 0 off, otherwise where it applies
     // kernel of later calls (fsg_ctx_set_kernel)
     fsg_kernel kernel = FSG_GAUSSIAN;
     // precision mode: the dropped share of every degree allowed (0: e^-25)

@@ -365,6 +365,56 @@ def test_bf16_split_later_passes_use_root_masks(ctx, n, d, L, cap, comps):
     p32.close()
 
 
+def _mixed_scale_rows(n, d, seed):
+    """Clustered points whose rows stress the integer slices: rows scaled by
+    powers of two and by non-powers, exact zeros, coordinates far below their
+    row's largest (not representable in the seven digits), negative extremes
+    and one all-zero row."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-6.0, 6.0, size=(5, d))
+    X = centres[rng.integers(0, 5, size=n)] + rng.normal(0.0, 1.0, size=(n, d))
+    X[rng.random(n) < 0.1] *= 2.0 ** rng.integers(-3, 2)
+    X[rng.random(n) < 0.1] *= 1.37
+    zero = rng.random((n, d)) < 0.02
+    X[zero] = 0.0
+    tiny = rng.random((n, d)) < 0.01
+    X[tiny] = rng.choice([-1.0, 1.0], size=tiny.sum()) * 10.0 ** rng.uniform(-30, -8, size=tiny.sum())
+    X[rng.integers(0, n, size=8), rng.integers(0, d, size=8)] = -15.99
+    X[n // 2] = 0.0
+    return X.astype(np.float32)
+
+
+@pytest.mark.parametrize("n,d,L", [(3000, 64, 6), (2500, 40, 5), (700, 33, 4)])
+def test_exact_slices_against_fp64_recompute(ctx, n, d, L):
+    """The integer-slice recompute of the root pass (32 < d <= 64) against
+    the FP64 matrix-core recompute on the same kept set and the oracle: its
+    cross terms are within 4.1 d 2^-53 |q| |x| of exact, so degrees agree
+    with the FP64 recompute to 1e-12 relative and with the oracle to 1e-9,
+    and the sampled neighbours are the same (the masses move far less than
+    the decision band)."""
+    X = _mixed_scale_rows(n, d, 4242 + n + d)
+    gamma = 1.0 / (2.0 * 0.5 * d)
+    seed = 99 + n
+    pbf = fsg.Points(ctx, to_dev(X), "bf16_split")
+    try:
+        ctx.set_exact_slices(True)
+        nbr1, deg1, _ = fsg.sample_edges(ctx, pbf, gamma, L, seed)
+        ctx.set_exact_slices(False)
+        nbr0, deg0, _ = fsg.sample_edges(ctx, pbf, gamma, L, seed)
+    finally:
+        ctx.set_exact_slices(None)
+    nbr1, deg1, nbr0, deg0 = (t.cpu().numpy() for t in (nbr1, deg1, nbr0, deg0))
+    say(f"slices n={n} d={d}: degree rel diff to FP64 recompute "
+        f"{np.max(np.abs(deg1 - deg0) / np.maximum(deg0, 1e-300)):.2e}")
+    np.testing.assert_allclose(deg1, deg0, rtol=1e-12, atol=0.0)
+    rdeg = oracle.degrees(X, gamma)
+    rel = np.abs(deg1 - rdeg) / np.maximum(rdeg, 1e-300)
+    rel[rdeg == 0] = np.abs(deg1[rdeg == 0])
+    assert rel.max() < 1e-9, f"degree max rel err {rel.max()}"
+    assert np.array_equal(nbr1, nbr0)
+    pbf.close()
+
+
 @pytest.mark.parametrize("n,d,L,spread,comps", [(1, 3, 2, 10.0, 1), (100, 8, 5, 10.0, 3), (255, 2, 6, 20.0, 4),
                                                 (4097, 16, 8, 12.0, 10), (20_001, 64, 6, 10.0, 30),
                                                 (6000, 100, 6, 10.0, 12), (9000, 128, 5, 10.0, 16),
