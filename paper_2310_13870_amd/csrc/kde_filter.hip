@@ -116,6 +116,12 @@ kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
         const WorkItem w = a.items[it];
         const SegDesc sg = a.segs[w.seg];
         const KdeArgs& J = MULTI ? a.jobs[sg.job] : a;
+        // the set's arrays read per block, loaded once per item (a multi-set
+        // table lives in global memory, which the bin stores could alias)
+        const double* const Xp = J.Xp;
+        const double* const xnorm = J.xnorm;
+        const int8_t* const Xs = J.Xs;
+        const int32_t* const xe = J.xe;
         const int32_t* bnd = J.bounds + sg.bound_off;
         const double s256 = 256.0 * J.s;  // exponent terms scaled by 256 for exp2_256_tab
         const double two_s = 2.0 * s256;
@@ -237,14 +243,14 @@ kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
         // consecutive entries 4g .. 4g+3
         auto prepare = [&](Gathered<D4>& g, int32_t pos, int32_t cnt) {
             const int32_t gl = queue[pos + ((pr < cnt) ? pr : 0)];
-            load_row_part<D4>(g.xf, J.Xp, gl, grp);
+            load_row_part<D4>(g.xf, Xp, gl, grp);
             g.first = uniform(queue[pos]);
             g.last = uniform(queue[pos + cnt - 1]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int32_t idx = 4 * grp + i;
                 g.jj[i] = (idx < cnt) ? queue[pos + idx] : INT32_MAX;
-                const double v = J.xnorm[(idx < cnt) ? g.jj[i] : g.first];
+                const double v = xnorm[(idx < cnt) ? g.jj[i] : g.first];
                 g.xn[i] = (idx < cnt) ? v : __builtin_inf();
             }
         };
@@ -253,7 +259,7 @@ kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
         // result element i of lane group g is row 4g + i)
         auto prepare_s = [&](GatheredS& g, int32_t pos, int32_t cnt) {
             const int32_t gl = queue[pos + ((r < cnt) ? r : 0)];
-            const int8_t* xrow = J.Xs + (int64_t)gl * kSliceRow + 16 * grp;
+            const int8_t* xrow = Xs + (int64_t)gl * kSliceRow + 16 * grp;
 #pragma unroll
             for (int sb = 0; sb < kSlices; ++sb) g.xs[sb] = *(const int4_t*)(xrow + 64 * sb);
             g.first = uniform(queue[pos]);
@@ -266,8 +272,8 @@ kde_exact_kept_kernel(KdeArgs a, unsigned long long* __restrict__ next_item) {
                 const int32_t idx = 4 * grp + i;
                 const int32_t col = queue[pos + min(idx, cnt - 1)];
                 g.jj[i] = (idx < cnt) ? col : INT32_MAX;
-                g.xn[i] = J.xnorm[col];
-                g.xe[i] = J.xe[col];
+                g.xn[i] = xnorm[col];
+                g.xe[i] = xe[col];
             }
         };
 
