@@ -364,6 +364,19 @@ static double margin_for(int64_t n, double kde_error) {
     return std::log((double)n) + kMarginExtra;
 }
 
+// The index-order split fragments and -|x|^2/2 of a point set, which only a
+// scan over every tile reads (the pruned scan reads the pivot-order copies):
+// written on the first such scan.  Under stream capture the launch is
+// recorded each time, so that an eager call never reads them unwritten.
+static fsg_status ensure_index_split(fsg_ctx* ctx, fsg_points* X) {
+    if (X->xb_ready) return FSG_OK;
+    FSG_HIP(ctx, launch_prep_split(X->X, X->norm, X->n, X->d, X->KB, X->n_pad, X->Xb, X->xa, ctx->stream));
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    FSG_HIP(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+    if (cs == hipStreamCaptureStatusNone) X->xb_ready = true;
+    return FSG_OK;
+}
+
 static MaskArgs root_mask_args(const fsg_points* X, double gamma, int num_cus, int32_t kind = FSG_GAUSSIAN,
                                double kde_error = 0.0) {
     MaskArgs m;
@@ -585,6 +598,7 @@ static fsg_status root_bins(fsg_ctx* ctx, fsg_points* X, double gamma, int D, do
         if (prune && X->Xbp) {
             if ((st = pruned_keep_mask(ctx, X, m)) != FSG_OK) return st;
         } else {
+            if ((st = ensure_index_split(ctx, X)) != FSG_OK) return st;
             // pairs examined: every data column once per 64-query tile
             FSG_HIP(ctx, launch_add_i64(ctx->filter_counts + 1, tiles * n, ctx->stream));
             StageTimer t(ctx, "kde_mask");
@@ -711,7 +725,6 @@ static fsg_status prep_precision_mode(fsg_ctx* ctx, fsg_points* p) {
     if ((st = ws(ctx, "pivot_dist16", (size_t)P * P, &d16)) != FSG_OK) return st;
     if ((st = ws(ctx, "pivot_rank", (size_t)P, &rank)) != FSG_OK) return st;
     StageTimer t(ctx, "prep");
-    FSG_HIP(ctx, launch_prep_split(p->X, p->norm, n, p->d, KB, p->n_pad, p->Xb, p->xa, ctx->stream));
     if (sliced) FSG_HIP(ctx, launch_prep_slices(p->X, n, p->d, p->n_pad, p->Xs, p->xe, ctx->stream));
     FSG_HIP(ctx, launch_pivots(p->X, n, p->d, P, p->dmin, label, p->order, ctx->stream));
     // cells labelled along a nearest-neighbour chain of the pivots, so that
@@ -1152,6 +1165,7 @@ static fsg_status job_root_args(fsg_ctx* ctx, fsg_job* j, KdeArgs* a, MaskArgs* 
         a->out_rows = X->order;
         a->mask = j->mask;
         a->n_blocks = X->n_pad / 16;
+        if ((st = ensure_index_split(ctx, X)) != FSG_OK) return st;
         *m = root_mask_args(X, j->S.gamma, ctx->num_cus);
         m->ntheta = j->ntheta;
         m->mask = j->mask;

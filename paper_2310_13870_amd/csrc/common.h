@@ -291,7 +291,8 @@ struct fsg_points {
     double* norm = nullptr;    // FP64 ||x||^2 [n_pad]
     // precision mode (FSG_BF16_SPLIT)
     int32_t KB = 0;            // 32-wide K steps of the split operands
-    void* Xb = nullptr;        // data-side split fragments
+    void* Xb = nullptr;        // data-side split fragments (with xa: written on first use by a full scan)
+    bool xb_ready = false;
     void* Qb = nullptr;        // query-side split fragments in pivot order (rows: n rounded up to kThetaPad)
     float* xa = nullptr;       // -|x|^2/2 in FP32 [n_pad]
     double* dmin = nullptr;    // upper bound on each point's smallest squared distance
