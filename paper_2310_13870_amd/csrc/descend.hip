@@ -143,6 +143,107 @@ __global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a0,
     }
 }
 
+// Root pass of one set with 2^D <= 1024 bins: one wave per point (four per
+// block, each with its own LDS), so that four times as many points are in
+// flight and no block-wide barrier is needed.  Lane t sums its 2^D / 64
+// consecutive bins in registers; every internal node is the sum of its two
+// children, as in descend_root_kernel, so the trees (and the walks) are the
+// same bit for bit.
+constexpr int kWaveRootMaxD = 10;
+
+__global__ __launch_bounds__(256) void descend_root_wave_kernel(DescArgs a, int32_t n_groups) {
+    extern __shared__ double smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int32_t nb = 1 << a.D;
+    const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
+    // per wave: tree[k], k in [1, nb), then the Philox blocks of its chunk
+    double* tree = smem + (size_t)wv * ((size_t)nb + (size_t)4 * chunk * n_groups);
+    uint64_t* words = (uint64_t*)(tree + nb);
+    const int32_t g0 = a.start_level >> 2;
+    const int32_t per = nb >= 64 ? nb / 64 : 1;  // bins per lane (<= 16)
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    for (int64_t e = (int64_t)blockIdx.x * 4 + wv; e < a.n_entries; e += n_waves) {
+        const double* M = a.M + e * nb;
+        int32_t top;  // the LDS levels built below start at nodes [top, 2 top)
+        if (nb >= 2) {
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = (k < per && lane * per + k < nb) ? M[lane * per + k] : 0.0;
+            int32_t cnt = per, lvl_nodes = nb;
+            while (cnt > 1) {
+                cnt >>= 1;
+                lvl_nodes >>= 1;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < cnt) v[k] = v[2 * k] + v[2 * k + 1];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k < cnt) tree[lvl_nodes + lane * cnt + k] = v[k];
+            }
+            if (per == 1) {
+                // one bin per lane: the first internal level from pairs of lanes
+                const double o = __shfl_xor(v[0], 1);
+                if ((lane & 1) == 0 && lane < nb) tree[nb / 2 + lane / 2] = v[0] + o;
+                top = nb / 2;
+            } else {
+                top = lvl_nodes;  // 64
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t c = top >> 1; c >= 1; c >>= 1) {
+                if (lane < c) tree[c + lane] = tree[2 * (c + lane)] + tree[2 * (c + lane) + 1];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        const double root = (nb >= 2) ? tree[1] : M[0];
+        if (a.deg != nullptr && lane == 0) a.deg[e] = root;
+        for (int32_t c0 = 0; c0 < a.L; c0 += kDescChunk) {
+            const int32_t cn = min(kDescChunk, a.L - c0);
+            for (int32_t c = lane; c < cn * n_groups; c += 64) {
+                const int32_t k = c / n_groups, g = g0 + (c - k * n_groups);
+                const PhiloxWords w = philox4x64_10((uint64_t)e, (uint64_t)(c0 + k), (uint64_t)g, 0, a.seed, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) words[c * 4 + q] = w.w[q];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < cn) {
+                const int32_t l = c0 + lane;
+                const int64_t smp = e * a.L + l;
+                const uint64_t* wk = words + (int64_t)lane * n_groups * 4;
+                if (!(root > 0.0)) {
+                    a.node[smp] = -1;  // isolated point: no neighbour
+                } else {
+                    float mg = (a.margin != nullptr) ? a.margin[smp] : 0.0f;
+                    int32_t m = 0;
+                    for (int32_t t = 0; t < a.D; ++t) {
+                        const int32_t level = a.start_level + t;
+                        const double u = word_to_uniform(wk[((level >> 2) - g0) * 4 + (level & 3)]);
+                        const int32_t c = (1 << (t + 1)) + 2 * m;
+                        double mL, mR;
+                        if (t + 1 < a.D) {
+                            mL = tree[c];
+                            mR = tree[c + 1];
+                        } else {
+                            mL = M[2 * m];  // the children are bins
+                            mR = M[2 * m + 1];
+                        }
+                        const bool left = choose_left(u, mL, mR, a.margin != nullptr, &mg);
+                        m = 2 * m + (left ? 0 : 1);
+                    }
+                    a.node[smp] = m;
+                    if (a.margin != nullptr) a.margin[smp] = mg;
+                }
+            }
+            // the next point (or chunk) rewrites the tree and the words
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 // Later passes: one thread per entry (a single sample); the 2^D bin masses are
 // held in registers and each level's child masses are summed directly.
 template <int D>
@@ -200,6 +301,13 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
         if (a.D < 1 || a.D > 11) return hipErrorInvalidValue;  // the tree build assumes 2 <= 2^D <= 8 * 256
         int32_t n_groups = 0;
         const size_t lds = desc_root_lds(a, &n_groups);
+        if (a.D <= kWaveRootMaxD && 4 * lds <= 65536) {
+            // one wave per point (LDS: four trees and their Philox blocks)
+            int64_t blocks = (a.n_entries + 3) / 4;
+            if (blocks > (1 << 18)) blocks = 1 << 18;
+            descend_root_wave_kernel<<<(unsigned)blocks, 256, 4 * lds, st>>>(a, n_groups);
+            return hipGetLastError();
+        }
         int64_t blocks = a.n_entries;
         if (blocks > (1 << 20)) blocks = 1 << 20;
         descend_root_kernel<false><<<(unsigned)blocks, kDescThreads, lds, st>>>(a, n_groups);
