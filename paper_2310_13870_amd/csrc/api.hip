@@ -1526,9 +1526,11 @@ static fsg_status batch_root_descend(fsg_ctx* ctx, const std::vector<fsg_job*>& 
         int64_t* hoff = (int64_t*)(h + o_off);
         int64_t total = 0;
         size_t lds = 0;
+        int32_t max_D = 0;
         for (int32_t i = 0; i < G; ++i) {
             const fsg_job* j = g[i];
             DescArgs da = desc_args(j->S, 0);
+            max_D = std::max(max_D, da.D);
             da.M = j->M;
             da.n_entries = j->S.X->n;
             da.entry_sample = nullptr;
@@ -1552,6 +1554,7 @@ static fsg_status batch_root_descend(fsg_ctx* ctx, const std::vector<fsg_job*>& 
         T->a0.job_entry_off = (const int64_t*)((char*)T->dev + o_off);
         T->a0.n_jobs = G;
         T->a0.lds_bytes = lds;
+        T->a0.D = max_D;  // a multi-set launch reads each set's D from its table; this picks the kernel
         ctx->desc_cache.push_back(T);
     }
     StageTimer t(ctx, "descend");

@@ -464,7 +464,7 @@ hipError_t launch_split_pairs(const double* pairs, int64_t n, double* left, doub
 struct DescArgs {
     const double* M;           // masses [entries][2^D]
     int64_t n_entries;
-    int32_t D;                 // levels resolved by this pass
+    int32_t D;                 // levels resolved by this pass (multi-set launch: the largest)
     int32_t start_level;       // level of the nodes the entries sit at
     int32_t L;
     uint64_t seed;

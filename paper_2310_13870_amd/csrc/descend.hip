@@ -143,27 +143,44 @@ __global__ __launch_bounds__(kDescThreads) void descend_root_kernel(DescArgs a0,
     }
 }
 
-// Root pass of one set with 2^D <= 1024 bins: one wave per point (four per
-// block, each with its own LDS), so that four times as many points are in
-// flight and no block-wide barrier is needed.  Lane t sums its 2^D / 64
-// consecutive bins in registers; every internal node is the sum of its two
-// children, as in descend_root_kernel, so the trees (and the walks) are the
-// same bit for bit.
+// Root pass with 2^D <= 1024 bins: one wave per point (four per block, each
+// with its own LDS), so that four times as many points are in flight and no
+// block-wide barrier is needed.  Lane t sums its 2^D / 64 consecutive bins in
+// registers; every internal node is the sum of its two children, as in
+// descend_root_kernel, so the trees (and the walks) are the same bit for bit.
+// MULTI: entries of several sets (a0.jobs), each wave's LDS region sized by
+// a0.lds_bytes (the largest set's).
 constexpr int kWaveRootMaxD = 10;
 
-__global__ __launch_bounds__(256) void descend_root_wave_kernel(DescArgs a, int32_t n_groups) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void descend_root_wave_kernel(DescArgs a0, int32_t n_groups0) {
     extern __shared__ double smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int32_t nb = 1 << a.D;
-    const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
-    // per wave: tree[k], k in [1, nb), then the Philox blocks of its chunk
-    double* tree = smem + (size_t)wv * ((size_t)nb + (size_t)4 * chunk * n_groups);
-    uint64_t* words = (uint64_t*)(tree + nb);
-    const int32_t g0 = a.start_level >> 2;
-    const int32_t per = nb >= 64 ? nb / 64 : 1;  // bins per lane (<= 16)
     const int64_t n_waves = (int64_t)gridDim.x * 4;
-    for (int64_t e = (int64_t)blockIdx.x * 4 + wv; e < a.n_entries; e += n_waves) {
+    for (int64_t ge = (int64_t)blockIdx.x * 4 + wv; ge < a0.n_entries; ge += n_waves) {
+        int64_t e = ge;
+        int32_t job = 0;
+        if (MULTI) {  // the point set owning entry ge (uniform binary search)
+            int32_t lo = 0, hi = a0.n_jobs;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (a0.job_entry_off[mid] <= ge) lo = mid; else hi = mid;
+            }
+            job = lo;
+            e = ge - a0.job_entry_off[job];
+        }
+        // a copy: the stores below could alias a job table in global memory
+        const DescArgs a = MULTI ? a0.jobs[job] : a0;
+        const int32_t n_groups = MULTI ? desc_groups(a) : n_groups0;
+        const int32_t nb = 1 << a.D;
+        const int32_t chunk = a.L < kDescChunk ? a.L : kDescChunk;
+        // per wave: tree[k], k in [1, nb), then the Philox blocks of its chunk
+        const size_t region = MULTI ? a0.lds_bytes / sizeof(double) : (size_t)nb + (size_t)4 * chunk * n_groups;
+        double* tree = smem + (size_t)wv * region;
+        uint64_t* words = (uint64_t*)(tree + nb);
+        const int32_t g0 = a.start_level >> 2;
+        const int32_t per = nb >= 64 ? nb / 64 : 1;  // bins per lane (<= 16)
         const double* M = a.M + e * nb;
         int32_t top;  // the LDS levels built below start at nodes [top, 2 top)
         if (nb >= 2) {
@@ -292,6 +309,13 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
     if (a.n_entries < 1) return hipSuccess;
     if (a.jobs != nullptr) {  // root passes of several sets (tables built by the caller)
         if (a.lds_bytes == 0) return hipErrorInvalidValue;
+        // a.D: the largest D of the sets
+        if (a.D <= kWaveRootMaxD && 4 * a.lds_bytes <= 65536) {
+            int64_t blocks = (a.n_entries + 3) / 4;
+            if (blocks > (1 << 18)) blocks = 1 << 18;
+            descend_root_wave_kernel<true><<<(unsigned)blocks, 256, 4 * a.lds_bytes, st>>>(a, 0);
+            return hipGetLastError();
+        }
         int64_t blocks = a.n_entries;
         if (blocks > (1 << 20)) blocks = 1 << 20;
         descend_root_kernel<true><<<(unsigned)blocks, kDescThreads, a.lds_bytes, st>>>(a, 0);
@@ -305,7 +329,7 @@ hipError_t launch_descend_bins(const DescArgs& a, hipStream_t st) {
             // one wave per point (LDS: four trees and their Philox blocks)
             int64_t blocks = (a.n_entries + 3) / 4;
             if (blocks > (1 << 18)) blocks = 1 << 18;
-            descend_root_wave_kernel<<<(unsigned)blocks, 256, 4 * lds, st>>>(a, n_groups);
+            descend_root_wave_kernel<false><<<(unsigned)blocks, 256, 4 * lds, st>>>(a, n_groups);
             return hipGetLastError();
         }
         int64_t blocks = a.n_entries;
