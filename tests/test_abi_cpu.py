@@ -54,6 +54,11 @@ def test_status_strings_and_host_validation():
     lib.fsg_last_error.restype = ctypes.c_char_p
     lib.fsg_last_error.argtypes = [ctypes.c_void_p]
     assert lib.fsg_last_error(None) == b""
+    # the context settings, too
+    for name in ("fsg_ctx_set_pruning", "fsg_ctx_set_exact_slices", "fsg_ctx_set_levels_per_pass"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        assert f(None, 1) == -1, name
 
 
 def test_batch_and_graph_calls_validate_on_the_host():
