@@ -443,22 +443,33 @@ __global__ __launch_bounds__(kConvThreads) void mask_to_index_kernel(PruneArgs a
         for (int32_t c = (int32_t)(threadIdx.x >> 6); c < a.P; c += kConvThreads / 64) {
             if (!((w[c >> 5] >> (c & 31)) & 1u)) continue;
             const int64_t b1 = ((int64_t)a.cell_start[c + 1] + 15) >> 4;
-            for (int64_t b = (a.cell_start[c] >> 4) + (threadIdx.x & 63); b < b1; b += 64) {
-                const uint32_t m = mrow[b];
-                if (m == 0u) continue;
-                // positions 16 b .. 16 b + 15 exist: the order array is padded
-                // to whole blocks (the padding's bits are never set)
-                const int4* ob = (const int4*)(a.order + 16 * b);
-                int4 o[4];
+            // four blocks per lane at a time: their masks and point indices
+            // are all loaded before the first is used
+            for (int64_t bq = (a.cell_start[c] >> 4) + (threadIdx.x & 63); bq < b1; bq += 256) {
+                uint32_t m[4];
+                int4 o[4][4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) o[q] = ob[q];
-                const int32_t pts[16] = {o[0].x, o[0].y, o[0].z, o[0].w, o[1].x, o[1].y, o[1].z, o[1].w,
-                                         o[2].x, o[2].y, o[2].z, o[2].w, o[3].x, o[3].y, o[3].z, o[3].w};
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t b = bq + 64 * u;
+                    m[u] = (b < b1) ? (uint32_t)mrow[b] : 0u;
+                    // positions 16 b .. 16 b + 15 exist: the order array is
+                    // padded to whole blocks (the padding's bits are never set)
+                    const int4* ob = (const int4*)(a.order + 16 * (b < b1 ? b : bq));
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if ((m >> k) & 1u) {
-                        const int64_t j = (int64_t)pts[k] - w0;
-                        if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
+                    for (int q = 0; q < 4; ++q) o[u][q] = ob[q];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (m[u] == 0u) continue;
+                    const int32_t pts[16] = {o[u][0].x, o[u][0].y, o[u][0].z, o[u][0].w, o[u][1].x, o[u][1].y,
+                                             o[u][1].z, o[u][1].w, o[u][2].x, o[u][2].y, o[u][2].z, o[u][2].w,
+                                             o[u][3].x, o[u][3].y, o[u][3].z, o[u][3].w};
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        if ((m[u] >> k) & 1u) {
+                            const int64_t j = (int64_t)pts[k] - w0;
+                            if (j >= 0 && j < kConvWindow) atomicOr(&bits[j >> 5], 1u << (j & 31));
+                        }
                     }
                 }
             }
