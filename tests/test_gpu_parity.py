@@ -384,7 +384,8 @@ def _mixed_scale_rows(n, d, seed):
     return X.astype(np.float32)
 
 
-@pytest.mark.parametrize("n,d,L", [(3000, 64, 6), (2500, 40, 5), (700, 33, 4)])
+@pytest.mark.parametrize("n,d,L", [(3000, 64, 6), (2500, 40, 5), (700, 33, 4), (1, 64, 3), (2, 48, 2),
+                                   (17, 64, 4), (65, 36, 5)])
 def test_exact_slices_against_fp64_recompute(ctx, n, d, L):
     """The integer-slice recompute of the root pass (32 < d <= 64) against
     the FP64 matrix-core recompute on the same kept set and the oracle: its
